@@ -1,0 +1,376 @@
+"""Pins of the FP64 oracle against things other than itself.
+
+Each test checks one oracle routine against an independent statement:
+published known answers, a library routine, a closed form written in a
+different parametrisation, brute force on the model's log density, or the
+distribution the draw must follow.  None of these run on a GPU.
+"""
+import os
+import shutil
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+import scipy.linalg
+import scipy.sparse
+import scipy.stats
+
+import synth
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+# ---------------------------------------------------------------------------
+# Philox4x32-10
+# ---------------------------------------------------------------------------
+def test_philox_known_answers(orc):
+    # Known-answer vectors published with Random123 (Salmon et al., SC'11),
+    # philox4x32 with 10 rounds: (counter, key) -> output.
+    kat = [
+        ([0, 0, 0, 0], [0, 0], [0x6627E8D5, 0xE169C58D, 0xBC57AC4C, 0x9B00DBD8]),
+        ([0xFFFFFFFF] * 4, [0xFFFFFFFF] * 2, [0x408F276D, 0x41C83B0E, 0xA20BC7C6, 0x6D5451FD]),
+        ([0x243F6A88, 0x85A308D3, 0x13198A2E, 0x03707344], [0xA4093822, 0x299F31D0],
+         [0xD16CFE09, 0x94FDCCEB, 0x5001E420, 0x24126EA1]),
+    ]
+    for ctr, key, want in kat:
+        assert orc.philox(ctr, key).tolist() == want
+
+
+def test_philox_matches_rocrand_header(orc):
+    """Bit-exact against rocRAND's Philox4x32-10 source header on 2000 random
+    (counter, key) pairs, host-compiled."""
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available")
+    rng = np.random.default_rng(5)
+    words = rng.integers(0, 1 << 32, size=(2000, 6), dtype=np.uint64).astype(np.uint32)
+    words[:10, :4] = 0  # a few structured counters too
+    words[10:20, 2] = (np.arange(10) << 24).astype(np.uint32)
+    with tempfile.TemporaryDirectory() as d:
+        exe = os.path.join(d, "dump")
+        subprocess.check_call([hipcc, "-x", "hip", "--cuda-host-only", "-O1",
+                               os.path.join(HERE, "rocrand_philox_dump.cpp"), "-o", exe])
+        inp = "\n".join(" ".join("%x" % v for v in row) for row in words) + "\n"
+        out = subprocess.run([exe], input=inp, capture_output=True, text=True, check=True).stdout
+    ref = np.array([[int(x, 16) for x in line.split()] for line in out.strip().splitlines()],
+                   dtype=np.uint64)
+    mine = np.array([orc.philox(w[:4], w[4:]) for w in words], dtype=np.uint64)
+    assert np.array_equal(ref, mine)
+
+
+# ---------------------------------------------------------------------------
+# Normals and chi-square
+# ---------------------------------------------------------------------------
+def test_box_muller_normals_distribution(orc):
+    z = np.concatenate([orc.normals(11, i, 3, 1, 0, 400) for i in range(2500)])  # 10^6
+    assert abs(z.mean()) < 5 / np.sqrt(len(z))
+    assert abs(z.var() - 1.0) < 5 * np.sqrt(2.0 / len(z))
+    assert scipy.stats.kstest(z, "norm").pvalue > 1e-3
+    # the pairs (cos, sin) of one block are uncorrelated
+    assert abs(np.corrcoef(z[0::2], z[1::2])[0, 1]) < 5 / np.sqrt(len(z) / 2)
+
+
+def test_normals_counter_layout(orc):
+    # normal k comes from block k // 4, lane k % 4: a prefix of a longer
+    # request equals the shorter request, and blocks are independent of n.
+    a = orc.normals(3, 7, 9, 2, 0, 10)
+    b = orc.normals(3, 7, 9, 2, 0, 16)
+    assert np.array_equal(a, b[:10])
+    # stream, t, row and c3 each change the block
+    base = orc.normals(3, 7, 9, 2, 0, 4)
+    for args in [(3, 8, 9, 2, 0), (3, 7, 10, 2, 0), (3, 7, 9, 1, 0), (3, 7, 9, 2, 1), (4, 7, 9, 2, 0)]:
+        assert not np.allclose(orc.normals(*args, 4), base)
+
+
+@pytest.mark.parametrize("dof", [2.0, 3.0, 12.5, 51.0, 1003.0])
+def test_chi2_distribution(orc, dof):
+    n = 20000
+    draws = np.array([orc.chi2(21, 3, 5, i, dof)[0] for i in range(n)])
+    assert scipy.stats.kstest(draws, scipy.stats.chi2(dof).cdf).pvalue > 1e-3
+    assert abs(draws.mean() - dof) < 5 * np.sqrt(2 * dof / n)
+
+
+# ---------------------------------------------------------------------------
+# Cholesky
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("K", [1, 2, 5, 32, 100])
+def test_cholesky_against_scipy(orc, K):
+    rng = np.random.default_rng(K)
+    A = rng.standard_normal((K, K + 3))
+    P = A @ A.T + 0.1 * np.eye(K)
+    L = orc.cholesky(P)
+    assert np.allclose(np.triu(L, 1), 0)
+    assert np.all(np.diag(L) > 0)
+    ref = scipy.linalg.cholesky(P, lower=True)
+    assert np.allclose(L, ref, rtol=1e-10, atol=1e-12 * np.abs(ref).max())
+    eps = np.finfo(float).eps
+    assert np.linalg.norm(L @ L.T - P) <= 10 * K * eps * np.linalg.norm(P)
+
+
+def test_cholesky_rejects_indefinite(orc):
+    with pytest.raises(np.linalg.LinAlgError):
+        orc.cholesky(np.array([[1.0, 2.0], [2.0, 1.0]]))
+
+
+# ---------------------------------------------------------------------------
+# Row conditional
+# ---------------------------------------------------------------------------
+def _row_problem(K, d, seed, nY=50):
+    rng = np.random.default_rng(seed)
+    Y = rng.standard_normal((nY, K)) * 0.7
+    nbr = np.sort(rng.choice(nY, d, replace=False)).astype(np.int32)
+    rc = rng.standard_normal(d) * 1.3
+    mu = rng.standard_normal(K) * 0.3
+    A = rng.standard_normal((K, K))
+    Lam = A @ A.T / K + 0.5 * np.eye(K)
+    return Y, nbr, rc, mu, Lam
+
+
+def test_row_draw_k1_by_hand(orc):
+    # K = 1: precision lambda + alpha sum y^2, mean (lambda mu + alpha sum r y) / precision
+    Y, nbr, rc, mu, Lam = _row_problem(1, 7, 3)
+    alpha = 2.0
+    y = Y[nbr, 0]
+    prec = Lam[0, 0] + alpha * np.sum(y * y)
+    mean = (Lam[0, 0] * mu[0] + alpha * np.sum(rc * y)) / prec
+    for z in [0.0, 1.0, -2.5]:
+        x = orc.row_draw_z(alpha, nbr, rc, Y, mu, Lam, np.array([z]))
+        assert x[0] == pytest.approx(mean + z / np.sqrt(prec), rel=1e-13, abs=1e-14)
+
+
+def _log_density(x, alpha, Y, nbr, rc, mu, Lam):
+    # log p(x | ratings, Y, mu, Lam) up to a constant, straight from the model:
+    # Gaussian likelihood r' ~ N(x.y, 1/alpha) times the prior N(mu, Lam^-1).
+    res = rc - Y[nbr] @ x
+    dx = x - mu
+    return -0.5 * alpha * np.sum(res * res) - 0.5 * dx @ Lam @ dx
+
+
+def _affine_map(orc, alpha, Y, nbr, rc, mu, Lam):
+    """Mean x(0) and the matrix G with x(z) = x(0) + G z, read off the oracle."""
+    K = Y.shape[1]
+    m = orc.row_draw_z(alpha, nbr, rc, Y, mu, Lam, np.zeros(K))
+    G = np.stack([orc.row_draw_z(alpha, nbr, rc, Y, mu, Lam, np.eye(K)[k]) - m for k in range(K)],
+                 axis=1)
+    return m, G
+
+
+@pytest.mark.parametrize("K,d", [(1, 3), (2, 5), (3, 1), (4, 9), (4, 0)])
+def test_row_draw_brute_force_log_density(orc, K, d):
+    """Gradient of the log density vanishes at the oracle's mean, and the
+    oracle's sampling covariance G G^T inverts the negative Hessian, both by
+    central finite differences of the model's log density."""
+    alpha = 2.0
+    Y, nbr, rc, mu, Lam = _row_problem(K, d, 100 + K + d)
+    m, G = _affine_map(orc, alpha, Y, nbr, rc, mu, Lam)
+    f = lambda x: _log_density(x, alpha, Y, nbr, rc, mu, Lam)
+    h = 1e-4
+    E = np.eye(K)
+    grad = np.array([(f(m + h * E[k]) - f(m - h * E[k])) / (2 * h) for k in range(K)])
+    assert np.abs(grad).max() < 1e-6
+    H = np.zeros((K, K))
+    hh = 1e-2
+    for a in range(K):
+        for b in range(K):
+            H[a, b] = (f(m + hh * E[a] + hh * E[b]) - f(m + hh * E[a] - hh * E[b])
+                       - f(m - hh * E[a] + hh * E[b]) + f(m - hh * E[a] - hh * E[b])) / (4 * hh * hh)
+    cov = G @ G.T
+    assert np.allclose(cov @ (-H), np.eye(K), atol=1e-6)
+
+
+def test_row_draw_quadrature_k2(orc):
+    """K = 2: mean and covariance by grid quadrature of exp(log density)."""
+    alpha = 2.0
+    Y, nbr, rc, mu, Lam = _row_problem(2, 6, 77)
+    m, G = _affine_map(orc, alpha, Y, nbr, rc, mu, Lam)
+    sd = np.sqrt(np.diag(G @ G.T))
+    g0 = np.linspace(m[0] - 9 * sd[0], m[0] + 9 * sd[0], 801)
+    g1 = np.linspace(m[1] - 9 * sd[1], m[1] + 9 * sd[1], 801)
+    X0, X1 = np.meshgrid(g0, g1, indexing="ij")
+    pts = np.stack([X0.ravel(), X1.ravel()], 1)
+    res = rc[None, :] - pts @ Y[nbr].T
+    dx = pts - mu
+    lp = -0.5 * alpha * np.sum(res * res, 1) - 0.5 * np.einsum("ij,jk,ik->i", dx, Lam, dx)
+    w = np.exp(lp - lp.max())
+    w /= w.sum()
+    qm = w @ pts
+    qc = (pts - qm).T @ ((pts - qm) * w[:, None])
+    assert np.allclose(qm, m, atol=1e-6 * sd.max())
+    assert np.allclose(qc, G @ G.T, rtol=1e-4, atol=1e-8)
+
+
+def test_row_draw_closed_form_scipy(orc):
+    """Mean equals cho_solve(P, b) and G G^T equals P^-1 at K = 32."""
+    K, alpha = 32, 2.0
+    Y, nbr, rc, mu, Lam = _row_problem(K, 40, 9, nY=200)
+    m, G = _affine_map(orc, alpha, Y, nbr, rc, mu, Lam)
+    # Normal equations of the posterior in the form (X^T X alpha + Lam) x = ...
+    Xd = Y[nbr]
+    P = alpha * Xd.T @ Xd + Lam
+    b = alpha * Xd.T @ rc + Lam @ mu
+    c = scipy.linalg.cho_factor(P, lower=True)
+    assert np.allclose(m, scipy.linalg.cho_solve(c, b), rtol=1e-10, atol=1e-12)
+    assert np.allclose(G @ G.T, scipy.linalg.cho_solve(c, np.eye(K)), rtol=1e-9, atol=1e-12)
+    # G is upper triangular (x = L^-T (y + z)), fixing the sampling convention
+    assert np.allclose(np.tril(G, -1), 0, atol=1e-14)
+
+
+def test_row_draws_moments(orc):
+    """10^5 draws of one row over t: empirical mean and covariance."""
+    K, alpha = 3, 2.0
+    Y, nbr, rc, mu, Lam = _row_problem(K, 5, 31, nY=20)
+    m, G = _affine_map(orc, alpha, Y, nbr, rc, mu, Lam)
+    cov = G @ G.T
+    ptr = np.array([0, len(nbr)], np.int64)
+    n = 100000
+    draws = np.zeros((n, K))
+    X = np.zeros((1, K))
+    for t in range(n):
+        orc.update_rows(ptr, nbr, rc, Y, X, mu, Lam, alpha, 99, 1, t + 1)
+        draws[t] = X[0]
+    em = draws.mean(0)
+    assert np.all(np.abs(em - m) < 5 * np.sqrt(np.diag(cov) / n))
+    ec = np.cov(draws.T)
+    se = np.sqrt((cov ** 2 + np.outer(np.diag(cov), np.diag(cov))) / n)
+    assert np.all(np.abs(ec - cov) < 5 * se)
+
+
+def test_update_rows_thread_invariance(orc):
+    r = synth.random_small(4, 300, 200, 6000, 8)
+    ch = orc.Chain(r.M, r.N, 8, r.csr_ptr, r.csr_col, r.csr_val, r.test_row, r.test_col,
+                   r.test_val, seed=5)
+    outs = []
+    for th in (1, 7):
+        orc.set_threads(th)
+        X = ch.U.copy()
+        orc.update_rows(ch.csr_ptr, ch.csr_col, ch.csr_rc, ch.V, X, np.zeros(8), np.eye(8) * 2,
+                        2.0, 5, 1, 3)
+        outs.append(X)
+    orc.set_threads(os.cpu_count() or 1)
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_transpose_against_scipy(orc):
+    r = synth.random_small(9, 120, 90, 2500, 4, empty_rows=5)
+    A = scipy.sparse.csr_matrix((r.csr_val, r.csr_col, r.csr_ptr), shape=(r.M, r.N)).tocsc()
+    A.sort_indices()
+    p, i, v = orc.transpose_csr(r.M, r.N, r.csr_ptr, r.csr_col, r.csr_val)
+    assert np.array_equal(p, A.indptr) and np.array_equal(i, A.indices)
+    assert np.array_equal(v, A.data)
+
+
+# ---------------------------------------------------------------------------
+# Normal-Wishart hyperparameter draw
+# ---------------------------------------------------------------------------
+def test_hyper_k1_normal_gamma(orc):
+    """K = 1 reduces to the Normal-Gamma model: with prior precision
+    lambda ~ Gamma(shape nu0/2, rate 1/(2 W0)) and mu | lambda ~ N(mu0,
+    1/(beta0 lambda)), the posterior is Gamma(shape nu0/2 + n/2,
+    rate 1/(2 W0) + SS/2 + beta0 n (xbar - mu0)^2 / (2 (beta0 + n))) and
+    mu | lambda ~ N((beta0 mu0 + n xbar)/(beta0 + n), 1/((beta0 + n) lambda))."""
+    rng = np.random.default_rng(8)
+    X = rng.standard_normal((40, 1)) * 0.8 + 0.3
+    mu0, beta0, nu0, W0 = np.array([0.2]), 2.0, 1.0, np.array([[1.5]])
+    n, xb = len(X), X.mean()
+    shape = nu0 / 2 + n / 2
+    rate = 1 / (2 * W0[0, 0]) + 0.5 * np.sum((X - xb) ** 2) + beta0 * n * (xb - mu0[0]) ** 2 / (2 * (beta0 + n))
+    mun = (beta0 * mu0[0] + n * xb) / (beta0 + n)
+    lam, zs = [], []
+    for t in range(4000):
+        mu, L = orc.hyper_draw(X, mu0, beta0, nu0, W0, 17, 3, t + 1)
+        lam.append(L[0, 0])
+        zs.append((mu[0] - mun) * np.sqrt((beta0 + n) * L[0, 0]))
+    lam = np.array(lam)
+    assert scipy.stats.kstest(lam, scipy.stats.gamma(shape, scale=1 / rate).cdf).pvalue > 1e-3
+    assert scipy.stats.kstest(np.array(zs), "norm").pvalue > 1e-3
+
+
+def _nw_posterior_uncentred(X, mu0, beta0, nu0, W0):
+    """Normal-Wishart posterior written with raw second moments:
+    T*^-1 = W0^-1 + sum x x^T + beta0 mu0 mu0^T - beta* mu* mu*^T."""
+    n = X.shape[0]
+    beta_s = beta0 + n
+    mu_s = (beta0 * mu0 + X.sum(0)) / beta_s
+    Tinv = np.linalg.inv(W0) + X.T @ X + beta0 * np.outer(mu0, mu0) - beta_s * np.outer(mu_s, mu_s)
+    return mu_s, beta_s, nu0 + n, np.linalg.inv(Tinv)
+
+
+def test_hyper_wishart_moments_k3(orc):
+    rng = np.random.default_rng(12)
+    K = 3
+    X = rng.standard_normal((25, K)) @ np.array([[1.0, 0.3, 0.0], [0.0, 0.7, 0.2], [0.0, 0.0, 1.2]])
+    mu0, beta0, nu0 = np.array([0.1, -0.2, 0.0]), 2.0, float(K)
+    A = rng.standard_normal((K, K))
+    W0 = A @ A.T / K + np.eye(K)
+    mu_s, beta_s, nu_s, Ws = _nw_posterior_uncentred(X, mu0, beta0, nu0, W0)
+    n = 20000
+    lams = np.zeros((n, K, K))
+    mus = np.zeros((n, K))
+    for t in range(n):
+        mus[t], lams[t] = orc.hyper_draw(X, mu0, beta0, nu0, W0, 23, 4, t + 1)
+    mean = nu_s * Ws
+    var = nu_s * (Ws ** 2 + np.outer(np.diag(Ws), np.diag(Ws)))
+    assert np.all(np.abs(lams.mean(0) - mean) < 5 * np.sqrt(var / n))
+    assert np.all(np.abs(lams.var(0) - var) < 0.1 * var)
+    ref_tr = np.trace(scipy.stats.wishart(df=nu_s, scale=Ws).rvs(20000, random_state=1), axis1=1, axis2=2)
+    tr = np.trace(lams, axis1=1, axis2=2)
+    assert scipy.stats.ks_2samp(tr, ref_tr).pvalue > 1e-3
+    # mu | Lambda ~ N(mu*, (beta* Lambda)^-1): whitened residuals are N(0, I)
+    w = np.stack([np.linalg.cholesky(beta_s * lams[t]).T @ (mus[t] - mu_s) for t in range(n)])
+    assert np.all(np.abs(w.mean(0)) < 5 / np.sqrt(n))
+    assert np.allclose(np.cov(w.T), np.eye(K), atol=5 * np.sqrt(2.0 / n))
+
+
+# ---------------------------------------------------------------------------
+# Whole chain
+# ---------------------------------------------------------------------------
+def test_chain_recovers_planted_uniform(orc):
+    """Well-conditioned planted problem (1000 x 500, 40% density, rank 10,
+    noise sd 0.5): held-out RMSE of the posterior mean reaches noise level."""
+    r = synth.planted_uniform()
+    ch = orc.Chain(r.M, r.N, 10, r.csr_ptr, r.csr_col, r.csr_val, r.test_row, r.test_col,
+                   r.test_val, seed=101, burn_in=5)
+    res = ch.run(1, 20)
+    assert res[-1][0] <= 1.10 * 0.5
+
+
+def test_chain_planted_zipf_beats_mean_baseline(orc):
+    """The Zipf-skewed planted problem (1000 x 500, 20,000 ratings, K = 10):
+    the chain must beat predicting the training mean."""
+    r = synth.planted()
+    ch = orc.Chain(r.M, r.N, 10, r.csr_ptr, r.csr_col, r.csr_val, r.test_row, r.test_col,
+                   r.test_val, seed=101)
+    res = ch.run(1, 20)
+    base = np.sqrt(np.mean((r.test_val - r.csr_val.astype(np.float64).mean()) ** 2))
+    assert res[-1][0] < 0.9 * base
+    assert np.isfinite(ch.U).all() and np.isfinite(ch.V).all()
+
+
+def test_init_factor_scale(orc):
+    X = orc.init_factor(5, 5, 4000, 16)
+    assert abs(X.var() - 16 ** -0.5) < 0.02 * 16 ** -0.5
+    # row i of the init equals the row-noise layout with t = 0 and stream INIT_U
+    assert np.allclose(X[123], orc.normals(5, 123, 0, 5, 0, 16) * 16 ** -0.25)
+
+
+# ---------------------------------------------------------------------------
+# Fold-in
+# ---------------------------------------------------------------------------
+def test_foldin_mean_variance_by_direct_formula(orc):
+    rng = np.random.default_rng(3)
+    S, N, K = 4, 30, 5
+    Vs = rng.standard_normal((S, N, K)) * 0.5
+    mus = rng.standard_normal((S, K)) * 0.1
+    Lams = np.stack([np.eye(K) * (1.5 + s) for s in range(S)])
+    movie = np.array([1, 4, 9, 20], np.int32)
+    rc = rng.standard_normal(4)
+    U, mean, var = orc.foldin(2.0, movie, rc, Vs, mus, Lams, 42, (5 << 32) | 77, 3.0)
+    P = np.einsum("sk,snk->sn", U, Vs) + 3.0
+    assert np.allclose(mean, P.mean(0))
+    assert np.allclose(var, 0.5 + P.var(0))
+    # each u_s is the row draw with the fold-in noise counter
+    for s in range(S):
+        z = orc.normals(42, 77, s, orc.FOLDIN, 5, K)
+        x = orc.row_draw_z(2.0, movie, rc, Vs[s], mus[s], Lams[s], z)
+        assert np.allclose(U[s], x, rtol=1e-14, atol=1e-15)
