@@ -1,0 +1,180 @@
+/*
+ * bpmf.h -- C ABI of the MI355X (gfx950) BPMF Gibbs-sweep library.
+ *
+ * The method is the Gibbs sampler of Bayesian Probabilistic Matrix
+ * Factorization as laid out in Vander Aa, Chakroun & Haber, "Distributed
+ * Bayesian Probabilistic Matrix Factorization" (2017):
+ *   - Sec. I: a sparse rating matrix R (M x N, users x movies) is approximated
+ *     by U V^T with U: M x K and V: N x K, K << M, N.
+ *   - Sec. II, Algorithm 1: each sampling iteration draws the movie
+ *     hyperparameters from V, updates every movie from its ratings and the
+ *     users who rated it (plus sampled noise), draws the user hyperparameters
+ *     from U, updates every user likewise, then predicts every test point and
+ *     computes the RMSE.
+ *   - Sec. II: the per-item update is a few K x K matrix/vector operations and
+ *     one K x K factorisation.
+ * The model the paper cites (BPMF): r_ij ~ N(u_i . v_j, 1/alpha); rows of U
+ * and V ~ N(mu, Lambda^-1) per side; (mu, Lambda) ~ Normal-Wishart(mu0,
+ * beta0, W0, nu0).  Row draw: P = Lambda + alpha sum_j y_j y_j^T,
+ * b = Lambda mu + alpha sum_j r'_ij y_j, P = L L^T, x = L^-T (L^-1 b + z).
+ *
+ * Conventions for every call:
+ *   - All pointers are HOST pointers unless stated otherwise; the library
+ *     copies what it needs before returning (inputs are borrowed only for the
+ *     duration of the call).  Output buffers are allocated by the caller with
+ *     the sizes stated.
+ *   - Matrices are row-major.  Factors are rows x K.  Ratings are CSR with
+ *     int64 row offsets, int32 column ids strictly increasing within a row
+ *     and float32 values.
+ *   - A context owns all device memory (hipMalloc) and one HIP stream; it is
+ *     bound to the device that was current at bpmf_create.
+ *   - Gibbs calls on one context must not run concurrently.
+ *   - Every call returns BPMF_OK (0) or a negative status; on failure the
+ *     context is unchanged (except after BPMF_E_DEVICE, which is sticky:
+ *     only bpmf_destroy is then valid) and bpmf_last_error() describes it.
+ *   - Randomness: every normal and chi-square draw is a function of
+ *     (seed, counter) through Philox4x32-10 (Salmon et al., SC'11) with key
+ *     (lo32(seed), hi32(seed)); row noise uses counter
+ *     (row, t, stream<<24 | block, 0), so a draw depends only on
+ *     (seed, t, side, row), never on launch order or thread count.
+ */
+#ifndef BPMF_H
+#define BPMF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bpmf_ctx bpmf_ctx;
+
+enum {
+    BPMF_OK = 0,
+    BPMF_PENDING = 1,      /* fold-in result not ready yet */
+    BPMF_E_INVAL = -1,     /* bad argument, or K out of range */
+    BPMF_E_RANGE = -2,     /* an index outside [0, M) or [0, N) */
+    BPMF_E_FORMAT = -3,    /* CSR not monotone, columns unsorted/duplicated, CSC not the transpose, non-finite value */
+    BPMF_E_NOMEM = -4,     /* device allocation failed */
+    BPMF_E_DEVICE = -5,    /* HIP error (sticky) */
+    BPMF_E_BUSY = -6,      /* fold-in queue full; retry later */
+    BPMF_E_TOOBIG = -7,    /* fold-in request larger than the memory pool */
+    BPMF_E_NOSAMPLES = -8, /* fold-in before any bpmf_store_sample */
+    BPMF_E_NOTFOUND = -9   /* unknown fold-in request id */
+};
+
+/* Sides of the factorisation: U holds the M users, V the N movies. */
+enum { BPMF_SIDE_U = 0, BPMF_SIDE_V = 1 };
+
+/* Arithmetic of the row update.
+ *   BPMF_FP64      : factors, Gram, Cholesky and solves in FP64.
+ *   BPMF_FP32      : factors FP32; Gram on FP32 matrix cores (MFMA) with FP32
+ *                    accumulation; FP32 Cholesky and solves.
+ *   BPMF_BF16_GRAM : as FP32, but the gathered factor rows are rounded to
+ *                    BF16 and the Gram runs on BF16 MFMA with FP32
+ *                    accumulation (rhs, Cholesky and solves stay FP32).
+ * The hyperparameter draw is FP64 in every mode. */
+enum { BPMF_FP64 = 0, BPMF_FP32 = 1, BPMF_BF16_GRAM = 2 };
+
+typedef struct bpmf_params {
+    int32_t K;            /* latent dimension, 1..128 */
+    int32_t prec;         /* BPMF_FP64 / BPMF_FP32 / BPMF_BF16_GRAM */
+    double alpha;         /* rating precision (default 2) */
+    double beta0;         /* Normal-Wishart beta0 (default 2) */
+    double nu0;           /* Wishart degrees of freedom (default K) */
+    const double *mu0;    /* K values; NULL means 0 */
+    const double *W0;     /* K x K SPD Wishart scale; NULL means identity */
+    uint64_t seed;        /* Philox key */
+    int32_t center;       /* 1: subtract the mean training rating (default 1) */
+    int32_t burn_in;      /* sweeps t <= burn_in are left out of the running prediction mean */
+    int32_t foldin_S;     /* fold-in sample ring size (default 16) */
+    int32_t split_threshold; /* rows with more ratings are split across wavefronts (0: library default) */
+    uint64_t foldin_pool_bytes; /* fold-in device memory budget (0: 256 MiB) */
+} bpmf_params;
+
+/* Fill *p with the defaults above for latent dimension K. */
+void bpmf_default_params(bpmf_params *p, int32_t K);
+
+/* Create a context from training ratings (CSR over the M users) and test
+ * triples.  csc_* may be NULL: the transpose (columns ascending, rows
+ * ascending within a column) is then built by the library; when given it
+ * must be exactly that transpose (BPMF_E_FORMAT otherwise).  The factors
+ * are initialised as X_ik = K^-1/4 z with z the Philox normals of counter
+ * (row, 0, stream<<24 | block, 0), stream 5 for U and 6 for V.
+ * Validation: ptr[0] = 0, ptr non-decreasing, ptr[M] = nnz; columns in
+ * [0, N) and strictly increasing per row; values finite; test ids in range. */
+int bpmf_create(int64_t M, int64_t N, const int64_t *csr_ptr, const int32_t *csr_col,
+                const float *csr_val, const int64_t *csc_ptr, const int32_t *csc_row,
+                const float *csc_val, int64_t nnz, const int32_t *test_row,
+                const int32_t *test_col, const float *test_val, int64_t n_test,
+                const bpmf_params *p, bpmf_ctx **out);
+
+/* Algorithm 1, "sample hyper-parameters movies based on V" (side V) or
+ * "users based on U" (side U), for sweep t: Normal-Wishart posterior draw in
+ * FP64 on the device (Bartlett decomposition; chi-square counter
+ * (k, t, stream<<24 | 0, attempt), lower normals (block, t, stream<<24 | 1, 0),
+ * mu normals (block, t, stream<<24 | 2, 0), stream 3 for U, 4 for V). */
+int bpmf_sample_hyper(bpmf_ctx *c, int32_t side, uint32_t t);
+
+/* Algorithm 1, the item loop of one side for sweep t: every row of the side
+ * is redrawn from its conditional given the other factor and the side's
+ * current hyperparameters (row noise stream 1 for U, 2 for V). */
+int bpmf_update_side(bpmf_ctx *c, int32_t side, uint32_t t);
+
+/* Algorithm 1 for sweeps t0 .. t0+n-1 (each: hyper V, update V, hyper U,
+ * update U, predict), captured once as a HIP graph and replayed; the sweep
+ * counter lives in device memory.  rmse_avg / rmse_last receive n values
+ * each (either may be NULL): RMSE of the running mean prediction (sweeps
+ * t > burn_in) and of the current sample. */
+int bpmf_run_sweeps(bpmf_ctx *c, uint32_t t0, uint32_t n, double *rmse_avg, double *rmse_last);
+
+/* Algorithm 1, "predict rating and compute RMSE".  n == 0: predict the
+ * registered test set with the current factors, fold the prediction into the
+ * running mean as sweep t (if t > burn_in), and return the two RMSEs.
+ * n > 0: predict the n given (row, col) pairs into out[n] (float,
+ * u_row . v_col + mean rating) without touching the running mean; the RMSE
+ * pointers are then ignored. */
+int bpmf_predict(bpmf_ctx *c, uint32_t t, int64_t n, const int32_t *row, const int32_t *col,
+                 float *out, double *rmse_avg, double *rmse_last);
+
+/* Factor access: host buffer of rows x K values, float in FP32/BF16 modes and
+ * double in FP64 mode (bpmf_get_factor_f64 / bpmf_set_factor_f64 convert). */
+int bpmf_get_factor(bpmf_ctx *c, int32_t side, void *host);
+int bpmf_set_factor(bpmf_ctx *c, int32_t side, const void *host);
+int bpmf_get_factor_f64(bpmf_ctx *c, int32_t side, double *host);
+int bpmf_set_factor_f64(bpmf_ctx *c, int32_t side, const double *host);
+
+/* Hyperparameters of a side: mu (K) and Lambda (K x K), FP64. */
+int bpmf_get_hyper(bpmf_ctx *c, int32_t side, double *mu, double *Lambda);
+int bpmf_set_hyper(bpmf_ctx *c, int32_t side, const double *mu, const double *Lambda);
+
+/* The CSC the library uses (N+1 offsets, nnz row ids, nnz centred values as
+ * stored: float, or double in FP64 mode, r - mean).  For verification. */
+int bpmf_get_csc(bpmf_ctx *c, int64_t *ptr, int32_t *row, void *rc);
+
+/* The degree plan of a side: perm[rows] = row ids in processing order
+ * (degree descending, ties by row id), n_split = number of rows split
+ * across wavefronts (they come first in perm).  Either pointer may be NULL. */
+int bpmf_get_plan(bpmf_ctx *c, int32_t side, int32_t *perm, int64_t *n_split);
+
+/* Mean training rating subtracted from the ratings (0 when center = 0). */
+double bpmf_mean_rating(const bpmf_ctx *c);
+
+/* Block until all work queued on the context's stream has finished. */
+int bpmf_synchronize(bpmf_ctx *c);
+
+/* Device time (ms, HIP events on the context stream) of the most recent
+ * bpmf_update_side / bpmf_sample_hyper / bpmf_run_sweeps call. */
+int bpmf_last_time_ms(bpmf_ctx *c, double *ms);
+
+/* Message of the last failed call on c (or of the last failed create when c
+ * is NULL). */
+const char *bpmf_last_error(const bpmf_ctx *c);
+
+void bpmf_destroy(bpmf_ctx *c);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BPMF_H */

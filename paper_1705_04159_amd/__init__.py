@@ -1,0 +1,255 @@
+"""Python binding of libbpmf.so: the MI355X (gfx950) BPMF Gibbs sampler.
+
+Argument marshalling only: every step of the sampler (hyperparameter draw,
+row updates, prediction) runs in the library's HIP kernels.  The binding
+refuses to work without the built library -- there is no CPU fallback.
+
+Names follow the paper (Vander Aa, Chakroun, Haber 2017): R is M x N
+(users x movies), U is M x K, V is N x K; Algorithm 1 alternates a hyper
+draw and an update of every movie, then of every user, then predicts the
+test points.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbpmf.so")
+
+SIDE_U, SIDE_V = 0, 1
+FP64, FP32, BF16_GRAM = 0, 1, 2
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16_GRAM, "bf16_gram": BF16_GRAM}
+
+OK, PENDING = 0, 1
+E_INVAL, E_RANGE, E_FORMAT, E_NOMEM, E_DEVICE = -1, -2, -3, -4, -5
+E_BUSY, E_TOOBIG, E_NOSAMPLES, E_NOTFOUND = -6, -7, -8, -9
+
+# Every symbol the C ABI exports (include/bpmf.h).
+EXPORTS = [
+    "bpmf_default_params", "bpmf_create", "bpmf_sample_hyper", "bpmf_update_side",
+    "bpmf_run_sweeps", "bpmf_predict", "bpmf_get_factor", "bpmf_set_factor",
+    "bpmf_get_factor_f64", "bpmf_set_factor_f64", "bpmf_get_hyper", "bpmf_set_hyper",
+    "bpmf_get_csc", "bpmf_get_plan", "bpmf_mean_rating", "bpmf_synchronize",
+    "bpmf_last_time_ms", "bpmf_last_error", "bpmf_destroy",
+]
+
+
+class BPMFError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("bpmf status %d: %s" % (code, msg))
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("K", ctypes.c_int32),
+        ("prec", ctypes.c_int32),
+        ("alpha", ctypes.c_double),
+        ("beta0", ctypes.c_double),
+        ("nu0", ctypes.c_double),
+        ("mu0", ctypes.c_void_p),
+        ("W0", ctypes.c_void_p),
+        ("seed", ctypes.c_uint64),
+        ("center", ctypes.c_int32),
+        ("burn_in", ctypes.c_int32),
+        ("foldin_S", ctypes.c_int32),
+        ("split_threshold", ctypes.c_int32),
+        ("foldin_pool_bytes", ctypes.c_uint64),
+    ]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libbpmf.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libbpmf.so is not built (run `python -m paper_1705_04159_amd.build`); "
+                              "there is no fallback implementation")
+        L = ctypes.CDLL(LIB_PATH)
+        P, i32, i64, u32, dbl = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
+                                 ctypes.c_double)
+        L.bpmf_default_params.argtypes = [P, i32]
+        L.bpmf_default_params.restype = None
+        L.bpmf_create.argtypes = [i64, i64, P, P, P, P, P, P, i64, P, P, P, i64, P, P]
+        L.bpmf_sample_hyper.argtypes = [P, i32, u32]
+        L.bpmf_update_side.argtypes = [P, i32, u32]
+        L.bpmf_run_sweeps.argtypes = [P, u32, u32, P, P]
+        L.bpmf_predict.argtypes = [P, u32, i64, P, P, P, P, P]
+        for name in ("bpmf_get_factor", "bpmf_set_factor", "bpmf_get_factor_f64",
+                     "bpmf_set_factor_f64"):
+            getattr(L, name).argtypes = [P, i32, P]
+        L.bpmf_get_hyper.argtypes = [P, i32, P, P]
+        L.bpmf_set_hyper.argtypes = [P, i32, P, P]
+        L.bpmf_get_csc.argtypes = [P, P, P, P]
+        L.bpmf_get_plan.argtypes = [P, i32, P, P]
+        L.bpmf_mean_rating.argtypes = [P]
+        L.bpmf_mean_rating.restype = dbl
+        L.bpmf_synchronize.argtypes = [P]
+        L.bpmf_last_time_ms.argtypes = [P, P]
+        L.bpmf_last_error.argtypes = [P]
+        L.bpmf_last_error.restype = ctypes.c_char_p
+        L.bpmf_destroy.argtypes = [P]
+        L.bpmf_destroy.restype = None
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _c(a, dt):
+    return None if a is None else np.ascontiguousarray(a, dtype=dt)
+
+
+class Sampler:
+    """One BPMF Gibbs chain resident on the current GPU.
+
+    ratings: an object with M, N, csr_ptr, csr_col, csr_val, test_row,
+    test_col, test_val (e.g. ``synth.Ratings``)."""
+
+    def __init__(self, ratings, K, prec="fp32", alpha=2.0, beta0=2.0, nu0=None, mu0=None,
+                 W0=None, seed=0, center=True, burn_in=0, split_threshold=0, csc=None):
+        L = lib()
+        self.M, self.N, self.K = int(ratings.M), int(ratings.N), int(K)
+        self.prec = PRECISIONS[prec] if isinstance(prec, str) else int(prec)
+        p = Params()
+        L.bpmf_default_params(ctypes.byref(p), self.K)
+        p.prec = self.prec
+        p.alpha, p.beta0 = float(alpha), float(beta0)
+        p.nu0 = float(K if nu0 is None else nu0)
+        self._mu0 = _c(mu0, np.float64)
+        self._W0 = _c(W0, np.float64)
+        p.mu0 = None if self._mu0 is None else self._mu0.ctypes.data
+        p.W0 = None if self._W0 is None else self._W0.ctypes.data
+        p.seed = int(seed)
+        p.center = 1 if center else 0
+        p.burn_in = int(burn_in)
+        p.split_threshold = int(split_threshold)
+        ptr = _c(ratings.csr_ptr, np.int64)
+        col = _c(ratings.csr_col, np.int32)
+        val = _c(ratings.csr_val, np.float32)
+        tr = _c(ratings.test_row, np.int32)
+        tc = _c(ratings.test_col, np.int32)
+        tv = _c(ratings.test_val, np.float32)
+        cp = cr = cv = None
+        if csc is not None:
+            cp, cr, cv = _c(csc[0], np.int64), _c(csc[1], np.int32), _c(csc[2], np.float32)
+        self.nnz = int(ptr[-1])
+        self.n_test = len(tr)
+        ctx = ctypes.c_void_p()
+        rc = L.bpmf_create(self.M, self.N, _ptr(ptr), _ptr(col), _ptr(val), _ptr(cp), _ptr(cr),
+                           _ptr(cv), self.nnz, _ptr(tr), _ptr(tc), _ptr(tv), self.n_test,
+                           ctypes.byref(p), ctypes.byref(ctx))
+        if rc != OK:
+            raise BPMFError(rc, L.bpmf_last_error(None).decode())
+        self._ctx = ctx
+
+    # -- plumbing --------------------------------------------------------
+    def _check(self, rc):
+        if rc not in (OK, PENDING):
+            raise BPMFError(rc, lib().bpmf_last_error(self._ctx).decode())
+        return rc
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            lib().bpmf_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def rows(self, side):
+        return self.M if side == SIDE_U else self.N
+
+    @property
+    def dtype(self):
+        return np.float64 if self.prec == FP64 else np.float32
+
+    # -- Algorithm 1 -------------------------------------------------------
+    def sample_hyper(self, side, t):
+        self._check(lib().bpmf_sample_hyper(self._ctx, side, t))
+
+    def update_side(self, side, t):
+        self._check(lib().bpmf_update_side(self._ctx, side, t))
+
+    def run_sweeps(self, t0, n):
+        avg = np.zeros(n)
+        last = np.zeros(n)
+        self._check(lib().bpmf_run_sweeps(self._ctx, t0, n, _ptr(avg), _ptr(last)))
+        return avg, last
+
+    def predict_test(self, t):
+        a = ctypes.c_double()
+        b = ctypes.c_double()
+        self._check(lib().bpmf_predict(self._ctx, t, 0, None, None, None, ctypes.byref(a),
+                                       ctypes.byref(b)))
+        return a.value, b.value
+
+    def predict(self, row, col):
+        row = _c(row, np.int32)
+        col = _c(col, np.int32)
+        out = np.zeros(len(row), np.float32)
+        if len(row):
+            self._check(lib().bpmf_predict(self._ctx, 0, len(row), _ptr(row), _ptr(col), _ptr(out),
+                                           None, None))
+        return out
+
+    # -- state -------------------------------------------------------------
+    def get_factor(self, side):
+        X = np.zeros((self.rows(side), self.K), self.dtype)
+        self._check(lib().bpmf_get_factor(self._ctx, side, _ptr(X)))
+        return X
+
+    def set_factor(self, side, X):
+        X = _c(X, self.dtype)
+        assert X.shape == (self.rows(side), self.K)
+        self._check(lib().bpmf_set_factor(self._ctx, side, _ptr(X)))
+
+    def get_hyper(self, side):
+        mu = np.zeros(self.K)
+        Lam = np.zeros((self.K, self.K))
+        self._check(lib().bpmf_get_hyper(self._ctx, side, _ptr(mu), _ptr(Lam)))
+        return mu, Lam
+
+    def set_hyper(self, side, mu, Lam):
+        mu = _c(mu, np.float64)
+        Lam = _c(Lam, np.float64)
+        self._check(lib().bpmf_set_hyper(self._ctx, side, _ptr(mu), _ptr(Lam)))
+
+    def get_csc(self):
+        ptr = np.zeros(self.N + 1, np.int64)
+        row = np.zeros(self.nnz, np.int32)
+        rc = np.zeros(self.nnz, self.dtype)
+        self._check(lib().bpmf_get_csc(self._ctx, _ptr(ptr), _ptr(row), _ptr(rc)))
+        return ptr, row, rc
+
+    def get_plan(self, side):
+        perm = np.zeros(self.rows(side), np.int32)
+        ns = ctypes.c_int64()
+        self._check(lib().bpmf_get_plan(self._ctx, side, _ptr(perm), ctypes.byref(ns)))
+        return perm, ns.value
+
+    @property
+    def mean_rating(self):
+        return float(lib().bpmf_mean_rating(self._ctx))
+
+    def synchronize(self):
+        self._check(lib().bpmf_synchronize(self._ctx))
+
+    def last_time_ms(self):
+        ms = ctypes.c_double()
+        self._check(lib().bpmf_last_time_ms(self._ctx, ctypes.byref(ms)))
+        return ms.value

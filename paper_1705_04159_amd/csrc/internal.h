@@ -1,0 +1,120 @@
+// internal.h -- library-private types shared by the host runtime and the
+// kernel launchers.  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+namespace bpmf {
+
+// One unit of row-update work.  slot < 0: the whole row [beg, end) of the
+// neighbour list is processed and the row is redrawn.  slot >= 0: only the
+// segment [beg, end) is accumulated and its partial Gram and rhs are written
+// to partial slot `slot` (the row is finished later from its slots).
+struct RowItem {
+    int32_t row;
+    int32_t slot;
+    int64_t beg;
+    int64_t end;
+};
+
+// A split row: its partials are slots [first, first + count), summed in
+// slot order.
+struct FinishItem {
+    int32_t row;
+    int32_t first;
+    int32_t count;
+    int32_t pad;
+};
+
+struct Side {
+    int64_t rows = 0;
+    int64_t *ptr = nullptr;  // device [rows + 1] neighbour offsets
+    int32_t *nbr = nullptr;  // device [nnz] neighbour ids (other side)
+    void *rc = nullptr;      // device [nnz] centred ratings (float, or double in FP64 mode)
+    void *X = nullptr;       // device [rows * ld] factor
+    uint16_t *Xbf = nullptr; // device [rows * ld] BF16 copy of the factor (BF16 mode)
+    double *mu = nullptr;    // device [K]
+    double *Lam = nullptr;   // device [K * K]
+    void *Lam_w = nullptr;   // device [K * K] Lambda in working precision
+    void *Lmu_w = nullptr;   // device [K]     Lambda mu in working precision
+    RowItem *items = nullptr;
+    int64_t n_items = 0;
+    FinishItem *fin = nullptr;
+    int64_t n_fin = 0;
+    int64_t n_slots = 0;
+    std::vector<int32_t> perm;  // host copy of the processing order
+    int64_t n_split = 0;
+    uint32_t stream_row = 0, stream_hyp = 0, stream_init = 0;
+};
+
+}  // namespace bpmf
+
+struct bpmf_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int64_t M = 0, N = 0, nnz = 0, n_test = 0;
+    int K = 0, ld = 0, prec = 1;
+    double alpha = 2, beta0 = 2, nu0 = 0, rbar = 0;
+    uint64_t seed = 0;
+    int burn_in = 0;
+    int split_threshold = 0;
+    double *d_mu0 = nullptr, *d_W0inv = nullptr;
+    bpmf::Side side[2];
+    // test set
+    int32_t *test_row = nullptr, *test_col = nullptr;
+    float *test_val = nullptr;
+    double *pred_sum = nullptr;
+    double *rmse_part = nullptr;  // per-block partial sums of squared errors
+    int rmse_blocks = 0;
+    double *rmse_hist = nullptr;  // [2 * hist_cap] (avg, last) per sweep of a run
+    int64_t hist_cap = 0;
+    // hyper workspace
+    double *hyp_part = nullptr;   // [hyp_blocks * (K + K(K+1)/2)]
+    int hyp_blocks = 0;
+    double *hyp_stats = nullptr;  // [K + K(K+1)/2]
+    double *hyp_scratch = nullptr;// [4 * K * K + 8 * K]
+    int *hyp_status = nullptr;    // device flag: 1 = ok
+    // split partials
+    void *part = nullptr;
+    int64_t part_slots = 0;
+    // device counters: [0] = t, [1] = t0 of the running graph, [2] = running-mean count
+    uint32_t *ctr = nullptr;
+    // predict scratch for user-supplied pairs
+    int32_t *q_row = nullptr, *q_col = nullptr;
+    float *q_out = nullptr;
+    int64_t q_cap = 0;
+    // graph of one sweep
+    hipGraphExec_t graph = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    double last_ms = 0;
+    std::string err;
+    bool sticky = false;
+};
+
+namespace bpmf {
+
+// ---- launchers (defined in the .hip files; all enqueue on `s`) ----
+// Row update of one side: items, then split-row finishes.
+hipError_t launch_row_update(bpmf_ctx *c, int side_id, hipStream_t s);
+// Hyper draw of one side (statistics, reduction, single-workgroup draw).
+hipError_t launch_hyper(bpmf_ctx *c, int side_id, hipStream_t s);
+// Predict the registered test set as sweep ctr[0]; writes rmse_hist[slot].
+hipError_t launch_predict_test(bpmf_ctx *c, hipStream_t s);
+hipError_t launch_predict_pairs(bpmf_ctx *c, int64_t n, hipStream_t s);
+// Factor initialisation from Philox normals.
+hipError_t launch_init_factor(bpmf_ctx *c, int side_id, hipStream_t s);
+// Device counters.
+hipError_t launch_set_counter(uint32_t *ctr, int idx, uint32_t value, hipStream_t s);
+hipError_t launch_advance_t(uint32_t *ctr, hipStream_t s);
+hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t s);
+// Working-precision prior (Lambda, Lambda mu) from the FP64 hyperparameters.
+hipError_t launch_prior_to_working(bpmf_ctx *c, int side_id, hipStream_t s);
+// BF16 copy of a factor.
+hipError_t launch_to_bf16(bpmf_ctx *c, int side_id, hipStream_t s);
+// Largest dynamic LDS a generic row kernel needs for K (bytes).
+size_t row_generic_lds_bytes(int K, int prec);
+
+}  // namespace bpmf

@@ -1,0 +1,225 @@
+// misc.hip -- initialisation, prediction/RMSE and small bookkeeping kernels.
+//
+// Prediction follows Algorithm 1's last loop ("predict rating and compute
+// RMSE" over all test points): p = u_row . v_col + mean rating; the running
+// mean of p over sweeps t > burn_in is kept in FP64; the two RMSEs (running
+// mean, current sample) are reduced in a fixed order (per-block tree, then
+// one block over the block sums), so they are bit-reproducible.
+#include "internal.h"
+#include "rng_device.h"
+
+namespace bpmf {
+namespace {
+
+constexpr int kGroup = 16;  // lanes per test pair
+
+__device__ __forceinline__ double as_f64(float v) { return (double)v; }
+__device__ __forceinline__ double as_f64(double v) { return v; }
+
+// X_ik = scale * z(stream, t = 0, row i, k); padding columns are zeroed.
+template <typename T>
+__global__ void init_factor(int K, int ld, int64_t rows, double scale, uint64_t seed,
+                            uint32_t stream, T *__restrict__ X)
+{
+    const int nb = (K + 3) / 4;
+    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= rows * nb) return;
+    int64_t row = q / nb;
+    int blk = (int)(q - row * nb);
+    double z[4];
+    normals_block(seed, (uint32_t)row, 0u, stream, (uint32_t)blk, 0u, z);
+    for (int l = 0; l < 4; ++l) {
+        int k = 4 * blk + l;
+        if (k < ld) X[(size_t)row * ld + k] = k < K ? (T)(scale * z[l]) : T(0);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ double group_dot(int K, const T *u, const T *v, int g)
+{
+    T s = T(0);
+    for (int k = g; k < K; k += kGroup) s += u[k] * v[k];
+#pragma unroll
+    for (int off = kGroup / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, kGroup);
+    return as_f64(s);
+}
+
+// One group of 16 lanes per test pair (grid-stride over pairs with a fixed
+// grid).  Writes per-block sums of squared errors (running mean, sample).
+template <typename T>
+__global__ __launch_bounds__(256) void predict_test(
+    int K, int ld, int64_t n, const int32_t *__restrict__ row, const int32_t *__restrict__ col,
+    const float *__restrict__ val, const T *__restrict__ U, const T *__restrict__ V, double rbar,
+    double *__restrict__ pred_sum, const uint32_t *__restrict__ ctr, int burn_in,
+    double *__restrict__ part)
+{
+    __shared__ double red[2][256 / kGroup];
+    const uint32_t t = ctr[0];
+    const uint32_t cnt = ctr[2];
+    const bool use = (int64_t)t > (int64_t)burn_in;
+    const int g = threadIdx.x % kGroup;
+    const int grp = threadIdx.x / kGroup;
+    const int64_t groups_total = (int64_t)gridDim.x * (256 / kGroup);
+    double sa = 0.0, sl = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * (256 / kGroup) + grp; e < n; e += groups_total) {
+        double p = group_dot<T>(K, U + (size_t)row[e] * ld, V + (size_t)col[e] * ld, g) + rbar;
+        double avg;
+        if (use) {
+            double s = pred_sum[e] + p;
+            avg = s / (double)(cnt + 1);
+            if (g == 0) pred_sum[e] = s;
+        } else {
+            avg = cnt ? pred_sum[e] / (double)cnt : p;
+        }
+        double r = (double)val[e];
+        sa += (avg - r) * (avg - r);
+        sl += (p - r) * (p - r);
+    }
+    if (g == 0) {
+        red[0][grp] = sa;
+        red[1][grp] = sl;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        double s = 0.0;
+        for (int q = 0; q < 256 / kGroup; ++q) s += red[threadIdx.x][q];
+        part[2 * blockIdx.x + threadIdx.x] = s;
+    }
+}
+
+// One block: sum the per-block partials in order, store the RMSEs of this
+// sweep in hist[slot], slot = t - t0, and count the sweep into the running
+// mean if t > burn_in.
+__global__ void predict_finalize(int nblk, int64_t n, const double *__restrict__ part,
+                                 uint32_t *__restrict__ ctr, int burn_in, double *__restrict__ hist,
+                                 int64_t hist_cap)
+{
+    if (threadIdx.x != 0) return;
+    double sa = 0.0, sl = 0.0;
+    for (int b = 0; b < nblk; ++b) {
+        sa += part[2 * b];
+        sl += part[2 * b + 1];
+    }
+    const uint32_t t = ctr[0];
+    int64_t slot = (int64_t)t - (int64_t)ctr[1];
+    if (slot < 0 || slot >= hist_cap) slot = hist_cap - 1;
+    double dn = n > 0 ? (double)n : 1.0;
+    hist[2 * slot] = sqrt(sa / dn);
+    hist[2 * slot + 1] = sqrt(sl / dn);
+    if ((int64_t)t > (int64_t)burn_in) ctr[2] += 1;
+}
+
+template <typename T>
+__global__ void predict_pairs(int K, int ld, int64_t n, const int32_t *__restrict__ row,
+                              const int32_t *__restrict__ col, const T *__restrict__ U,
+                              const T *__restrict__ V, double rbar, float *__restrict__ out)
+{
+    const int g = threadIdx.x % kGroup;
+    int64_t e = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kGroup;
+    if (e >= n) return;
+    double p = group_dot<T>(K, U + (size_t)row[e] * ld, V + (size_t)col[e] * ld, g) + rbar;
+    if (g == 0) out[e] = (float)p;
+}
+
+__global__ void set_counter(uint32_t *ctr, int idx, uint32_t v) { ctr[idx] = v; }
+__global__ void advance_t(uint32_t *ctr) { ctr[0] += 1u; }
+
+__global__ void fill_f64(double *p, int64_t n, double v)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// Round-to-nearest-even FP32 -> BF16.
+__global__ void to_bf16(const float *__restrict__ x, uint16_t *__restrict__ y, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t u = __float_as_uint(x[i]);
+    uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7FFFu + lsb;
+    y[i] = (uint16_t)(u >> 16);
+}
+
+}  // namespace
+
+hipError_t launch_init_factor(bpmf_ctx *c, int side_id, hipStream_t s)
+{
+    Side &sd = c->side[side_id];
+    const int nb = (c->K + 3) / 4;
+    int64_t total = sd.rows * nb;
+    double scale = pow((double)c->K, -0.25);
+    unsigned grid = (unsigned)((total + 255) / 256);
+    if (grid == 0) return hipSuccess;
+    if (c->prec == 0)
+        hipLaunchKernelGGL((init_factor<double>), dim3(grid), dim3(256), 0, s, c->K, c->ld,
+                           sd.rows, scale, c->seed, sd.stream_init, (double *)sd.X);
+    else
+        hipLaunchKernelGGL((init_factor<float>), dim3(grid), dim3(256), 0, s, c->K, c->ld,
+                           sd.rows, scale, c->seed, sd.stream_init, (float *)sd.X);
+    return hipGetLastError();
+}
+
+hipError_t launch_predict_test(bpmf_ctx *c, hipStream_t s)
+{
+    int nblk = c->rmse_blocks;
+    if (c->prec == 0)
+        hipLaunchKernelGGL((predict_test<double>), dim3(nblk), dim3(256), 0, s, c->K, c->ld,
+                           c->n_test, c->test_row, c->test_col, c->test_val,
+                           (const double *)c->side[0].X, (const double *)c->side[1].X, c->rbar,
+                           c->pred_sum, c->ctr, c->burn_in, c->rmse_part);
+    else
+        hipLaunchKernelGGL((predict_test<float>), dim3(nblk), dim3(256), 0, s, c->K, c->ld,
+                           c->n_test, c->test_row, c->test_col, c->test_val,
+                           (const float *)c->side[0].X, (const float *)c->side[1].X, c->rbar,
+                           c->pred_sum, c->ctr, c->burn_in, c->rmse_part);
+    hipLaunchKernelGGL(predict_finalize, dim3(1), dim3(64), 0, s, nblk, c->n_test, c->rmse_part,
+                       c->ctr, c->burn_in, c->rmse_hist, c->hist_cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_predict_pairs(bpmf_ctx *c, int64_t n, hipStream_t s)
+{
+    unsigned grid = (unsigned)((n * kGroup + 255) / 256);
+    if (grid == 0) return hipSuccess;
+    if (c->prec == 0)
+        hipLaunchKernelGGL((predict_pairs<double>), dim3(grid), dim3(256), 0, s, c->K, c->ld, n,
+                           c->q_row, c->q_col, (const double *)c->side[0].X,
+                           (const double *)c->side[1].X, c->rbar, c->q_out);
+    else
+        hipLaunchKernelGGL((predict_pairs<float>), dim3(grid), dim3(256), 0, s, c->K, c->ld, n,
+                           c->q_row, c->q_col, (const float *)c->side[0].X,
+                           (const float *)c->side[1].X, c->rbar, c->q_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_counter(uint32_t *ctr, int idx, uint32_t value, hipStream_t s)
+{
+    hipLaunchKernelGGL(set_counter, dim3(1), dim3(1), 0, s, ctr, idx, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_advance_t(uint32_t *ctr, hipStream_t s)
+{
+    hipLaunchKernelGGL(advance_t, dim3(1), dim3(1), 0, s, ctr);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_bf16(bpmf_ctx *c, int side_id, hipStream_t s)
+{
+    Side &sd = c->side[side_id];
+    int64_t n = sd.rows * c->ld;
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(to_bf16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                       (const float *)sd.X, sd.Xbf, n);
+    return hipGetLastError();
+}
+
+}  // namespace bpmf

@@ -1,0 +1,711 @@
+// runtime.cpp -- host side of the C ABI declared in include/bpmf.h:
+// validation, the degree plan, device memory, the sweep graph and timing.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/bpmf.h"
+#include "internal.h"
+
+namespace bpmf {
+hipError_t launch_row_generic(bpmf_ctx *c, int side_id, hipStream_t s);
+hipError_t launch_row_fast(bpmf_ctx *c, int side_id, hipStream_t s, bool *handled);
+hipError_t prepare_kernels(bpmf_ctx *c);
+}  // namespace bpmf
+
+using namespace bpmf;
+
+namespace {
+
+thread_local std::string g_create_err;
+
+int fail(bpmf_ctx *c, int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    if (c) {
+        c->err = buf;
+        if (code == BPMF_E_DEVICE) c->sticky = true;
+    } else {
+        g_create_err = buf;
+    }
+    return code;
+}
+
+#define HIPCK(c, expr)                                                                     \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail((c), e_ == hipErrorOutOfMemory ? BPMF_E_NOMEM : BPMF_E_DEVICE,     \
+                        "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, __LINE__); \
+    } while (0)
+
+#define STICKY(c)                                                                     \
+    do {                                                                              \
+        if (!(c)) return BPMF_E_INVAL;                                                \
+        if ((c)->sticky) return fail((c), BPMF_E_DEVICE, "context unusable after a device error: %s", (c)->err.c_str()); \
+    } while (0)
+
+template <typename T>
+hipError_t dalloc(T **p, size_t count)
+{
+    *p = nullptr;
+    if (count == 0) count = 1;
+    return hipMalloc((void **)p, count * sizeof(T));
+}
+
+// Host Cholesky-based inverse of an SPD matrix (row-major), for W0^-1 at
+// setup.  Returns false if A is not SPD.
+bool spd_inverse_host(int K, const std::vector<double> &A, std::vector<double> &inv)
+{
+    std::vector<double> L(A);
+    for (int j = 0; j < K; ++j) {
+        double s = L[j * K + j];
+        for (int k = 0; k < j; ++k) s -= L[j * K + k] * L[j * K + k];
+        if (!(s > 0)) return false;
+        double d = sqrt(s);
+        L[j * K + j] = d;
+        for (int i = j + 1; i < K; ++i) {
+            double v = L[i * K + j];
+            for (int k = 0; k < j; ++k) v -= L[i * K + k] * L[j * K + k];
+            L[i * K + j] = v / d;
+        }
+    }
+    inv.assign((size_t)K * K, 0.0);
+    std::vector<double> col(K);
+    for (int j = 0; j < K; ++j) {
+        for (int i = 0; i < K; ++i) {
+            double v = (i == j) ? 1.0 : 0.0;
+            for (int k = 0; k < i; ++k) v -= L[i * K + k] * col[k];
+            col[i] = v / L[i * K + i];
+        }
+        for (int i = K - 1; i >= 0; --i) {
+            double v = col[i];
+            for (int k = i + 1; k < K; ++k) v -= L[k * K + i] * col[k];
+            col[i] = v / L[i * K + i];
+        }
+        for (int i = 0; i < K; ++i) inv[i * K + j] = col[i];
+    }
+    for (int i = 0; i < K; ++i)
+        for (int j = 0; j < i; ++j) {
+            double s = 0.5 * (inv[i * K + j] + inv[j * K + i]);
+            inv[i * K + j] = inv[j * K + i] = s;
+        }
+    return true;
+}
+
+// Degree plan of one side: rows in degree-descending order (ties by row id);
+// rows with more than `split` ratings are cut into segments of at most
+// `seg` ratings whose partial sums land in consecutive slots.
+void plan_side(const std::vector<int64_t> &ptr, int64_t rows, int64_t split, int64_t seg,
+               std::vector<int32_t> &perm, int64_t &n_split, std::vector<RowItem> &items,
+               std::vector<FinishItem> &fin, int64_t &n_slots)
+{
+    perm.resize(rows);
+    std::iota(perm.begin(), perm.end(), 0);
+    std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) {
+        return (ptr[a + 1] - ptr[a]) > (ptr[b + 1] - ptr[b]);
+    });
+    n_split = 0;
+    while (n_split < rows && ptr[perm[n_split] + 1] - ptr[perm[n_split]] > split) ++n_split;
+    items.clear();
+    fin.clear();
+    n_slots = 0;
+    for (int64_t q = 0; q < n_split; ++q) {
+        int32_t r = perm[q];
+        int64_t beg = ptr[r], end = ptr[r + 1];
+        FinishItem f{r, (int32_t)n_slots, 0, 0};
+        for (int64_t s = beg; s < end; s += seg) {
+            items.push_back(RowItem{r, (int32_t)n_slots, s, std::min(end, s + seg)});
+            ++n_slots;
+            ++f.count;
+        }
+        fin.push_back(f);
+    }
+    for (int64_t q = n_split; q < rows; ++q) {
+        int32_t r = perm[q];
+        items.push_back(RowItem{r, -1, ptr[r], ptr[r + 1]});
+    }
+}
+
+size_t elem_bytes(const bpmf_ctx *c) { return c->prec == 0 ? sizeof(double) : sizeof(float); }
+
+hipError_t enqueue_update(bpmf_ctx *c, int side_id, hipStream_t s)
+{
+    bool handled = false;
+    hipError_t e = launch_row_fast(c, side_id, s, &handled);
+    if (e != hipSuccess) return e;
+    if (!handled) e = launch_row_generic(c, side_id, s);
+    if (e != hipSuccess) return e;
+    if (c->prec == 2) e = launch_to_bf16(c, side_id, s);
+    return e;
+}
+
+hipError_t enqueue_sweep(bpmf_ctx *c, hipStream_t s)
+{
+    hipError_t e;
+    if ((e = launch_advance_t(c->ctr, s)) != hipSuccess) return e;
+    if ((e = launch_hyper(c, BPMF_SIDE_V, s)) != hipSuccess) return e;
+    if ((e = enqueue_update(c, BPMF_SIDE_V, s)) != hipSuccess) return e;
+    if ((e = launch_hyper(c, BPMF_SIDE_U, s)) != hipSuccess) return e;
+    if ((e = enqueue_update(c, BPMF_SIDE_U, s)) != hipSuccess) return e;
+    return launch_predict_test(c, s);
+}
+
+void free_side(Side &s)
+{
+    hipFree(s.ptr);
+    hipFree(s.nbr);
+    hipFree(s.rc);
+    hipFree(s.X);
+    hipFree(s.Xbf);
+    hipFree(s.mu);
+    hipFree(s.Lam);
+    hipFree(s.Lam_w);
+    hipFree(s.Lmu_w);
+    hipFree(s.items);
+    hipFree(s.fin);
+}
+
+}  // namespace
+
+extern "C" {
+
+void bpmf_default_params(bpmf_params *p, int32_t K)
+{
+    memset(p, 0, sizeof(*p));
+    p->K = K;
+    p->prec = BPMF_FP32;
+    p->alpha = 2.0;
+    p->beta0 = 2.0;
+    p->nu0 = (double)K;
+    p->mu0 = nullptr;
+    p->W0 = nullptr;
+    p->seed = 0;
+    p->center = 1;
+    p->burn_in = 0;
+    p->foldin_S = 16;
+    p->split_threshold = 0;
+    p->foldin_pool_bytes = 0;
+}
+
+const char *bpmf_last_error(const bpmf_ctx *c) { return c ? c->err.c_str() : g_create_err.c_str(); }
+
+int bpmf_create(int64_t M, int64_t N, const int64_t *csr_ptr, const int32_t *csr_col,
+                const float *csr_val, const int64_t *csc_ptr, const int32_t *csc_row,
+                const float *csc_val, int64_t nnz, const int32_t *test_row,
+                const int32_t *test_col, const float *test_val, int64_t n_test,
+                const bpmf_params *p, bpmf_ctx **out)
+{
+    if (!out || !p) return fail(nullptr, BPMF_E_INVAL, "null output or params");
+    *out = nullptr;
+    const int K = p->K;
+    if (K < 1 || K > 128) return fail(nullptr, BPMF_E_INVAL, "K=%d outside 1..128", K);
+    if (p->prec < 0 || p->prec > 2) return fail(nullptr, BPMF_E_INVAL, "bad precision %d", p->prec);
+    if (p->prec == BPMF_FP64 && K > 64) return fail(nullptr, BPMF_E_INVAL, "FP64 mode supports K <= 64");
+    if (!(p->alpha > 0) || !(p->beta0 > 0) || !(p->nu0 > K - 1))
+        return fail(nullptr, BPMF_E_INVAL, "need alpha > 0, beta0 > 0, nu0 > K - 1");
+    if (M < 1 || N < 1 || M > INT32_MAX || N > INT32_MAX || nnz < 0)
+        return fail(nullptr, BPMF_E_INVAL, "bad sizes M=%lld N=%lld nnz=%lld", (long long)M,
+                    (long long)N, (long long)nnz);
+    if (!csr_ptr || (nnz > 0 && (!csr_col || !csr_val)))
+        return fail(nullptr, BPMF_E_INVAL, "missing CSR arrays");
+    if (n_test < 0 || (n_test > 0 && (!test_row || !test_col || !test_val)))
+        return fail(nullptr, BPMF_E_INVAL, "missing test arrays");
+    // ---- validate CSR ----
+    if (csr_ptr[0] != 0 || csr_ptr[M] != nnz)
+        return fail(nullptr, BPMF_E_FORMAT, "csr_ptr must start at 0 and end at nnz");
+    for (int64_t i = 0; i < M; ++i) {
+        if (csr_ptr[i + 1] < csr_ptr[i])
+            return fail(nullptr, BPMF_E_FORMAT, "csr_ptr decreases at row %lld", (long long)i);
+        for (int64_t e = csr_ptr[i]; e < csr_ptr[i + 1]; ++e) {
+            if (csr_col[e] < 0 || csr_col[e] >= N)
+                return fail(nullptr, BPMF_E_RANGE, "column %d out of range at %lld", csr_col[e],
+                            (long long)e);
+            if (e > csr_ptr[i] && csr_col[e] <= csr_col[e - 1])
+                return fail(nullptr, BPMF_E_FORMAT,
+                            "columns not strictly increasing in row %lld", (long long)i);
+            if (!isfinite(csr_val[e]))
+                return fail(nullptr, BPMF_E_FORMAT, "non-finite rating at %lld", (long long)e);
+        }
+    }
+    for (int64_t e = 0; e < n_test; ++e) {
+        if (test_row[e] < 0 || test_row[e] >= M || test_col[e] < 0 || test_col[e] >= N)
+            return fail(nullptr, BPMF_E_RANGE, "test pair %lld out of range", (long long)e);
+        if (!isfinite(test_val[e])) return fail(nullptr, BPMF_E_FORMAT, "non-finite test value");
+    }
+    // ---- transpose (counting sort, rows ascending within a column) ----
+    std::vector<int64_t> tptr(N + 1, 0);
+    std::vector<int32_t> trow(nnz);
+    std::vector<float> tval(nnz);
+    for (int64_t e = 0; e < nnz; ++e) tptr[csr_col[e] + 1]++;
+    for (int64_t j = 0; j < N; ++j) tptr[j + 1] += tptr[j];
+    {
+        std::vector<int64_t> fill(tptr.begin(), tptr.end() - 1);
+        for (int64_t i = 0; i < M; ++i)
+            for (int64_t e = csr_ptr[i]; e < csr_ptr[i + 1]; ++e) {
+                int64_t q = fill[csr_col[e]]++;
+                trow[q] = (int32_t)i;
+                tval[q] = csr_val[e];
+            }
+    }
+    if (csc_ptr || csc_row || csc_val) {
+        if (!csc_ptr || (nnz > 0 && (!csc_row || !csc_val)))
+            return fail(nullptr, BPMF_E_INVAL, "incomplete CSC arrays");
+        if (memcmp(csc_ptr, tptr.data(), sizeof(int64_t) * (N + 1)) ||
+            (nnz && memcmp(csc_row, trow.data(), sizeof(int32_t) * nnz)) ||
+            (nnz && memcmp(csc_val, tval.data(), sizeof(float) * nnz)))
+            return fail(nullptr, BPMF_E_FORMAT, "CSC is not the exact transpose of the CSR");
+    }
+    std::vector<double> mu0(K, 0.0), W0((size_t)K * K, 0.0), W0inv;
+    if (p->mu0)
+        for (int k = 0; k < K; ++k) mu0[k] = p->mu0[k];
+    for (int k = 0; k < K; ++k) W0[(size_t)k * K + k] = 1.0;
+    if (p->W0)
+        for (size_t q = 0; q < (size_t)K * K; ++q) W0[q] = p->W0[q];
+    if (!spd_inverse_host(K, W0, W0inv)) return fail(nullptr, BPMF_E_INVAL, "W0 is not SPD");
+
+    bpmf_ctx *c = new bpmf_ctx();
+    c->M = M;
+    c->N = N;
+    c->nnz = nnz;
+    c->n_test = n_test;
+    c->K = K;
+    c->prec = p->prec;
+    c->ld = p->prec == BPMF_FP64 ? K : ((K + 3) / 4) * 4;
+    c->alpha = p->alpha;
+    c->beta0 = p->beta0;
+    c->nu0 = p->nu0;
+    c->seed = p->seed;
+    c->burn_in = p->burn_in;
+    c->split_threshold = p->split_threshold > 0 ? p->split_threshold : 4096;
+    double rbar = 0.0;
+    if (p->center) {
+        double s = 0.0;
+        for (int64_t e = 0; e < nnz; ++e) s += (double)csr_val[e];
+        rbar = nnz ? s / (double)nnz : 0.0;
+    }
+    c->rbar = rbar;
+    int rc = BPMF_OK;
+#define CK(expr)                         \
+    do {                                 \
+        hipError_t e_ = (expr);          \
+        if (e_ != hipSuccess) {          \
+            rc = fail(nullptr, e_ == hipErrorOutOfMemory ? BPMF_E_NOMEM : BPMF_E_DEVICE, \
+                      "%s: %s", #expr, hipGetErrorString(e_)); \
+            goto error;                  \
+        }                                \
+    } while (0)
+    {
+        CK(hipGetDevice(&c->device));
+        CK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+        CK(hipEventCreate(&c->ev0));
+        CK(hipEventCreate(&c->ev1));
+        const size_t es = elem_bytes(c);
+        std::vector<int64_t> csr_ptr_v(csr_ptr, csr_ptr + M + 1);
+        const std::vector<int64_t> *ptrs[2] = {&csr_ptr_v, &tptr};
+        const int32_t *nbrs[2] = {csr_col, trow.data()};
+        const float *vals[2] = {csr_val, tval.data()};
+        for (int sid = 0; sid < 2; ++sid) {
+            Side &sd = c->side[sid];
+            sd.rows = sid == 0 ? M : N;
+            sd.stream_row = sid == 0 ? 1u : 2u;
+            sd.stream_hyp = sid == 0 ? 3u : 4u;
+            sd.stream_init = sid == 0 ? 5u : 6u;
+            CK(dalloc(&sd.ptr, sd.rows + 1));
+            CK(dalloc(&sd.nbr, nnz));
+            CK(hipMalloc(&sd.rc, std::max<size_t>(1, nnz) * es));
+            CK(hipMalloc(&sd.X, std::max<size_t>(1, (size_t)sd.rows * c->ld) * es));
+            if (c->prec == BPMF_BF16_GRAM) CK(dalloc(&sd.Xbf, (size_t)sd.rows * c->ld));
+            CK(dalloc(&sd.mu, K));
+            CK(dalloc(&sd.Lam, (size_t)K * K));
+            CK(hipMalloc(&sd.Lam_w, (size_t)K * K * es));
+            CK(hipMalloc(&sd.Lmu_w, (size_t)K * es));
+            CK(hipMemcpy(sd.ptr, ptrs[sid]->data(), sizeof(int64_t) * (sd.rows + 1),
+                         hipMemcpyHostToDevice));
+            if (nnz) CK(hipMemcpy(sd.nbr, nbrs[sid], sizeof(int32_t) * nnz, hipMemcpyHostToDevice));
+            if (nnz) {
+                if (c->prec == BPMF_FP64) {
+                    std::vector<double> r(nnz);
+                    for (int64_t e = 0; e < nnz; ++e) r[e] = (double)vals[sid][e] - rbar;
+                    CK(hipMemcpy(sd.rc, r.data(), sizeof(double) * nnz, hipMemcpyHostToDevice));
+                } else {
+                    std::vector<float> r(nnz);
+                    for (int64_t e = 0; e < nnz; ++e) r[e] = (float)((double)vals[sid][e] - rbar);
+                    CK(hipMemcpy(sd.rc, r.data(), sizeof(float) * nnz, hipMemcpyHostToDevice));
+                }
+            }
+            std::vector<RowItem> items;
+            std::vector<FinishItem> fin;
+            plan_side(*ptrs[sid], sd.rows, c->split_threshold, 2048, sd.perm, sd.n_split, items,
+                      fin, sd.n_slots);
+            sd.n_items = (int64_t)items.size();
+            sd.n_fin = (int64_t)fin.size();
+            CK(dalloc(&sd.items, items.size()));
+            CK(dalloc(&sd.fin, fin.size()));
+            if (!items.empty())
+                CK(hipMemcpy(sd.items, items.data(), sizeof(RowItem) * items.size(),
+                             hipMemcpyHostToDevice));
+            if (!fin.empty())
+                CK(hipMemcpy(sd.fin, fin.data(), sizeof(FinishItem) * fin.size(),
+                             hipMemcpyHostToDevice));
+            // prior mean as the initial hyperparameters: mu0, nu0 W0
+            std::vector<double> lam0((size_t)K * K);
+            for (size_t q = 0; q < lam0.size(); ++q) lam0[q] = p->nu0 * W0[q];
+            CK(hipMemcpy(sd.mu, mu0.data(), sizeof(double) * K, hipMemcpyHostToDevice));
+            CK(hipMemcpy(sd.Lam, lam0.data(), sizeof(double) * K * K, hipMemcpyHostToDevice));
+        }
+        const int KK2 = K * (K + 1) / 2;
+        c->part_slots = std::max(c->side[0].n_slots, c->side[1].n_slots);
+        CK(hipMalloc(&c->part, std::max<size_t>(1, (size_t)c->part_slots * (KK2 + K)) * es));
+        CK(dalloc(&c->d_mu0, K));
+        CK(dalloc(&c->d_W0inv, (size_t)K * K));
+        CK(hipMemcpy(c->d_mu0, mu0.data(), sizeof(double) * K, hipMemcpyHostToDevice));
+        CK(hipMemcpy(c->d_W0inv, W0inv.data(), sizeof(double) * K * K, hipMemcpyHostToDevice));
+        c->hyp_blocks = 512;
+        CK(dalloc(&c->hyp_part, (size_t)c->hyp_blocks * (K + KK2)));
+        CK(dalloc(&c->hyp_stats, (size_t)(K + KK2)));
+        CK(dalloc(&c->hyp_scratch, (size_t)4 * K * K + 8 * K));
+        CK(dalloc(&c->hyp_status, 1));
+        {
+            int one = 1;
+            CK(hipMemcpy(c->hyp_status, &one, sizeof(int), hipMemcpyHostToDevice));
+        }
+        // test set
+        CK(dalloc(&c->test_row, n_test));
+        CK(dalloc(&c->test_col, n_test));
+        CK(dalloc(&c->test_val, n_test));
+        CK(dalloc(&c->pred_sum, n_test));
+        if (n_test) {
+            CK(hipMemcpy(c->test_row, test_row, sizeof(int32_t) * n_test, hipMemcpyHostToDevice));
+            CK(hipMemcpy(c->test_col, test_col, sizeof(int32_t) * n_test, hipMemcpyHostToDevice));
+            CK(hipMemcpy(c->test_val, test_val, sizeof(float) * n_test, hipMemcpyHostToDevice));
+        }
+        c->rmse_blocks = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (n_test + 15) / 16));
+        CK(dalloc(&c->rmse_part, 2 * (size_t)c->rmse_blocks));
+        c->hist_cap = 64;
+        CK(dalloc(&c->rmse_hist, 2 * (size_t)c->hist_cap));
+        CK(dalloc(&c->ctr, 4));
+        CK(hipMemsetAsync(c->ctr, 0, 4 * sizeof(uint32_t), c->stream));
+        CK(launch_fill_f64(c->pred_sum, n_test, 0.0, c->stream));
+        CK(prepare_kernels(c));
+        for (int sid = 0; sid < 2; ++sid) {
+            CK(launch_init_factor(c, sid, c->stream));
+            CK(launch_prior_to_working(c, sid, c->stream));
+            if (c->prec == BPMF_BF16_GRAM) CK(launch_to_bf16(c, sid, c->stream));
+        }
+        CK(hipStreamSynchronize(c->stream));
+    }
+#undef CK
+    *out = c;
+    return BPMF_OK;
+error:
+    bpmf_destroy(c);
+    return rc;
+}
+
+void bpmf_destroy(bpmf_ctx *c)
+{
+    if (!c) return;
+    if (c->stream) hipStreamSynchronize(c->stream);
+    if (c->graph) hipGraphExecDestroy(c->graph);
+    for (auto &s : c->side) free_side(s);
+    hipFree(c->d_mu0);
+    hipFree(c->d_W0inv);
+    hipFree(c->test_row);
+    hipFree(c->test_col);
+    hipFree(c->test_val);
+    hipFree(c->pred_sum);
+    hipFree(c->rmse_part);
+    hipFree(c->rmse_hist);
+    hipFree(c->hyp_part);
+    hipFree(c->hyp_stats);
+    hipFree(c->hyp_scratch);
+    hipFree(c->hyp_status);
+    hipFree(c->part);
+    hipFree(c->ctr);
+    hipFree(c->q_row);
+    hipFree(c->q_col);
+    hipFree(c->q_out);
+    if (c->ev0) hipEventDestroy(c->ev0);
+    if (c->ev1) hipEventDestroy(c->ev1);
+    if (c->stream) hipStreamDestroy(c->stream);
+    delete c;
+}
+
+static int check_side(bpmf_ctx *c, int32_t side)
+{
+    if (side != BPMF_SIDE_U && side != BPMF_SIDE_V) return fail(c, BPMF_E_INVAL, "bad side %d", side);
+    return BPMF_OK;
+}
+
+static int timed_end(bpmf_ctx *c)
+{
+    HIPCK(c, hipEventRecord(c->ev1, c->stream));
+    HIPCK(c, hipEventSynchronize(c->ev1));
+    float ms = 0;
+    HIPCK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    c->last_ms = ms;
+    return BPMF_OK;
+}
+
+static int check_hyper_status(bpmf_ctx *c)
+{
+    int st = 1;
+    HIPCK(c, hipMemcpy(&st, c->hyp_status, sizeof(int), hipMemcpyDeviceToHost));
+    if (!st) {
+        int one = 1;
+        HIPCK(c, hipMemcpy(c->hyp_status, &one, sizeof(int), hipMemcpyHostToDevice));
+        return fail(c, BPMF_E_DEVICE, "hyperparameter draw hit a non-SPD matrix");
+    }
+    return BPMF_OK;
+}
+
+int bpmf_sample_hyper(bpmf_ctx *c, int32_t side, uint32_t t)
+{
+    STICKY(c);
+    if (int r = check_side(c, side)) return r;
+    HIPCK(c, hipEventRecord(c->ev0, c->stream));
+    HIPCK(c, launch_set_counter(c->ctr, 0, t, c->stream));
+    HIPCK(c, launch_hyper(c, side, c->stream));
+    if (int r = timed_end(c)) return r;
+    return check_hyper_status(c);
+}
+
+int bpmf_update_side(bpmf_ctx *c, int32_t side, uint32_t t)
+{
+    STICKY(c);
+    if (int r = check_side(c, side)) return r;
+    HIPCK(c, hipEventRecord(c->ev0, c->stream));
+    HIPCK(c, launch_set_counter(c->ctr, 0, t, c->stream));
+    HIPCK(c, enqueue_update(c, side, c->stream));
+    return timed_end(c);
+}
+
+int bpmf_run_sweeps(bpmf_ctx *c, uint32_t t0, uint32_t n, double *rmse_avg, double *rmse_last)
+{
+    STICKY(c);
+    if (n == 0) return BPMF_OK;
+    if (t0 == 0) return fail(c, BPMF_E_INVAL, "sweeps are numbered from 1 (t = 0 is the initialisation)");
+    if ((int64_t)n > c->hist_cap) {
+        HIPCK(c, hipStreamSynchronize(c->stream));
+        hipFree(c->rmse_hist);
+        c->rmse_hist = nullptr;
+        int64_t cap = std::max<int64_t>(n, 2 * c->hist_cap);
+        HIPCK(c, dalloc(&c->rmse_hist, 2 * (size_t)cap));
+        c->hist_cap = cap;
+        if (c->graph) {
+            hipGraphExecDestroy(c->graph);
+            c->graph = nullptr;
+        }
+    }
+    if (!c->graph) {
+        hipGraph_t g = nullptr;
+        HIPCK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+        hipError_t e = enqueue_sweep(c, c->stream);
+        hipError_t e2 = hipStreamEndCapture(c->stream, &g);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (g) hipGraphDestroy(g);
+            return fail(c, BPMF_E_DEVICE, "graph capture failed: %s / %s", hipGetErrorString(e),
+                        hipGetErrorString(e2));
+        }
+        e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+        hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            c->graph = nullptr;
+            return fail(c, BPMF_E_DEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
+        }
+    }
+    HIPCK(c, launch_set_counter(c->ctr, 0, t0 - 1, c->stream));
+    HIPCK(c, launch_set_counter(c->ctr, 1, t0, c->stream));
+    HIPCK(c, hipEventRecord(c->ev0, c->stream));
+    for (uint32_t i = 0; i < n; ++i) HIPCK(c, hipGraphLaunch(c->graph, c->stream));
+    if (int r = timed_end(c)) return r;
+    if (int r = check_hyper_status(c)) return r;
+    std::vector<double> h(2 * (size_t)n);
+    HIPCK(c, hipMemcpy(h.data(), c->rmse_hist, sizeof(double) * 2 * n, hipMemcpyDeviceToHost));
+    for (uint32_t i = 0; i < n; ++i) {
+        if (rmse_avg) rmse_avg[i] = h[2 * i];
+        if (rmse_last) rmse_last[i] = h[2 * i + 1];
+    }
+    return BPMF_OK;
+}
+
+int bpmf_predict(bpmf_ctx *c, uint32_t t, int64_t n, const int32_t *row, const int32_t *col,
+                 float *out, double *rmse_avg, double *rmse_last)
+{
+    STICKY(c);
+    if (n < 0) return fail(c, BPMF_E_INVAL, "negative n");
+    if (n == 0) {
+        HIPCK(c, launch_set_counter(c->ctr, 0, t, c->stream));
+        HIPCK(c, launch_set_counter(c->ctr, 1, t, c->stream));
+        HIPCK(c, launch_predict_test(c, c->stream));
+        double h[2];
+        HIPCK(c, hipMemcpyAsync(h, c->rmse_hist, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+        HIPCK(c, hipStreamSynchronize(c->stream));
+        if (rmse_avg) *rmse_avg = h[0];
+        if (rmse_last) *rmse_last = h[1];
+        return BPMF_OK;
+    }
+    if (!row || !col || !out) return fail(c, BPMF_E_INVAL, "null pair arrays");
+    for (int64_t e = 0; e < n; ++e)
+        if (row[e] < 0 || row[e] >= c->M || col[e] < 0 || col[e] >= c->N)
+            return fail(c, BPMF_E_RANGE, "pair %lld out of range", (long long)e);
+    if (n > c->q_cap) {
+        HIPCK(c, hipStreamSynchronize(c->stream));
+        hipFree(c->q_row);
+        hipFree(c->q_col);
+        hipFree(c->q_out);
+        c->q_row = c->q_col = nullptr;
+        c->q_out = nullptr;
+        c->q_cap = 0;
+        HIPCK(c, dalloc(&c->q_row, n));
+        HIPCK(c, dalloc(&c->q_col, n));
+        HIPCK(c, dalloc(&c->q_out, n));
+        c->q_cap = n;
+    }
+    HIPCK(c, hipMemcpyAsync(c->q_row, row, sizeof(int32_t) * n, hipMemcpyHostToDevice, c->stream));
+    HIPCK(c, hipMemcpyAsync(c->q_col, col, sizeof(int32_t) * n, hipMemcpyHostToDevice, c->stream));
+    HIPCK(c, launch_predict_pairs(c, n, c->stream));
+    HIPCK(c, hipMemcpyAsync(out, c->q_out, sizeof(float) * n, hipMemcpyDeviceToHost, c->stream));
+    HIPCK(c, hipStreamSynchronize(c->stream));
+    return BPMF_OK;
+}
+
+static int copy_factor(bpmf_ctx *c, int32_t side, void *host, bool to_host)
+{
+    Side &sd = c->side[side];
+    size_t es = elem_bytes(c);
+    HIPCK(c, hipStreamSynchronize(c->stream));
+    if (sd.rows == 0) return BPMF_OK;
+    if (to_host)
+        HIPCK(c, hipMemcpy2D(host, c->K * es, sd.X, c->ld * es, c->K * es, sd.rows,
+                             hipMemcpyDeviceToHost));
+    else
+        HIPCK(c, hipMemcpy2D(sd.X, c->ld * es, host, c->K * es, c->K * es, sd.rows,
+                             hipMemcpyHostToDevice));
+    return BPMF_OK;
+}
+
+int bpmf_get_factor(bpmf_ctx *c, int32_t side, void *host)
+{
+    STICKY(c);
+    if (int r = check_side(c, side)) return r;
+    if (!host) return fail(c, BPMF_E_INVAL, "null buffer");
+    return copy_factor(c, side, host, true);
+}
+
+int bpmf_set_factor(bpmf_ctx *c, int32_t side, const void *host)
+{
+    STICKY(c);
+    if (int r = check_side(c, side)) return r;
+    if (!host) return fail(c, BPMF_E_INVAL, "null buffer");
+    if (int r = copy_factor(c, side, const_cast<void *>(host), false)) return r;
+    if (c->prec == BPMF_BF16_GRAM) {
+        HIPCK(c, launch_to_bf16(c, side, c->stream));
+        HIPCK(c, hipStreamSynchronize(c->stream));
+    }
+    return BPMF_OK;
+}
+
+int bpmf_get_factor_f64(bpmf_ctx *c, int32_t side, double *host)
+{
+    STICKY(c);
+    if (int r = check_side(c, side)) return r;
+    if (!host) return fail(c, BPMF_E_INVAL, "null buffer");
+    if (c->prec == BPMF_FP64) return copy_factor(c, side, host, true);
+    size_t n = (size_t)c->side[side].rows * c->K;
+    std::vector<float> tmp(n);
+    if (int r = copy_factor(c, side, tmp.data(), true)) return r;
+    for (size_t q = 0; q < n; ++q) host[q] = tmp[q];
+    return BPMF_OK;
+}
+
+int bpmf_set_factor_f64(bpmf_ctx *c, int32_t side, const double *host)
+{
+    STICKY(c);
+    if (int r = check_side(c, side)) return r;
+    if (!host) return fail(c, BPMF_E_INVAL, "null buffer");
+    if (c->prec == BPMF_FP64) return copy_factor(c, side, const_cast<double *>(host), false);
+    size_t n = (size_t)c->side[side].rows * c->K;
+    std::vector<float> tmp(n);
+    for (size_t q = 0; q < n; ++q) tmp[q] = (float)host[q];
+    return bpmf_set_factor(c, side, tmp.data());
+}
+
+int bpmf_get_hyper(bpmf_ctx *c, int32_t side, double *mu, double *Lambda)
+{
+    STICKY(c);
+    if (int r = check_side(c, side)) return r;
+    HIPCK(c, hipStreamSynchronize(c->stream));
+    if (mu) HIPCK(c, hipMemcpy(mu, c->side[side].mu, sizeof(double) * c->K, hipMemcpyDeviceToHost));
+    if (Lambda)
+        HIPCK(c, hipMemcpy(Lambda, c->side[side].Lam, sizeof(double) * c->K * c->K,
+                           hipMemcpyDeviceToHost));
+    return BPMF_OK;
+}
+
+int bpmf_set_hyper(bpmf_ctx *c, int32_t side, const double *mu, const double *Lambda)
+{
+    STICKY(c);
+    if (int r = check_side(c, side)) return r;
+    if (!mu || !Lambda) return fail(c, BPMF_E_INVAL, "null hyperparameters");
+    HIPCK(c, hipStreamSynchronize(c->stream));
+    HIPCK(c, hipMemcpy(c->side[side].mu, mu, sizeof(double) * c->K, hipMemcpyHostToDevice));
+    HIPCK(c, hipMemcpy(c->side[side].Lam, Lambda, sizeof(double) * c->K * c->K,
+                       hipMemcpyHostToDevice));
+    HIPCK(c, launch_prior_to_working(c, side, c->stream));
+    HIPCK(c, hipStreamSynchronize(c->stream));
+    return BPMF_OK;
+}
+
+int bpmf_get_csc(bpmf_ctx *c, int64_t *ptr, int32_t *row, void *rc)
+{
+    STICKY(c);
+    Side &sd = c->side[BPMF_SIDE_V];
+    HIPCK(c, hipStreamSynchronize(c->stream));
+    if (ptr) HIPCK(c, hipMemcpy(ptr, sd.ptr, sizeof(int64_t) * (c->N + 1), hipMemcpyDeviceToHost));
+    if (row && c->nnz)
+        HIPCK(c, hipMemcpy(row, sd.nbr, sizeof(int32_t) * c->nnz, hipMemcpyDeviceToHost));
+    if (rc && c->nnz)
+        HIPCK(c, hipMemcpy(rc, sd.rc, elem_bytes(c) * c->nnz, hipMemcpyDeviceToHost));
+    return BPMF_OK;
+}
+
+int bpmf_get_plan(bpmf_ctx *c, int32_t side, int32_t *perm, int64_t *n_split)
+{
+    STICKY(c);
+    if (int r = check_side(c, side)) return r;
+    Side &sd = c->side[side];
+    if (perm) memcpy(perm, sd.perm.data(), sizeof(int32_t) * sd.rows);
+    if (n_split) *n_split = sd.n_split;
+    return BPMF_OK;
+}
+
+double bpmf_mean_rating(const bpmf_ctx *c) { return c ? c->rbar : 0.0; }
+
+int bpmf_synchronize(bpmf_ctx *c)
+{
+    STICKY(c);
+    HIPCK(c, hipStreamSynchronize(c->stream));
+    return BPMF_OK;
+}
+
+int bpmf_last_time_ms(bpmf_ctx *c, double *ms)
+{
+    if (!c || !ms) return BPMF_E_INVAL;
+    *ms = c->last_ms;
+    return BPMF_OK;
+}
+
+}  // extern "C"

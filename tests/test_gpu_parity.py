@@ -1,0 +1,316 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Every test here runs kernels on an MI355X and compares their results with
+the oracle on identical inputs and identical Philox noise.  Tolerances:
+  * integer / index work (CSC transpose, plan, counters): bit-exact;
+  * single-step row draws: ||x_gpu - x_orc||_2 <= tol * max(||x_orc||_2,
+    1e-3 sqrt(K)) per row, tol = 1e-10 in FP64 mode, 1e-4 in FP32 mode,
+    2e-2 in BF16-Gram mode;
+  * hyperparameter draws (FP64 in every mode): 1e-9 relative;
+  * whole chains: |RMSE_gpu / RMSE_orc - 1| <= 0.5%.
+"""
+import sys
+
+import numpy as np
+import pytest
+import scipy.sparse
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-10, "fp32": 1e-4, "bf16": 2e-2}
+
+
+@pytest.fixture(scope="module")
+def bp():
+    import paper_1705_04159_amd as bp
+
+    bp.lib()
+    return bp
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def row_errors(x_gpu, x_orc):
+    K = x_orc.shape[1]
+    num = np.linalg.norm(x_gpu - x_orc, axis=1)
+    den = np.maximum(np.linalg.norm(x_orc, axis=1), 1e-3 * np.sqrt(K))
+    return num / den
+
+
+def _random_state(rng, M, N, K):
+    U = rng.standard_normal((M, K)) * K ** -0.25
+    V = rng.standard_normal((N, K)) * K ** -0.25
+    A = rng.standard_normal((K, K))
+    Lam = A @ A.T / K + np.eye(K)
+    mu = rng.standard_normal(K) * 0.1
+    return U, V, mu, Lam
+
+
+def _bf16_round(x):
+    """Round-to-nearest-even to BF16, returned as float64 (test-side copy)."""
+    u = np.asarray(x, np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16 << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def single_step(bp, orc, r, K, prec, side, t=7, seed=123, split=0, rows=None):
+    """Set identical state on both sides, update one side once, compare."""
+    _say("single_step %s K=%d prec=%s side=%d split=%d M=%d N=%d nnz=%d" % (
+        r.name, K, prec, side, split, r.M, r.N, r.nnz))
+    rng = np.random.default_rng(seed)
+    U, V, mu, Lam = _random_state(rng, r.M, r.N, K)
+    s = bp.Sampler(r, K, prec=prec, seed=seed, split_threshold=split)
+    s.set_factor(bp.SIDE_U, U)
+    s.set_factor(bp.SIDE_V, V)
+    s.set_hyper(side, mu, Lam)
+    s.update_side(side, t)
+    got = s.get_factor(side).astype(np.float64)
+    # oracle on the values the GPU holds (rounded to its storage precision)
+    Ug = s.get_factor(bp.SIDE_U).astype(np.float64)
+    Vg = s.get_factor(bp.SIDE_V).astype(np.float64)
+    rbar = s.mean_rating
+    s.close()
+    ch = orc.Chain(r.M, r.N, K, r.csr_ptr, r.csr_col, r.csr_val, r.test_row, r.test_col,
+                   r.test_val, seed=seed)
+    assert ch.rbar == rbar  # same FP64 sequential mean
+    if side == bp.SIDE_U:
+        Y = V.astype(np.float32 if prec != "fp64" else np.float64).astype(np.float64)
+        if prec == "bf16":
+            Y = _bf16_round(Y)
+        X = U.astype(np.float32 if prec != "fp64" else np.float64).astype(np.float64).copy()
+        orc.update_rows(ch.csr_ptr, ch.csr_col, ch.csr_rc, Y, X, mu, Lam, 2.0, seed, orc.ROW_U, t,
+                        rows=rows)
+        ref = X
+    else:
+        Y = U.astype(np.float32 if prec != "fp64" else np.float64).astype(np.float64)
+        if prec == "bf16":
+            Y = _bf16_round(Y)
+        X = V.astype(np.float32 if prec != "fp64" else np.float64).astype(np.float64).copy()
+        orc.update_rows(ch.csc_ptr, ch.csc_row, ch.csc_rc, Y, X, mu, Lam, 2.0, seed, orc.ROW_V, t,
+                        rows=rows)
+        ref = X
+    sel = np.arange(ref.shape[0]) if rows is None else np.asarray(rows)
+    err = row_errors(got[sel], ref[sel])
+    _say("  max row err %.3e (median %.3e)" % (err.max(), np.median(err)))
+    return err, got, ref
+
+
+# ---------------------------------------------------------------------------
+# index work: bit-exact
+# ---------------------------------------------------------------------------
+def test_csc_transpose_bitexact(bp):
+    r = synth.random_small(9, 300, 200, 5000, 4, empty_rows=7)
+    s = bp.Sampler(r, 4, prec="fp32")
+    ptr, row, rc = s.get_csc()
+    A = scipy.sparse.csr_matrix((r.csr_val, r.csr_col, r.csr_ptr), shape=(r.M, r.N)).tocsc()
+    A.sort_indices()
+    assert np.array_equal(ptr, A.indptr)
+    assert np.array_equal(row, A.indices)
+    assert np.array_equal(rc, (A.data.astype(np.float64) - s.mean_rating).astype(np.float32))
+    s.close()
+
+
+def test_plan_bitexact(bp):
+    r = synth.planted()
+    s = bp.Sampler(r, 10, prec="fp32", split_threshold=100)
+    for side, ptr in ((bp.SIDE_U, r.csr_ptr),
+                      (bp.SIDE_V, np.concatenate([[0], np.cumsum(np.bincount(r.csr_col, minlength=r.N))]))):
+        deg = np.diff(ptr)
+        perm, n_split = s.get_plan(side)
+        assert np.array_equal(perm, np.argsort(-deg, kind="stable"))
+        assert n_split == int((deg > 100).sum())
+    s.close()
+
+
+def test_create_rejects_bad_input(bp):
+    r = synth.random_small(1, 20, 10, 60, 3)
+    bad = synth.Ratings(**{**r.__dict__})
+    bad.csr_col = r.csr_col.copy()
+    bad.csr_col[0] = r.N  # out of range
+    with pytest.raises(bp.BPMFError) as e:
+        bp.Sampler(bad, 3)
+    assert e.value.code == bp.E_RANGE
+    bad.csr_col = r.csr_col.copy()
+    i = np.nonzero(np.diff(r.csr_ptr) >= 2)[0][0]
+    a = r.csr_ptr[i]
+    bad.csr_col[a + 1] = bad.csr_col[a]  # duplicate column in a row
+    with pytest.raises(bp.BPMFError) as e:
+        bp.Sampler(bad, 3)
+    assert e.value.code == bp.E_FORMAT
+    with pytest.raises(bp.BPMFError) as e:
+        bp.Sampler(r, 0)
+    assert e.value.code == bp.E_INVAL
+    # a CSC that is not the transpose
+    A = scipy.sparse.csr_matrix((r.csr_val, r.csr_col, r.csr_ptr), shape=(r.M, r.N)).tocsc()
+    A.sort_indices()
+    good = bp.Sampler(r, 3, csc=(A.indptr, A.indices, A.data))
+    good.close()
+    wrong = A.data.copy()
+    wrong[0] += 1
+    with pytest.raises(bp.BPMFError) as e:
+        bp.Sampler(r, 3, csc=(A.indptr, A.indices, wrong))
+    assert e.value.code == bp.E_FORMAT
+
+
+# ---------------------------------------------------------------------------
+# initialisation and noise
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_init_factor_matches_oracle(bp, orc, prec):
+    r = synth.random_small(2, 150, 70, 1200, 6)
+    s = bp.Sampler(r, 6, prec=prec, seed=77)
+    for side, stream, n in ((bp.SIDE_U, orc.INIT_U, r.M), (bp.SIDE_V, orc.INIT_V, r.N)):
+        got = s.get_factor(side).astype(np.float64)
+        ref = orc.init_factor(77, stream, n, 6)
+        tol = 1e-13 if prec == "fp64" else 1e-6
+        assert np.max(np.abs(got - ref)) <= tol * max(1.0, np.abs(ref).max())
+    s.close()
+
+
+# ---------------------------------------------------------------------------
+# single-step row parity
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("prec,K", [("fp64", 10), ("fp64", 1), ("fp64", 33), ("fp32", 10),
+                                    ("fp32", 32), ("fp32", 64), ("fp32", 100), ("fp32", 7),
+                                    ("bf16", 32), ("bf16", 100)])
+@pytest.mark.parametrize("side", [0, 1])
+def test_row_update_single_step(bp, orc, prec, K, side):
+    r = synth.random_small(40 + K, 700, 300, 20000, min(K, 16), empty_rows=5)
+    err, got, ref = single_step(bp, orc, r, K, prec, side)
+    assert np.isfinite(got).all()
+    assert err.max() <= TOL[prec], (err.max(), np.argmax(err))
+
+
+@pytest.mark.parametrize("prec,K", [("fp64", 10), ("fp32", 32), ("fp32", 100), ("bf16", 64)])
+def test_split_rows_single_step(bp, orc, prec, K):
+    """Heavy rows split into segments (fixed-order partial reduction)."""
+    r = synth.planted(seed=5, M=600, N=250, nnz=30000, K=min(K, 10), zipf=0.9)
+    err, got, ref = single_step(bp, orc, r, K, prec, 1, split=150)
+    assert err.max() <= TOL[prec], err.max()
+    err, got, ref = single_step(bp, orc, r, K, prec, 0, split=150)
+    assert err.max() <= TOL[prec], err.max()
+
+
+def test_row_update_planted_c1_shape_fp64(bp, orc):
+    r = synth.planted()
+    for side in (0, 1):
+        err, _, _ = single_step(bp, orc, r, 10, "fp64", side, t=3)
+        assert err.max() <= TOL["fp64"]
+
+
+# ---------------------------------------------------------------------------
+# hyperparameters
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("prec,K", [("fp64", 10), ("fp32", 32), ("fp32", 100), ("fp64", 1)])
+def test_hyper_draw_parity(bp, orc, prec, K):
+    r = synth.random_small(3, 900, 400, 5000, min(K, 8))
+    s = bp.Sampler(r, K, prec=prec, seed=31)
+    rng = np.random.default_rng(K)
+    U, V, _, _ = _random_state(rng, r.M, r.N, K)
+    s.set_factor(bp.SIDE_U, U)
+    s.set_factor(bp.SIDE_V, V)
+    for side, stream in ((bp.SIDE_U, orc.HYP_U), (bp.SIDE_V, orc.HYP_V)):
+        for t in (1, 9):
+            s.sample_hyper(side, t)
+            mu, Lam = s.get_hyper(side)
+            X = s.get_factor(side).astype(np.float64)
+            mu_r, Lam_r = orc.hyper_draw(X, np.zeros(K), 2.0, float(K), np.eye(K), 31, stream, t)
+            assert np.allclose(Lam, Lam_r, rtol=1e-9, atol=1e-9 * np.abs(Lam_r).max())
+            assert np.allclose(mu, mu_r, rtol=1e-9, atol=1e-9 * (1 + np.abs(mu_r).max()))
+    s.close()
+
+
+# ---------------------------------------------------------------------------
+# prediction
+# ---------------------------------------------------------------------------
+def test_predict_pairs_and_test_rmse(bp, orc):
+    r = synth.random_small(5, 400, 300, 8000, 8)
+    s = bp.Sampler(r, 8, prec="fp32", seed=3)
+    U = s.get_factor(bp.SIDE_U).astype(np.float64)
+    V = s.get_factor(bp.SIDE_V).astype(np.float64)
+    rows = np.array([0, 5, 399, 17], np.int32)
+    cols = np.array([0, 299, 3, 17], np.int32)
+    got = s.predict(rows, cols)
+    ref = orc.predict(rows, cols, U, V, s.mean_rating)
+    assert np.allclose(got, ref, rtol=1e-5, atol=1e-5)
+    avg, last = s.predict_test(1)
+    p = orc.predict(r.test_row, r.test_col, U, V, s.mean_rating)
+    ref_last = np.sqrt(np.mean((p - r.test_val.astype(np.float64)) ** 2))
+    assert last == pytest.approx(ref_last, rel=1e-6)
+    assert avg == pytest.approx(ref_last, rel=1e-6)  # first averaged sweep: mean of one sample
+    with pytest.raises(bp.BPMFError) as e:
+        s.predict(np.array([400], np.int32), np.array([0], np.int32))
+    assert e.value.code == bp.E_RANGE
+    s.close()
+
+
+# ---------------------------------------------------------------------------
+# whole chains
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_chain_planted_c1_matches_oracle(bp, orc, prec):
+    """Planted 1000 x 500, 20,000 ratings, K = 10, 20 sweeps: coupled chains
+    (same seed, same noise) end within 0.5% in held-out RMSE."""
+    r = synth.planted()
+    _say("chain C1 %s" % prec)
+    s = bp.Sampler(r, 10, prec=prec, seed=101)
+    avg, last = s.run_sweeps(1, 20)
+    ch = orc.Chain(r.M, r.N, 10, r.csr_ptr, r.csr_col, r.csr_val, r.test_row, r.test_col,
+                   r.test_val, seed=101)
+    res = ch.run(1, 20)
+    ref_avg = np.array([a for a, _ in res])
+    ref_last = np.array([b for _, b in res])
+    _say("gpu avg %s\norc avg %s" % (avg[-3:], ref_avg[-3:]))
+    assert abs(avg[-1] / ref_avg[-1] - 1) <= 0.005
+    assert abs(last[-1] / ref_last[-1] - 1) <= 0.005
+    if prec == "fp64":  # FP64 chains stay coupled to near round-off
+        U = s.get_factor(bp.SIDE_U)
+        assert np.max(np.abs(U - ch.U)) < 1e-6
+    s.close()
+
+
+def test_graph_replay_equals_eager(bp):
+    r = synth.random_small(8, 500, 250, 9000, 8)
+    a = bp.Sampler(r, 8, prec="fp32", seed=5)
+    avg, last = a.run_sweeps(1, 3)
+    b = bp.Sampler(r, 8, prec="fp32", seed=5)
+    for t in (1, 2, 3):
+        b.sample_hyper(bp.SIDE_V, t)
+        b.update_side(bp.SIDE_V, t)
+        b.sample_hyper(bp.SIDE_U, t)
+        b.update_side(bp.SIDE_U, t)
+        ea, el = b.predict_test(t)
+    assert np.array_equal(a.get_factor(bp.SIDE_U), b.get_factor(bp.SIDE_U))
+    assert np.array_equal(a.get_factor(bp.SIDE_V), b.get_factor(bp.SIDE_V))
+    assert last[-1] == el
+    # replaying the same graph again continues the chain deterministically
+    a2, l2 = a.run_sweeps(4, 2)
+    c = bp.Sampler(r, 8, prec="fp32", seed=5)
+    c.run_sweeps(1, 3)
+    c2, cl2 = c.run_sweeps(4, 2)
+    assert np.array_equal(l2, cl2)
+    for x in (a, b, c):
+        x.close()
+
+
+def test_checkpoint_resume_bitexact(bp):
+    r = synth.random_small(12, 400, 200, 7000, 6)
+    full = bp.Sampler(r, 6, prec="fp32", seed=9)
+    full.run_sweeps(1, 6)
+    part = bp.Sampler(r, 6, prec="fp32", seed=9)
+    part.run_sweeps(1, 3)
+    state = [part.get_factor(bp.SIDE_U), part.get_factor(bp.SIDE_V)]
+    part.close()
+    res = bp.Sampler(r, 6, prec="fp32", seed=9)
+    res.set_factor(bp.SIDE_U, state[0])
+    res.set_factor(bp.SIDE_V, state[1])
+    res.run_sweeps(4, 3)
+    assert np.array_equal(full.get_factor(bp.SIDE_U), res.get_factor(bp.SIDE_U))
+    assert np.array_equal(full.get_factor(bp.SIDE_V), res.get_factor(bp.SIDE_V))
+    full.close()
+    res.close()
