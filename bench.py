@@ -1,0 +1,194 @@
+#!/usr/bin/env python3
+"""Throughput of the BPMF Gibbs sweep (Algorithm 1) on one MI355X.
+
+A step is one full sweep: hyper draw of V, update of every movie, hyper draw
+of U, update of every user, prediction of the test set.  The default
+workload has the shape of a 20M-rating recommender (M = 138,493 users,
+N = 26,744 movies, 20,000,263 ratings, 10% held out, K = 32, FP32), made by
+the seeded generators in ``synth``; inputs are resident in HBM before the
+timed region starts.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+
+PEAK_FP32_TFLOPS = 157.3  # MI355X dense FP32 (matrix cores), TFLOP/s
+PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, GB/s
+L2_BYTES = 4 << 20  # one XCD's L2
+
+WORKLOADS = {
+    # name: (generator, K, precision)
+    "movielens": (synth.movielens_like, 32, "fp32"),
+    "netflix": (synth.netflix_like, 100, "fp32"),
+    "netflix_mini": (synth.netflix_mini, 100, "fp32"),
+    "chembl": (synth.chembl_like, 64, "fp32"),
+    "planted": (synth.planted, 10, "fp64"),
+}
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def algorithmic(K, nnz, rows_finished, rows_written, gather_row_bytes, src_bytes):
+    """Per-launch algorithmic work of the row kernel of one side.
+
+    FLOP: K(K+1) + 2K per rating (lower-triangle Gram + rhs) and
+    K^3/3 + 2K^2 per finished row (Cholesky + two triangular solves).
+    Bytes: 8 per rating (neighbour id + rating), the gathered row (K x
+    element size) per rating when the gathered factor exceeds one L2, and
+    the written row."""
+    flops = nnz * (K * (K + 1) + 2 * K) + rows_finished * (K ** 3 / 3.0 + 2 * K * K)
+    gather = gather_row_bytes * nnz if src_bytes > L2_BYTES else 0
+    byts = 8 * nnz + gather + 4 * K * rows_written
+    return flops, byts
+
+
+def cpu_baseline(r, K, seconds, seed):
+    """The FP64 oracle timed on this host on a bounded sample of the same
+    workload: random rows of both sides (in proportion M : N), updated with
+    the oracle's row routine and all host cores, until `seconds` elapse."""
+    import oracle
+
+    oracle.build()
+    rng = np.random.default_rng(seed)
+    ch = oracle.Chain(r.M, r.N, K, r.csr_ptr, r.csr_col, r.csr_val, r.test_row[:1],
+                      r.test_col[:1], r.test_val[:1], seed=seed)
+    mu, lam = np.zeros(K), np.eye(K) * K
+    order = rng.permutation(r.M + r.N)
+    done, t0 = 0, time.perf_counter()
+    batch = 512
+    while time.perf_counter() - t0 < seconds:
+        q = done % len(order)
+        sweep = 1 + done // len(order)
+        sel = order[q:q + batch]
+        u = sel[sel < r.M]
+        v = sel[sel >= r.M] - r.M
+        if len(v):
+            oracle.update_rows(ch.csc_ptr, ch.csc_row, ch.csc_rc, ch.U, ch.V, mu, lam, 2.0, seed,
+                               oracle.ROW_V, sweep, rows=v)
+        if len(u):
+            oracle.update_rows(ch.csr_ptr, ch.csr_col, ch.csr_rc, ch.V, ch.U, mu, lam, 2.0, seed,
+                               oracle.ROW_U, sweep, rows=u)
+        done += len(sel)
+    el = time.perf_counter() - t0
+    return {"value": done / el, "unit": "row-updates/s", "cores": oracle.max_threads(),
+            "kind": "oracle",
+            "sample": "%d row draws (FP64) over random rows of both sides of the same "
+                      "workload (%d rows per sweep), %.1f s" % (done, r.M + r.N, el)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="movielens", choices=sorted(WORKLOADS))
+    ap.add_argument("--prec", default=None, choices=["fp64", "fp32", "bf16"])
+    ap.add_argument("--seed", type=int, default=102)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-steps", type=int, default=5)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import paper_1705_04159_amd as bp
+
+    gen, K, prec = WORKLOADS[args.workload]
+    prec = args.prec or prec
+    t = time.perf_counter()
+    r = gen()
+    log("generated %s: M=%d N=%d nnz=%d test=%d in %.1fs" % (r.name, r.M, r.N, r.nnz,
+                                                             len(r.test_row), time.perf_counter() - t))
+    t = time.perf_counter()
+    s = bp.Sampler(r, K, prec=prec, seed=args.seed)
+    log("created context in %.1fs" % (time.perf_counter() - t))
+    steps, warm = args.steps, args.warmup
+    if warm > 0:
+        s.run_sweeps(1, warm)
+        log("warmup %d sweeps done" % warm)
+    s.synchronize()
+    t0 = time.perf_counter()
+    avg, last = s.run_sweeps(warm + 1, steps)  # returns after the stream is drained
+    s.synchronize()
+    wall = time.perf_counter() - t0
+    dev_ms = s.last_time_ms()
+    ms_per_step = 1000.0 * wall / steps
+    rows = r.M + r.N
+    value = rows / (ms_per_step / 1000.0)
+    log("timed %d sweeps: %.3f ms/sweep wall (%.3f device), rmse avg %.4f last %.4f" % (
+        steps, ms_per_step, dev_ms / steps, avg[-1], last[-1]))
+
+    # per-phase device times (eager launches bracketed by HIP events)
+    pn = max(1, min(args.profile_steps, 64))
+    ph = s.profile_sweeps(warm + steps + 1, pn)
+    names = ["hyper_V", "rows_V", "split_V", "hyper_U", "rows_U", "split_U", "predict"]
+    phase = {n: round(float(v), 4) for n, v in zip(names, ph)}
+    log("phases (ms): %s" % phase)
+    esize = 8 if prec == "fp64" else (2 if prec == "bf16" else 4)
+    _, ns_u = s.get_plan(bp.SIDE_U)
+    _, ns_v = s.get_plan(bp.SIDE_V)
+    cand = {
+        "rows_V": algorithmic(K, r.nnz, r.N - ns_v, r.N, K * esize, r.M * K * esize),
+        "rows_U": algorithmic(K, r.nnz, r.M - ns_u, r.M, K * esize, r.N * K * esize),
+    }
+    dom = max(cand, key=lambda n: phase[n])
+    flops, byts = cand[dom]
+    sec = phase[dom] / 1000.0
+    t_mfma = flops / (PEAK_FP32_TFLOPS * 1e12)
+    t_hbm = byts / (PEAK_HBM_GBS * 1e9)
+    if t_hbm > t_mfma:
+        roof = {"bound": "hbm", "achieved": round(byts / sec / 1e9, 1), "peak": PEAK_HBM_GBS,
+                "unit": "GB/s"}
+    else:
+        roof = {"bound": "mfma", "achieved": round(flops / sec / 1e12, 3), "peak": PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s"}
+    roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
+    roof["traffic"] = None
+    roof["kernel"] = "row update, side %s (mean of %d launches, %.4f ms)" % (dom[-1], pn, phase[dom])
+
+    out = {
+        "metric": "Gibbs row-updates/s",
+        "value": round(value, 1),
+        "unit": "row-updates/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warm,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16-gram/f32"}[prec],
+        "data": "synthetic",
+        "config": {"workload": r.name, "M": r.M, "N": r.N, "nnz_train": r.nnz,
+                   "n_test": int(len(r.test_row)), "K": K, "precision": prec,
+                   "parallelism": "single-gpu"},
+        "ratings_per_s": round(2 * r.nnz / (ms_per_step / 1000.0), 1),
+        "rmse_avg": round(float(avg[-1]), 5),
+        "rmse_last": round(float(last[-1]), 5),
+        "phase_ms": phase,
+        "roofline": roof,
+    }
+    s.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(r, K, args.cpu_seconds, args.seed)
+        log("cpu baseline: %s" % out["cpu_baseline"])
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

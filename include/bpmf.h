@@ -128,6 +128,13 @@ int bpmf_update_side(bpmf_ctx *c, int32_t side, uint32_t t);
  * t > burn_in) and of the current sample. */
 int bpmf_run_sweeps(bpmf_ctx *c, uint32_t t0, uint32_t n, double *rmse_avg, double *rmse_last);
 
+/* Algorithm 1 for sweeps t0 .. t0+n-1 launched eagerly with HIP events
+ * between its phases; phase_ms[7] receives the mean device time per sweep
+ * of: hyper draw V, row kernel of V (all rows and split-row segments),
+ * finishing of V's split rows, the same three for U, and prediction.  The chain advances exactly as with bpmf_run_sweeps
+ * (n must not exceed the RMSE history size of an earlier bpmf_run_sweeps). */
+int bpmf_profile_sweeps(bpmf_ctx *c, uint32_t t0, uint32_t n, double *phase_ms);
+
 /* Algorithm 1, "predict rating and compute RMSE".  n == 0: predict the
  * registered test set with the current factors, fold the prediction into the
  * running mean as sweep t (if t > burn_in), and return the two RMSEs.

@@ -30,7 +30,7 @@ E_BUSY, E_TOOBIG, E_NOSAMPLES, E_NOTFOUND = -6, -7, -8, -9
 # Every symbol the C ABI exports (include/bpmf.h).
 EXPORTS = [
     "bpmf_default_params", "bpmf_create", "bpmf_sample_hyper", "bpmf_update_side",
-    "bpmf_run_sweeps", "bpmf_predict", "bpmf_get_factor", "bpmf_set_factor",
+    "bpmf_run_sweeps", "bpmf_profile_sweeps", "bpmf_predict", "bpmf_get_factor", "bpmf_set_factor",
     "bpmf_get_factor_f64", "bpmf_set_factor_f64", "bpmf_get_hyper", "bpmf_set_hyper",
     "bpmf_get_csc", "bpmf_get_plan", "bpmf_mean_rating", "bpmf_synchronize",
     "bpmf_last_time_ms", "bpmf_last_error", "bpmf_destroy",
@@ -81,6 +81,7 @@ def lib() -> ctypes.CDLL:
         L.bpmf_update_side.argtypes = [P, i32, u32]
         L.bpmf_run_sweeps.argtypes = [P, u32, u32, P, P]
         L.bpmf_predict.argtypes = [P, u32, i64, P, P, P, P, P]
+        L.bpmf_profile_sweeps.argtypes = [P, u32, u32, P]
         for name in ("bpmf_get_factor", "bpmf_set_factor", "bpmf_get_factor_f64",
                      "bpmf_set_factor_f64"):
             getattr(L, name).argtypes = [P, i32, P]
@@ -190,6 +191,14 @@ class Sampler:
         last = np.zeros(n)
         self._check(lib().bpmf_run_sweeps(self._ctx, t0, n, _ptr(avg), _ptr(last)))
         return avg, last
+
+    def profile_sweeps(self, t0, n):
+        """Eager sweeps with per-phase HIP events; returns the mean ms per sweep
+        of (hyper V, rows V, split-finish V, hyper U, rows U, split-finish U,
+        predict)."""
+        out = np.zeros(7)
+        self._check(lib().bpmf_profile_sweeps(self._ctx, t0, n, _ptr(out)))
+        return out
 
     def predict_test(self, t):
         a = ctypes.c_double()

@@ -15,8 +15,8 @@
 #include "internal.h"
 
 namespace bpmf {
-hipError_t launch_row_generic(bpmf_ctx *c, int side_id, hipStream_t s);
-hipError_t launch_row_fast(bpmf_ctx *c, int side_id, hipStream_t s, bool *handled);
+hipError_t launch_row_generic(bpmf_ctx *c, int side_id, hipStream_t s, int stage);
+hipError_t launch_row_fast(bpmf_ctx *c, int side_id, hipStream_t s, int stage, bool *handled);
 hipError_t prepare_kernels(bpmf_ctx *c);
 }  // namespace bpmf
 
@@ -140,15 +140,44 @@ void plan_side(const std::vector<int64_t> &ptr, int64_t rows, int64_t split, int
 
 size_t elem_bytes(const bpmf_ctx *c) { return c->prec == 0 ? sizeof(double) : sizeof(float); }
 
-hipError_t enqueue_update(bpmf_ctx *c, int side_id, hipStream_t s)
+// Stage 0: the row kernel over all work items (whole rows and segments of
+// split rows).  Stage 1: finishing the split rows, then the BF16 copy.
+hipError_t enqueue_update_stage(bpmf_ctx *c, int side_id, hipStream_t s, int stage)
 {
     bool handled = false;
-    hipError_t e = launch_row_fast(c, side_id, s, &handled);
+    hipError_t e = launch_row_fast(c, side_id, s, stage, &handled);
     if (e != hipSuccess) return e;
-    if (!handled) e = launch_row_generic(c, side_id, s);
+    if (!handled) e = launch_row_generic(c, side_id, s, stage);
     if (e != hipSuccess) return e;
-    if (c->prec == 2) e = launch_to_bf16(c, side_id, s);
+    if (stage == 1 && c->prec == 2) e = launch_to_bf16(c, side_id, s);
     return e;
+}
+
+hipError_t enqueue_update(bpmf_ctx *c, int side_id, hipStream_t s)
+{
+    hipError_t e = enqueue_update_stage(c, side_id, s, 0);
+    if (e != hipSuccess) return e;
+    return enqueue_update_stage(c, side_id, s, 1);
+}
+
+// Algorithm 1 once, eagerly, with an event after every phase:
+// [hyper V][rows V][split V][hyper U][rows U][split U][predict] -> 7 intervals.
+hipError_t enqueue_sweep_profiled(bpmf_ctx *c, hipStream_t s, hipEvent_t *ev)
+{
+    hipError_t e;
+    if ((e = launch_advance_t(c->ctr, s)) != hipSuccess) return e;
+    if ((e = hipEventRecord(ev[0], s)) != hipSuccess) return e;
+    int q = 1;
+    for (int side : {BPMF_SIDE_V, BPMF_SIDE_U}) {
+        if ((e = launch_hyper(c, side, s)) != hipSuccess) return e;
+        if ((e = hipEventRecord(ev[q++], s)) != hipSuccess) return e;
+        if ((e = enqueue_update_stage(c, side, s, 0)) != hipSuccess) return e;
+        if ((e = hipEventRecord(ev[q++], s)) != hipSuccess) return e;
+        if ((e = enqueue_update_stage(c, side, s, 1)) != hipSuccess) return e;
+        if ((e = hipEventRecord(ev[q++], s)) != hipSuccess) return e;
+    }
+    if ((e = launch_predict_test(c, s)) != hipSuccess) return e;
+    return hipEventRecord(ev[7], s);
 }
 
 hipError_t enqueue_sweep(bpmf_ctx *c, hipStream_t s)
@@ -164,17 +193,8 @@ hipError_t enqueue_sweep(bpmf_ctx *c, hipStream_t s)
 
 void free_side(Side &s)
 {
-    hipFree(s.ptr);
-    hipFree(s.nbr);
-    hipFree(s.rc);
-    hipFree(s.X);
-    hipFree(s.Xbf);
-    hipFree(s.mu);
-    hipFree(s.Lam);
-    hipFree(s.Lam_w);
-    hipFree(s.Lmu_w);
-    hipFree(s.items);
-    hipFree(s.fin);
+    void *ps[] = {s.ptr, s.nbr, s.rc, s.X, s.Xbf, s.mu, s.Lam, s.Lam_w, s.Lmu_w, s.items, s.fin};
+    for (void *p : ps) (void)hipFree(p);
 }
 
 }  // namespace
@@ -288,7 +308,7 @@ int bpmf_create(int64_t M, int64_t N, const int64_t *csr_ptr, const int32_t *csr
     c->nu0 = p->nu0;
     c->seed = p->seed;
     c->burn_in = p->burn_in;
-    c->split_threshold = p->split_threshold > 0 ? p->split_threshold : 4096;
+    c->split_threshold = p->split_threshold > 0 ? p->split_threshold : 2048;
     double rbar = 0.0;
     if (p->center) {
         double s = 0.0;
@@ -347,7 +367,8 @@ int bpmf_create(int64_t M, int64_t N, const int64_t *csr_ptr, const int32_t *csr
             }
             std::vector<RowItem> items;
             std::vector<FinishItem> fin;
-            plan_side(*ptrs[sid], sd.rows, c->split_threshold, 2048, sd.perm, sd.n_split, items,
+            plan_side(*ptrs[sid], sd.rows, c->split_threshold,
+                      std::max<int64_t>(128, c->split_threshold / 2), sd.perm, sd.n_split, items,
                       fin, sd.n_slots);
             sd.n_items = (int64_t)items.size();
             sd.n_fin = (int64_t)fin.size();
@@ -417,29 +438,16 @@ error:
 void bpmf_destroy(bpmf_ctx *c)
 {
     if (!c) return;
-    if (c->stream) hipStreamSynchronize(c->stream);
-    if (c->graph) hipGraphExecDestroy(c->graph);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    if (c->graph) (void)hipGraphExecDestroy(c->graph);
     for (auto &s : c->side) free_side(s);
-    hipFree(c->d_mu0);
-    hipFree(c->d_W0inv);
-    hipFree(c->test_row);
-    hipFree(c->test_col);
-    hipFree(c->test_val);
-    hipFree(c->pred_sum);
-    hipFree(c->rmse_part);
-    hipFree(c->rmse_hist);
-    hipFree(c->hyp_part);
-    hipFree(c->hyp_stats);
-    hipFree(c->hyp_scratch);
-    hipFree(c->hyp_status);
-    hipFree(c->part);
-    hipFree(c->ctr);
-    hipFree(c->q_row);
-    hipFree(c->q_col);
-    hipFree(c->q_out);
-    if (c->ev0) hipEventDestroy(c->ev0);
-    if (c->ev1) hipEventDestroy(c->ev1);
-    if (c->stream) hipStreamDestroy(c->stream);
+    void *ps[] = {c->d_mu0, c->d_W0inv, c->test_row, c->test_col, c->test_val, c->pred_sum,
+                  c->rmse_part, c->rmse_hist, c->hyp_part, c->hyp_stats, c->hyp_scratch,
+                  c->hyp_status, c->part, c->ctr, c->q_row, c->q_col, c->q_out};
+    for (void *p : ps) (void)hipFree(p);
+    if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->ev1) (void)hipEventDestroy(c->ev1);
+    if (c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
 
@@ -539,6 +547,35 @@ int bpmf_run_sweeps(bpmf_ctx *c, uint32_t t0, uint32_t n, double *rmse_avg, doub
         if (rmse_last) rmse_last[i] = h[2 * i + 1];
     }
     return BPMF_OK;
+}
+
+int bpmf_profile_sweeps(bpmf_ctx *c, uint32_t t0, uint32_t n, double *phase_ms)
+{
+    STICKY(c);
+    if (n == 0 || !phase_ms) return fail(c, BPMF_E_INVAL, "need n > 0 and an output array");
+    if (t0 == 0) return fail(c, BPMF_E_INVAL, "sweeps are numbered from 1");
+    if ((int64_t)n > c->hist_cap) return fail(c, BPMF_E_INVAL, "n exceeds the RMSE history (run bpmf_run_sweeps with n first)");
+    hipEvent_t ev[8] = {};
+    for (auto &e : ev) HIPCK(c, hipEventCreate(&e));
+    double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+    int rc = BPMF_OK;
+    if (launch_set_counter(c->ctr, 0, t0 - 1, c->stream) != hipSuccess ||
+        launch_set_counter(c->ctr, 1, t0, c->stream) != hipSuccess)
+        rc = fail(c, BPMF_E_DEVICE, "counter launch failed");
+    for (uint32_t i = 0; i < n && rc == BPMF_OK; ++i) {
+        hipError_t e = enqueue_sweep_profiled(c, c->stream, ev);
+        if (e == hipSuccess) e = hipEventSynchronize(ev[7]);
+        for (int q = 0; q < 7 && e == hipSuccess; ++q) {
+            float ms = 0;
+            e = hipEventElapsedTime(&ms, ev[q], ev[q + 1]);
+            acc[q] += ms;
+        }
+        if (e != hipSuccess) rc = fail(c, BPMF_E_DEVICE, "profiled sweep: %s", hipGetErrorString(e));
+    }
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    if (rc != BPMF_OK) return rc;
+    for (int q = 0; q < 7; ++q) phase_ms[q] = acc[q] / n;
+    return check_hyper_status(c);
 }
 
 int bpmf_predict(bpmf_ctx *c, uint32_t t, int64_t n, const int32_t *row, const int32_t *col,
