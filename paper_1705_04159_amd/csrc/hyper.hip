@@ -12,9 +12,20 @@
 // A_kk = sqrt(chi2(nu* - k)), k = 0..K-1, and N(0,1) below the diagonal in
 // row-major order), then mu = mu* + chol(beta* Lambda)^-T z.
 //
-// Three launches: per-block FP64 moment sums over row chunks, an
-// entry-parallel fixed-order reduction of the block sums, and one workgroup
-// for the K x K algebra.  S is formed as sum x x^T - n xbar xbar^T.
+// Three launches: per-block FP64 moment sums over row chunks (S is formed as
+// sum x x^T - n xbar xbar^T), a fixed-order reduction of the block sums (one
+// wavefront per entry), and one workgroup for the K x K algebra.  The
+// algebra avoids forming W* and two of the three factorisations:
+//   * L_W is obtained from one Cholesky of the index-reversed W*^-1:
+//     J W*^-1 J = C C^T gives W*^-1 = (J C J)(J C J)^T with J C J upper
+//     triangular, hence W* = (J C J)^-T (J C J)^-1 and, by uniqueness of the
+//     Cholesky factor, L_W = J C^-T J, i.e. L_W[i][j] = (C^-1)[K-1-j][K-1-i];
+//   * B = L_W A is lower triangular with a positive diagonal, so it is the
+//     Cholesky factor of Lambda, and chol(beta* Lambda) = sqrt(beta*) B:
+//     mu = mu* + B^-T z / sqrt(beta*).
+// All K x K matrices are packed lower triangles in LDS when they fit.
+#include <algorithm>
+
 #include "internal.h"
 #include "rng_device.h"
 
@@ -22,7 +33,6 @@ namespace bpmf {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kRowsPerTile = 32;
 
 __device__ __forceinline__ int pk(int i, int j) { return i * (i + 1) / 2 + j; }
 
@@ -38,71 +48,73 @@ __device__ __forceinline__ void tri_index(int e, int &i, int &j)
 __device__ __forceinline__ double as_f64(float v) { return (double)v; }
 __device__ __forceinline__ double as_f64(double v) { return v; }
 
-// Block b sums rows [b*chunk, min(rows, (b+1)*chunk)):  entries e < K are
-// sum x_e, entries K + pk(i,j) are sum x_i x_j.
-template <typename XT>
+// Block b sums rows [b*chunk, min(rows, (b+1)*chunk)).  Entry e < K is
+// sum x_e (taken as x_e * 1 with a constant 1 appended to each staged row),
+// entry K + pk(i,j) is sum x_i x_j.  NE = entries per thread.
+template <int NE, typename XT>
 __global__ __launch_bounds__(kThreads) void hyper_moments(int K, const XT *__restrict__ X, int ld,
                                                           int64_t rows, int64_t chunk,
-                                                          double *__restrict__ part)
+                                                          int tile_rows, double *__restrict__ part)
 {
     extern __shared__ __align__(16) char smem_raw[];
-    double *tileX = (double *)smem_raw;  // kRowsPerTile * K
+    double *tileX = (double *)smem_raw;  // tile_rows * (K + 1)
     const int tid = threadIdx.x;
+    const int KA = K + 1;
     const int E = K + K * (K + 1) / 2;
     const int64_t r0 = (int64_t)blockIdx.x * chunk;
     const int64_t r1 = min<int64_t>(rows, r0 + chunk);
-    constexpr int kMaxE = (128 + 128 * 129 / 2 + kThreads - 1) / kThreads;  // 33
-    double acc[kMaxE];
-    int ia[kMaxE], ja[kMaxE];
+    double acc[NE];
+    int ia[NE], ja[NE];
 #pragma unroll
-    for (int m = 0; m < kMaxE; ++m) {
+    for (int m = 0; m < NE; ++m) {
         acc[m] = 0.0;
-        int e = tid + m * kThreads, i = -1, j = -1;
+        int e = tid + m * kThreads, i = 0, j = K;
         if (e < K) {
             i = e;
-            j = -1;
         } else if (e < E) {
             tri_index(e - K, i, j);
         }
         ia[m] = i;
         ja[m] = j;
     }
-    for (int64_t base = r0; base < r1; base += kRowsPerTile) {
-        int cnt = (int)min<int64_t>(kRowsPerTile, r1 - base);
-        for (int q = tid; q < cnt * K; q += kThreads) {
-            int rr = q / K, k = q - rr * K;
-            tileX[q] = as_f64(X[(size_t)(base + rr) * ld + k]);
+    for (int64_t base = r0; base < r1; base += tile_rows) {
+        const int cnt = (int)min<int64_t>(tile_rows, r1 - base);
+        for (int q = tid; q < cnt * KA; q += kThreads) {
+            const int rr = q / KA, k = q - rr * KA;
+            tileX[q] = k < K ? as_f64(X[(size_t)(base + rr) * ld + k]) : 1.0;
         }
         __syncthreads();
         for (int rr = 0; rr < cnt; ++rr) {
-            const double *x = tileX + rr * K;
+            const double *x = tileX + rr * KA;
 #pragma unroll
-            for (int m = 0; m < kMaxE; ++m) {
-                if (ia[m] >= 0) acc[m] += ja[m] < 0 ? x[ia[m]] : x[ia[m]] * x[ja[m]];
-            }
+            for (int m = 0; m < NE; ++m) acc[m] += x[ia[m]] * x[ja[m]];
         }
         __syncthreads();
     }
 #pragma unroll
-    for (int m = 0; m < kMaxE; ++m) {
-        int e = tid + m * kThreads;
+    for (int m = 0; m < NE; ++m) {
+        const int e = tid + m * kThreads;
         if (e < E) part[(size_t)blockIdx.x * E + e] = acc[m];
     }
 }
 
-// stats[e] = sum over blocks b (in order) of part[b][e].
-__global__ void hyper_reduce(int E, int nblk, const double *__restrict__ part,
-                             double *__restrict__ stats)
+// stats[e] = sum over blocks of part[b][e]: one wavefront per entry, lane l
+// sums blocks l, l+64, ... in order, then a fixed butterfly across lanes.
+__global__ __launch_bounds__(256) void hyper_reduce(int E, int nblk, const double *__restrict__ part,
+                                                   double *__restrict__ stats)
 {
-    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int e = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (e >= E) return;
     double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += part[(size_t)b * E + e];
-    stats[e] = s;
+    for (int b = lane; b < nblk; b += 64) s += part[(size_t)b * E + e];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (lane == 0) stats[e] = s;
 }
 
-// In-place Cholesky of a packed lower K x K matrix in LDS by the whole
-// workgroup.  Clears *ok on a non-positive pivot.
+// In-place Cholesky of a packed lower K x K matrix by the whole workgroup.
+// Clears *ok on a non-positive pivot.
 __device__ void chol_packed(int K, double *P, int *ok)
 {
     const int tid = threadIdx.x;
@@ -116,16 +128,42 @@ __device__ void chol_packed(int K, double *P, int *ok)
             P[pk(k, k)] = sqrt(d);
         }
         __syncthreads();
-        double dk = P[pk(k, k)];
+        const double dk = P[pk(k, k)];
         for (int i = k + 1 + tid; i < K; i += kThreads) P[pk(i, k)] /= dk;
         __syncthreads();
-        int m = K - k - 1;
-        int n = m * (m + 1) / 2;
+        const int m = K - k - 1;
+        const int n = m * (m + 1) / 2;
         for (int q = tid; q < n; q += kThreads) {
             int ii, jj;
             tri_index(q, ii, jj);
-            int i = k + 1 + ii, j = k + 1 + jj;
+            const int i = k + 1 + ii, j = k + 1 + jj;
             P[pk(i, j)] -= P[pk(i, k)] * P[pk(j, k)];
+        }
+        __syncthreads();
+    }
+}
+
+// X = C^-1 for a packed lower C (X packed lower, distinct storage):
+// forward substitution on the identity, one pivot row per step.
+__device__ void tri_inverse_packed(int K, const double *C, double *Xp)
+{
+    const int tid = threadIdx.x;
+    const int KK2 = K * (K + 1) / 2;
+    for (int e = tid; e < KK2; e += kThreads) {
+        int i, j;
+        tri_index(e, i, j);
+        Xp[e] = i == j ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    for (int k = 0; k < K; ++k) {
+        const double inv = 1.0 / C[pk(k, k)];
+        for (int j = tid; j <= k; j += kThreads) Xp[pk(k, j)] *= inv;  // row k final
+        __syncthreads();
+        // rows i > k: X[i][j] -= C[i][k] X[k][j], j <= k
+        const int rows = K - k - 1, cols = k + 1;
+        for (int q = tid; q < rows * cols; q += kThreads) {
+            const int i = k + 1 + q / cols, j = q - (q / cols) * cols;
+            Xp[pk(i, j)] -= C[pk(i, k)] * Xp[pk(k, j)];
         }
         __syncthreads();
     }
@@ -135,17 +173,20 @@ template <typename T>
 __global__ __launch_bounds__(kThreads) void hyper_draw(
     int K, int64_t n, const double *__restrict__ stats, const double *__restrict__ mu0,
     const double *__restrict__ W0inv, double beta0, double nu0, uint64_t seed, uint32_t stream,
-    const uint32_t *__restrict__ ctr, double *__restrict__ G0, double *__restrict__ G1,
+    const uint32_t *__restrict__ ctr, double *__restrict__ gbuf, int n_lds_bufs,
     double *__restrict__ mu_out, double *__restrict__ Lam_out, T *__restrict__ Lam_w,
     T *__restrict__ Lmu_w, int *__restrict__ status)
 {
     extern __shared__ __align__(16) char smem_raw[];
     const int KK2 = K * (K + 1) / 2;
-    double *Mp = (double *)smem_raw;  // packed lower
-    double *xbar = Mp + KK2;
-    double *mus = xbar + K;
-    double *zv = mus + K;
-    double *mu = zv + K;
+    double *vec = (double *)smem_raw;  // xbar, mu*, z, mu  (4K)
+    double *xbar = vec, *mus = vec + K, *zv = vec + 2 * K, *mu = vec + 3 * K;
+    double *buf[3];
+    for (int q = 0; q < 3; ++q)
+        buf[q] = q < n_lds_bufs ? vec + 4 * K + (size_t)q * KK2 : gbuf + (size_t)q * KK2;
+    double *Cm = buf[0];  // reversed W*^-1, then its Cholesky factor C, then A
+    double *Ci = buf[1];  // C^-1
+    double *Bm = buf[2];  // B = L_W A
     __shared__ int ok;
     const int tid = threadIdx.x;
     const uint32_t t = ctr[0];
@@ -159,104 +200,85 @@ __global__ __launch_bounds__(kThreads) void hyper_draw(
         mus[k] = (beta0 * mu0[k] + dn * xbar[k]) / beta_s;
     }
     __syncthreads();
-    // W*^-1 (packed lower)
-    for (int e = tid; e < KK2; e += kThreads) {
-        int i, j;
-        tri_index(e, i, j);
-        double S = stats[K + e] - dn * xbar[i] * xbar[j];
-        Mp[e] = W0inv[i * K + j] + S + shrink * (xbar[i] - mu0[i]) * (xbar[j] - mu0[j]);
-    }
-    __syncthreads();
-    chol_packed(K, Mp, &ok);
-    // G0 = R^-1 (lower), one column per thread
-    for (int j = tid; j < K; j += kThreads) {
-        for (int i = 0; i < j; ++i) G0[i * K + j] = 0.0;
-        G0[j * K + j] = 1.0 / Mp[pk(j, j)];
-        for (int i = j + 1; i < K; ++i) {
-            double s = 0.0;
-            for (int k = j; k < i; ++k) s += Mp[pk(i, k)] * G0[k * K + j];
-            G0[i * K + j] = -s / Mp[pk(i, i)];
-        }
-    }
-    __syncthreads();
-    // W* = R^-T R^-1 into Mp
+    // J W*^-1 J, packed: entry (i, j), i >= j, is W*^-1[K-1-j][K-1-i]
     for (int e = tid; e < KK2; e += kThreads) {
         int a, b;
-        tri_index(e, a, b);  // a >= b
-        double s = 0.0;
-        for (int k = a; k < K; ++k) s += G0[k * K + a] * G0[k * K + b];
-        Mp[e] = s;
+        tri_index(e, a, b);  // W*^-1 entry (a, b), a >= b
+        const double S = stats[K + e] - dn * xbar[a] * xbar[b];
+        const double w = W0inv[a * K + b] + S + shrink * (xbar[a] - mu0[a]) * (xbar[b] - mu0[b]);
+        Cm[pk(K - 1 - b, K - 1 - a)] = w;
     }
     __syncthreads();
-    chol_packed(K, Mp, &ok);  // Mp = L_W
-    // Bartlett factor A into G1 (full, upper zero)
-    for (int q = tid; q < K * K; q += kThreads) G1[q] = 0.0;
+    chol_packed(K, Cm, &ok);
+    tri_inverse_packed(K, Cm, Ci);
+    // Bartlett factor A (reuses Cm)
+    for (int e = tid; e < KK2; e += kThreads) Cm[e] = 0.0;
     __syncthreads();
     for (int k = tid; k < K; k += kThreads)
-        G1[k * K + k] = sqrt(chi_square(seed, stream, t, (uint32_t)k, nu_s - (double)k, &ok));
+        Cm[pk(k, k)] = sqrt(chi_square(seed, stream, t, (uint32_t)k, nu_s - (double)k, &ok));
     const int n_low = K * (K - 1) / 2;
     for (int blk = tid; 4 * blk < n_low; blk += kThreads) {
         double z[4];
         normals_block(seed, (uint32_t)blk, t, stream, 1u, 0u, z);
         for (int l = 0; l < 4 && 4 * blk + l < n_low; ++l) {
-            int e = 4 * blk + l, r, c;
-            tri_index(e, r, c);  // e = r(r+1)/2 + c with c <= r: shift to strict lower
-            // strict-lower row-major index: e = r'(r'-1)/2 + c', r' = r + 1 when c <= r
-            G1[(r + 1) * K + c] = z[l];
+            int r, c;
+            tri_index(4 * blk + l, r, c);  // strict-lower row-major index = pk(r+1, c)
+            Cm[pk(r + 1, c)] = z[l];
         }
     }
     __syncthreads();
-    // B = L_W A into G0 (lower)
-    for (int q = tid; q < K * K; q += kThreads) {
-        int r = q / K, c = q - r * K;
-        double s = 0.0;
-        if (c <= r)
-            for (int m = c; m <= r; ++m) s += Mp[pk(r, m)] * G1[m * K + c];
-        G0[q] = s;
-    }
-    __syncthreads();
-    // Lambda = B B^T; Mp <- beta* Lambda (packed)
+    // B = L_W A, L_W[r][m] = C^-1[K-1-m][K-1-r]
     for (int e = tid; e < KK2; e += kThreads) {
         int r, c;
         tri_index(e, r, c);
         double s = 0.0;
-        for (int m = 0; m <= c; ++m) s += G0[r * K + m] * G0[c * K + m];
+        for (int m = c; m <= r; ++m) s += Ci[pk(K - 1 - m, K - 1 - r)] * Cm[pk(m, c)];
+        Bm[e] = s;
+    }
+    __syncthreads();
+    // Lambda = B B^T
+    for (int e = tid; e < KK2; e += kThreads) {
+        int r, c;
+        tri_index(e, r, c);
+        double s = 0.0;
+        for (int m = 0; m <= c; ++m) s += Bm[pk(r, m)] * Bm[pk(c, m)];
         Lam_out[r * K + c] = s;
         Lam_out[c * K + r] = s;
+        Lam_w[r * K + c] = (T)s;
+        Lam_w[c * K + r] = (T)s;
     }
-    __syncthreads();
-    for (int e = tid; e < KK2; e += kThreads) {
-        int r, c;
-        tri_index(e, r, c);
-        Mp[e] = beta_s * Lam_out[r * K + c];
-    }
-    __syncthreads();
-    chol_packed(K, Mp, &ok);
     for (int blk = tid; 4 * blk < K; blk += kThreads) {
         double z[4];
         normals_block(seed, (uint32_t)blk, t, stream, 2u, 0u, z);
         for (int l = 0; l < 4 && 4 * blk + l < K; ++l) zv[4 * blk + l] = z[l];
     }
     __syncthreads();
-    // x = L^-T z (column oriented), in zv
+    // x = B^-T z (column oriented), in zv
     for (int i = K - 1; i >= 0; --i) {
-        if (tid == 0) zv[i] /= Mp[pk(i, i)];
+        if (tid == 0) zv[i] /= Bm[pk(i, i)];
         __syncthreads();
-        double xi = zv[i];
-        for (int j = tid; j < i; j += kThreads) zv[j] -= Mp[pk(i, j)] * xi;
+        const double xi = zv[i];
+        for (int j = tid; j < i; j += kThreads) zv[j] -= Bm[pk(i, j)] * xi;
         __syncthreads();
     }
+    const double rs = 1.0 / sqrt(beta_s);
     for (int k = tid; k < K; k += kThreads) {
-        mu[k] = mus[k] + zv[k];
+        mu[k] = mus[k] + zv[k] * rs;
         mu_out[k] = mu[k];
+    }
+    __syncthreads();
+    // Lambda mu from the packed factor: Lambda mu = B (B^T mu)
+    for (int i = tid; i < K; i += kThreads) {
+        double s = 0.0;
+        for (int j = i; j < K; ++j) s += Bm[pk(j, i)] * mu[j];
+        zv[i] = s;  // B^T mu
     }
     __syncthreads();
     for (int i = tid; i < K; i += kThreads) {
         double s = 0.0;
-        for (int j = 0; j < K; ++j) s += Lam_out[i * K + j] * mu[j];
+        for (int j = 0; j <= i; ++j) s += Bm[pk(i, j)] * zv[j];
         Lmu_w[i] = (T)s;
     }
-    for (int q = tid; q < K * K; q += kThreads) Lam_w[q] = (T)Lam_out[q];
     if (tid == 0 && !ok) *status = 0;
 }
 
@@ -274,6 +296,30 @@ __global__ void prior_to_working(int K, const double *__restrict__ mu, const dou
     for (int q = tid; q < K * K; q += blockDim.x) Lam_w[q] = (T)Lam[q];
 }
 
+template <int NE>
+void launch_moments(bpmf_ctx *c, const Side &sd, int used, int64_t chunk, hipStream_t s)
+{
+    const int tile_rows = (int)std::min<size_t>(64, 49152 / (sizeof(double) * (c->K + 1)));
+    const size_t lds = sizeof(double) * tile_rows * (c->K + 1);
+    if (c->prec == 0)
+        hipLaunchKernelGGL((hyper_moments<NE, double>), dim3(used), dim3(kThreads), lds, s, c->K,
+                           (const double *)sd.X, c->ld, sd.rows, chunk, tile_rows, c->hyp_part);
+    else
+        hipLaunchKernelGGL((hyper_moments<NE, float>), dim3(used), dim3(kThreads), lds, s, c->K,
+                           (const float *)sd.X, c->ld, sd.rows, chunk, tile_rows, c->hyp_part);
+}
+
+int lds_buffers(int K, int lds_max)
+{
+    const size_t KK2 = (size_t)K * (K + 1) / 2;
+    const size_t base = sizeof(double) * 4 * (size_t)K;
+    int nb = 3;
+    while (nb > 0 && base + sizeof(double) * nb * KK2 > (size_t)lds_max) --nb;
+    return nb;
+}
+
+size_t draw_lds(int K, int nb) { return sizeof(double) * (4 * (size_t)K + nb * (size_t)K * (K + 1) / 2); }
+
 }  // namespace
 
 hipError_t launch_hyper(bpmf_ctx *c, int side_id, hipStream_t s)
@@ -281,46 +327,53 @@ hipError_t launch_hyper(bpmf_ctx *c, int side_id, hipStream_t s)
     Side &sd = c->side[side_id];
     const int K = c->K;
     const int E = K + K * (K + 1) / 2;
-    int64_t rows = sd.rows;
-    int nblk = c->hyp_blocks;
+    const int64_t rows = sd.rows;
+    const int nblk = c->hyp_blocks;
     int64_t chunk = (rows + nblk - 1) / nblk;
     if (chunk < 1) chunk = 1;
     int used = (int)((rows + chunk - 1) / chunk);
     if (used < 1) used = 1;
-    size_t lds1 = sizeof(double) * kRowsPerTile * K;
-    if (c->prec == 0)
-        hipLaunchKernelGGL((hyper_moments<double>), dim3(used), dim3(kThreads), lds1, s, K,
-                           (const double *)sd.X, c->ld, rows, chunk, c->hyp_part);
-    else
-        hipLaunchKernelGGL((hyper_moments<float>), dim3(used), dim3(kThreads), lds1, s, K,
-                           (const float *)sd.X, c->ld, rows, chunk, c->hyp_part);
-    hipLaunchKernelGGL(hyper_reduce, dim3((E + 255) / 256), dim3(256), 0, s, E, used, c->hyp_part,
+    const int ne = (E + kThreads - 1) / kThreads;
+    if (ne <= 3) launch_moments<3>(c, sd, used, chunk, s);
+    else if (ne <= 9) launch_moments<9>(c, sd, used, chunk, s);
+    else if (ne <= 21) launch_moments<21>(c, sd, used, chunk, s);
+    else launch_moments<33>(c, sd, used, chunk, s);
+    hipLaunchKernelGGL(hyper_reduce, dim3((E + 3) / 4), dim3(256), 0, s, E, used, c->hyp_part,
                        c->hyp_stats);
-    size_t lds2 = sizeof(double) * ((size_t)K * (K + 1) / 2 + 4 * (size_t)K);
-    double *G0 = c->hyp_scratch, *G1 = G0 + (size_t)K * K;
+    const int nb = lds_buffers(K, c->hyp_lds_max);
+    const size_t lds2 = draw_lds(K, nb);
     if (c->prec == 0)
         hipLaunchKernelGGL((hyper_draw<double>), dim3(1), dim3(kThreads), lds2, s, K, rows,
                            c->hyp_stats, c->d_mu0, c->d_W0inv, c->beta0, c->nu0, c->seed,
-                           sd.stream_hyp, c->ctr, G0, G1, sd.mu, sd.Lam, (double *)sd.Lam_w,
-                           (double *)sd.Lmu_w, c->hyp_status);
+                           sd.stream_hyp, c->ctr, c->hyp_scratch, nb, sd.mu, sd.Lam,
+                           (double *)sd.Lam_w, (double *)sd.Lmu_w, c->hyp_status);
     else
         hipLaunchKernelGGL((hyper_draw<float>), dim3(1), dim3(kThreads), lds2, s, K, rows,
                            c->hyp_stats, c->d_mu0, c->d_W0inv, c->beta0, c->nu0, c->seed,
-                           sd.stream_hyp, c->ctr, G0, G1, sd.mu, sd.Lam, (float *)sd.Lam_w,
-                           (float *)sd.Lmu_w, c->hyp_status);
+                           sd.stream_hyp, c->ctr, c->hyp_scratch, nb, sd.mu, sd.Lam,
+                           (float *)sd.Lam_w, (float *)sd.Lmu_w, c->hyp_status);
     return hipGetLastError();
 }
 
 hipError_t prepare_hyper(bpmf_ctx *c)
 {
-    const int K = c->K;
-    size_t lds2 = sizeof(double) * ((size_t)K * (K + 1) / 2 + 4 * (size_t)K);
-    if (lds2 <= 65536) return hipSuccess;
-    hipError_t e = hipFuncSetAttribute((const void *)hyper_draw<double>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds2);
+    int dev_max = 65536;
+    hipError_t e = hipDeviceGetAttribute(&dev_max, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device);
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void *)hyper_draw<float>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds2);
+    c->hyp_lds_max = dev_max;
+    const size_t need = draw_lds(c->K, lds_buffers(c->K, dev_max));
+    if (need > 65536) {
+        e = hipFuncSetAttribute((const void *)hyper_draw<double>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)need);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void *)hyper_draw<float>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)need);
+        if (e != hipSuccess) {  // keep the draw within the default limit
+            (void)hipGetLastError();
+            c->hyp_lds_max = 65536;
+        }
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_prior_to_working(bpmf_ctx *c, int side_id, hipStream_t s)

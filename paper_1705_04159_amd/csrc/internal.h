@@ -77,6 +77,7 @@ struct bpmf_ctx {
     double *hyp_stats = nullptr;  // [K + K(K+1)/2]
     double *hyp_scratch = nullptr;// [4 * K * K + 8 * K]
     int *hyp_status = nullptr;    // device flag: 1 = ok
+    int hyp_lds_max = 65536;      // LDS bytes the draw kernel may use
     // split partials
     void *part = nullptr;
     int64_t part_slots = 0;

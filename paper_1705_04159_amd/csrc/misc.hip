@@ -87,25 +87,38 @@ __global__ __launch_bounds__(256) void predict_test(
     }
 }
 
-// One block: sum the per-block partials in order, store the RMSEs of this
-// sweep in hist[slot], slot = t - t0, and count the sweep into the running
-// mean if t > burn_in.
-__global__ void predict_finalize(int nblk, int64_t n, const double *__restrict__ part,
-                                 uint32_t *__restrict__ ctr, int burn_in, double *__restrict__ hist,
-                                 int64_t hist_cap)
+// One block: sum the per-block partials (each thread a fixed strided subset,
+// then a fixed tree), store the RMSEs of this sweep in hist[slot],
+// slot = t - t0, and count the sweep into the running mean if t > burn_in.
+__global__ __launch_bounds__(256) void predict_finalize(int nblk, int64_t n,
+                                                        const double *__restrict__ part,
+                                                        uint32_t *__restrict__ ctr, int burn_in,
+                                                        double *__restrict__ hist, int64_t hist_cap)
 {
-    if (threadIdx.x != 0) return;
+    __shared__ double red[2][256];
+    const int tid = threadIdx.x;
     double sa = 0.0, sl = 0.0;
-    for (int b = 0; b < nblk; ++b) {
+    for (int b = tid; b < nblk; b += 256) {
         sa += part[2 * b];
         sl += part[2 * b + 1];
     }
+    red[0][tid] = sa;
+    red[1][tid] = sl;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w) {
+            red[0][tid] += red[0][tid + w];
+            red[1][tid] += red[1][tid + w];
+        }
+        __syncthreads();
+    }
+    if (tid != 0) return;
     const uint32_t t = ctr[0];
     int64_t slot = (int64_t)t - (int64_t)ctr[1];
     if (slot < 0 || slot >= hist_cap) slot = hist_cap - 1;
-    double dn = n > 0 ? (double)n : 1.0;
-    hist[2 * slot] = sqrt(sa / dn);
-    hist[2 * slot + 1] = sqrt(sl / dn);
+    const double dn = n > 0 ? (double)n : 1.0;
+    hist[2 * slot] = sqrt(red[0][0] / dn);
+    hist[2 * slot + 1] = sqrt(red[1][0] / dn);
     if ((int64_t)t > (int64_t)burn_in) ctr[2] += 1;
 }
 
@@ -173,7 +186,7 @@ hipError_t launch_predict_test(bpmf_ctx *c, hipStream_t s)
                            c->n_test, c->test_row, c->test_col, c->test_val,
                            (const float *)c->side[0].X, (const float *)c->side[1].X, c->rbar,
                            c->pred_sum, c->ctr, c->burn_in, c->rmse_part);
-    hipLaunchKernelGGL(predict_finalize, dim3(1), dim3(64), 0, s, nblk, c->n_test, c->rmse_part,
+    hipLaunchKernelGGL(predict_finalize, dim3(1), dim3(256), 0, s, nblk, c->n_test, c->rmse_part,
                        c->ctr, c->burn_in, c->rmse_hist, c->hist_cap);
     return hipGetLastError();
 }

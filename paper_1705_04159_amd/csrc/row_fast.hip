@@ -1,50 +1,96 @@
 // row_fast.hip -- matrix-core row update for FP32 factors, K <= 64.
 //
-// One wavefront per work item (a whole row, or a segment of a split row).
 // Per row (Algorithm 1's item body with BPMF's conditional):
 //   P = Lambda + alpha sum_j y_j y_j^T,  b = Lambda mu + alpha sum_j r'_j y_j,
 //   P = L L^T,  y = L^-1 b,  x = L^-T (y + z).
+//
+// Work items are whole rows or segments of split rows; a wavefront takes
+// RPW consecutive items (RPW = 64 / padded K: 4 for K <= 16, 2 for K <= 32,
+// 1 above).
 //
 // Gram: the neighbour rows are gathered straight from HBM/L2 into the
 // operand registers of v_mfma_f32_16x16x4_f32 -- lane l holds component
 // 16*bi + (l % 16) of the neighbour row of rating 4g + l / 16, which is at
 // once the A operand of block row bi and the B operand of block column bj --
 // so only the nb(nb+1)/2 lower 16x16 blocks of P are accumulated (nb =
-// ceil(K/16)), four ratings per instruction.  The rhs accumulates on the
-// VALU from the same registers.
+// ceil(K/16)), four ratings per instruction; the rhs accumulates on the VALU
+// from the same registers.  Loads are buffer loads with 32-bit offsets:
+// out-of-range offsets return 0, which masks the ragged tail and the padded
+// components without branches.  The gather is software-pipelined: ids of
+// chunk c+2 and rows of chunk c+1 are in flight while chunk c is multiplied.
 //
 // Cholesky: the accumulators go through LDS into a column-per-lane layout
-// (lane c holds column c of P, plus b as an extra row).  Right-looking
-// elimination without the square roots: at step k every lane c > k updates
-// its column with the pivot column broadcast by v_readlane, so the pivot
-// row/column never needs rescaling; the extra row carries b through the
-// elimination, which is the forward solve L^-1 b.  Each lane finally scales
-// its column by 1/sqrt(d_c); the back solve runs row by row with one
-// readlane per row.
+// (lane c of a row's lane group holds column c of P, plus b as an extra row).
+// Right-looking elimination without square roots: at step k every column
+// c > k subtracts its multiple of pivot column k, broadcast from lane k
+// (v_readlane with one row per wave, ds_swizzle within 32- or 16-lane groups
+// with several), so finished columns never need rescaling; the extra row
+// carries b through the elimination, which is the forward solve L^-1 b.
+// Each lane finally scales its column by 1/sqrt(d_c); the back solve runs
+// row by row with one broadcast per row.
 //
-// Noise: lane c draws normal c of the row (Philox4x32-10 block c/4) with a
+// Noise: lane c draws normal c of its row (Philox4x32-10 block c/4) with a
 // Box-Muller evaluated in FP32 (the log of u close to 1 is taken as
 // log1p(-(1-u)) so that no bits are lost).
+#include <type_traits>
+
 #include "internal.h"
 #include "rng_device.h"
 
 namespace bpmf {
 
 hipError_t prepare_hyper(bpmf_ctx *c);
-hipError_t launch_row_generic(bpmf_ctx *c, int side_id, hipStream_t s, int stage);
 
 namespace {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-constexpr int kUnroll = 8;  // groups of 4 ratings in flight per wave
+constexpr int kUnroll = 4;              // groups of 4 ratings per chunk
+constexpr int kChunk = 4 * kUnroll;     // ratings per pipeline chunk
+constexpr uint32_t kOOB = 0x40000000u;  // offset beyond every buffer read here
+
+template <int I, int N, typename F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for<I + 1, N>(f);
+    }
+}
 
 __device__ __forceinline__ int pk(int i, int j) { return i * (i + 1) / 2 + j; }
 
-// Value of x in lane `src` (a compile-time constant), bit-exact.
 __device__ __forceinline__ float readlane_f(float x, int src)
 {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), src));
+}
+
+// x from lane k of the caller's lane group (the whole wave for RPW = 1,
+// 32 lanes for RPW = 2, 16 lanes for RPW = 4).
+template <int RPW, int k>
+__device__ __forceinline__ float bcast(float x)
+{
+    if constexpr (RPW == 1)
+        return readlane_f(x, k);
+    else if constexpr (RPW == 2)
+        return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(x), k << 5));
+    else
+        return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(x), 0x10 | (k << 5)));
+}
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *p, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+__device__ __forceinline__ uint32_t buf_u32(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    return __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0);
+}
+
+__device__ __forceinline__ float buf_f32(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    return __uint_as_float(buf_u32(r, off));
 }
 
 // Standard normal from Philox words: the pair (wr, wa) gives radius and
@@ -53,152 +99,43 @@ __device__ __forceinline__ float bm_normal_f32(uint32_t wr, uint32_t wa, bool si
 {
     float lnu;
     if (wr < 0x80000000u) {
-        float u = ((float)wr + 0.5f) * 2.3283064365386963e-10f;
+        const float u = ((float)wr + 0.5f) * 2.3283064365386963e-10f;
         lnu = logf(u);
     } else {
-        float v = ((float)(0xFFFFFFFFu - wr) + 0.5f) * 2.3283064365386963e-10f;  // 1 - u
+        const float v = ((float)(0xFFFFFFFFu - wr) + 0.5f) * 2.3283064365386963e-10f;  // 1 - u
         lnu = log1pf(-v);
     }
-    float rho = sqrtf(-2.0f * lnu);
-    float ua = ((float)wa + 0.5f) * 2.3283064365386963e-10f;
+    const float rho = sqrtf(-2.0f * lnu);
+    const float ua = ((float)wa + 0.5f) * 2.3283064365386963e-10f;
     float sv, cv;
     sincospif(2.0f * ua, &sv, &cv);
     return rho * (sine ? sv : cv);
 }
 
-template <int NB, int WPB>
-__global__ __launch_bounds__(64 * WPB) void row_fast_f32(
-    int K, float alpha, const RowItem *__restrict__ items, int64_t n_items,
-    const int32_t *__restrict__ nbr, const float *__restrict__ rc, const float *__restrict__ Y,
-    int ldy, const float *__restrict__ Lam, const float *__restrict__ Lmu, float *__restrict__ X,
-    int ldx, float *__restrict__ part, uint64_t seed, uint32_t stream,
-    const uint32_t *__restrict__ ctr)
+// Factor and sample one row held column-per-lane: lane c of the group has
+// v[r] = P[r][c] for r < KP (identity outside the leading K x K block) and
+// v[KP] = b_c.  Returns x_c (meaningful for c < K).
+template <int KP, int RPW>
+__device__ __forceinline__ float chol_sample_column(float (&v)[KP + 1], int K, int c, uint32_t row,
+                                                    uint32_t t, uint64_t seed, uint32_t stream)
 {
-    constexpr int KP = 16 * NB;
-    constexpr int LDP = KP + 1;
-    constexpr int NBLK = NB * (NB + 1) / 2;
-    extern __shared__ float smem_f[];
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int64_t item_id = (int64_t)blockIdx.x * WPB + wave;
-    if (item_id >= n_items) return;
-    float *Ps = smem_f + wave * (KP * LDP + KP);
-    float *bs = Ps + KP * LDP;
-    const RowItem it = items[item_id];
-    const int col = lane & 15;
-    const int kq = lane >> 4;
-
-    floatx4 acc[NBLK];
-#pragma unroll
-    for (int q = 0; q < NBLK; ++q) acc[q] = floatx4{0.f, 0.f, 0.f, 0.f};
-    float bacc[NB];
-#pragma unroll
-    for (int bi = 0; bi < NB; ++bi) bacc[bi] = 0.f;
-
-    for (int64_t base = it.beg; base < it.end; base += 4 * kUnroll) {
-        float yv[kUnroll][NB];
-        float rv[kUnroll];
-#pragma unroll
-        for (int g = 0; g < kUnroll; ++g) {
-            const int64_t t = base + 4 * g + kq;
-            const bool ok = t < it.end;
-            const int j = ok ? nbr[t] : 0;
-            rv[g] = ok ? rc[t] : 0.f;
-            const float *yrow = Y + (size_t)j * ldy;
-#pragma unroll
-            for (int bi = 0; bi < NB; ++bi) {
-                const int comp = 16 * bi + col;
-                yv[g][bi] = (ok && comp < K) ? yrow[comp] : 0.f;
-            }
-        }
-#pragma unroll
-        for (int g = 0; g < kUnroll; ++g) {
-            int q = 0;
-#pragma unroll
-            for (int bi = 0; bi < NB; ++bi) {
-#pragma unroll
-                for (int bj = 0; bj <= bi; ++bj) {
-                    acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(yv[g][bi], yv[g][bj], acc[q], 0, 0, 0);
-                    ++q;
-                }
-                bacc[bi] += rv[g] * yv[g][bi];
-            }
-        }
-    }
-    // sum the rhs over the four rating slots of each 16-lane column
-#pragma unroll
-    for (int bi = 0; bi < NB; ++bi) {
-        bacc[bi] += __shfl_xor(bacc[bi], 16);
-        bacc[bi] += __shfl_xor(bacc[bi], 32);
-    }
-
-    const int KK2 = K * (K + 1) / 2;
-    if (it.slot >= 0) {  // segment of a split row: write the raw partial sums
-        float *dst = part + (size_t)it.slot * (KK2 + K);
-        int q = 0;
-#pragma unroll
-        for (int bi = 0; bi < NB; ++bi) {
-#pragma unroll
-            for (int bj = 0; bj <= bi; ++bj) {
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int r = 16 * bi + 4 * kq + v, c = 16 * bj + col;
-                    if (r < K && c <= r) dst[pk(r, c)] = acc[q][v];
-                }
-                ++q;
-            }
-            const int c = 16 * bi + col;
-            if (kq == 0 && c < K) dst[KK2 + c] = bacc[bi];
-        }
-        return;
-    }
-
-    // accumulators -> symmetric P in this wave's LDS
-    {
-        int q = 0;
-#pragma unroll
-        for (int bi = 0; bi < NB; ++bi) {
-#pragma unroll
-            for (int bj = 0; bj <= bi; ++bj) {
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int r = 16 * bi + 4 * kq + v, c = 16 * bj + col;
-                    Ps[r * LDP + c] = acc[q][v];
-                    if (bi != bj) Ps[c * LDP + r] = acc[q][v];
-                }
-                ++q;
-            }
-            if (kq == 0) bs[16 * bi + col] = bacc[bi];
-        }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-
-    // column-per-lane: v[r] = P[r][c] (r < KP), v[KP] = b_c; padding is identity
-    const int c = lane;
-    const bool live = c < K;
-    float v[KP + 1];
-#pragma unroll
-    for (int r = 0; r < KP; ++r) {
-        float p = (c < KP) ? Ps[r * LDP + (c < KP ? c : 0)] : 0.f;
-        v[r] = (live && r < K) ? alpha * p + Lam[r * K + c] : (r == c ? 1.f : 0.f);
-    }
-    v[KP] = live ? alpha * bs[c] + Lmu[c] : 0.f;
-
     float mydiag = 1.f;
-#pragma unroll
-    for (int k = 0; k < KP; ++k) {  // padded columns are identity: their steps change nothing
-        const float dk = readlane_f(v[k], k);
+    static_for<0, KP>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        const float dk = bcast<RPW, k>(v[k]);
         if (c == k) mydiag = dk;
-        const float f = v[k] * __builtin_amdgcn_rcpf(dk);
-        const bool upd = c > k;
-#pragma unroll
-        for (int r = k + 1; r <= KP; ++r) {
-            const float prk = readlane_f(v[r], k);
-            if (upd) v[r] -= f * prk;
-        }
-    }
+        // lanes c <= k hold finished columns: multiplier 0 leaves them unchanged
+        const float f = c > k ? v[k] * __builtin_amdgcn_rcpf(dk) : 0.f;
+        float prk[KP + 1];
+        static_for<k + 1, KP + 1>([&](auto rc) {
+            constexpr int r = decltype(rc)::value;
+            prk[r] = bcast<RPW, k>(v[r]);
+        });
+        static_for<k + 1, KP + 1>([&](auto rc) {
+            constexpr int r = decltype(rc)::value;
+            v[r] -= f * prk[r];
+        });
+    });
     const float inv_s = __builtin_amdgcn_rsqf(mydiag);
 #pragma unroll
     for (int r = 0; r < KP; ++r) v[r] *= inv_s;  // column c of L (rows > c)
@@ -206,35 +143,260 @@ __global__ __launch_bounds__(64 * WPB) void row_fast_f32(
     // w = L^-1 b + z
     float w = v[KP] * inv_s;
     {
-        const uint32_t t = ctr[0];
         const uint32_t blk = (uint32_t)(c >> 2);
-        const Block4 bl = philox4x32_10((uint32_t)it.row, t, (stream << 24) | blk, 0u, seed);
+        const Block4 bl = philox4x32_10(row, t, (stream << 24) | blk, 0u, seed);
         const int m = c & 3;
         const uint32_t wr = m < 2 ? bl.w0 : bl.w2;
         const uint32_t wa = m < 2 ? bl.w1 : bl.w3;
-        if (live) w += bm_normal_f32(wr, wa, (m & 1) != 0);
+        if (c < K) w += bm_normal_f32(wr, wa, (m & 1) != 0);
     }
-    // x = L^-T w, rows from the last
+    // x = L^-T w, rows from the last (padded rows carry w = 0, x = 0)
     float accx = 0.f, myx = 0.f;
-#pragma unroll
-    for (int r = KP - 1; r >= 0; --r) {  // padded rows carry w = 0, x = 0
-        const float xr_all = (w - accx) * inv_s;
-        const float xr = readlane_f(xr_all, r);
+    static_for<0, KP>([&](auto qc) {
+        constexpr int r = KP - 1 - decltype(qc)::value;
+        const float xr = bcast<RPW, r>((w - accx) * inv_s);
         if (c == r) myx = xr;
         if (c < r) accx += v[r] * xr;
+    });
+    return myx;
+}
+
+// Gram and rhs of one work item into the accumulators (whole wave).
+template <int NB>
+__device__ __forceinline__ void gram_item(const RowItem &it, const int32_t *__restrict__ nbr,
+                                          const float *__restrict__ rc,
+                                          __amdgpu_buffer_rsrc_t ysrc, uint32_t ldy4,
+                                          const uint32_t (&lane_off)[NB], int kq,
+                                          floatx4 (&acc)[NB * (NB + 1) / 2], float (&bacc)[NB])
+{
+    const uint32_t cnt = (uint32_t)(it.end - it.beg);
+    const __amdgpu_buffer_rsrc_t jsrc = make_rsrc(nbr + it.beg, cnt * 4u);
+    const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(rc + it.beg, cnt * 4u);
+    const uint32_t nchunk = (cnt + kChunk - 1) / kChunk;
+    uint32_t jb[2][kUnroll];
+    float yb[2][kUnroll][NB];
+    float rb[2][kUnroll];
+    auto load_ids = [&](int buf, uint32_t ch) {
+#pragma unroll
+        for (int g = 0; g < kUnroll; ++g) jb[buf][g] = buf_u32(jsrc, (ch * kChunk + 4 * g + kq) * 4u);
+    };
+    auto load_rows = [&](int buf, uint32_t ch) {
+#pragma unroll
+        for (int g = 0; g < kUnroll; ++g) {
+            const uint32_t t = ch * kChunk + 4 * g + kq;
+            rb[buf][g] = buf_f32(rsrc, t * 4u);  // 0 past the end
+            const uint32_t base = t < cnt ? jb[buf][g] * ldy4 : kOOB;
+#pragma unroll
+            for (int bi = 0; bi < NB; ++bi) yb[buf][g][bi] = buf_f32(ysrc, base + lane_off[bi]);
+        }
+    };
+    auto compute = [&](int buf) {
+#pragma unroll
+        for (int g = 0; g < kUnroll; ++g) {
+            int q = 0;
+#pragma unroll
+            for (int bi = 0; bi < NB; ++bi) {
+#pragma unroll
+                for (int bj = 0; bj <= bi; ++bj) {
+                    acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(yb[buf][g][bi], yb[buf][g][bj], acc[q], 0, 0, 0);
+                    ++q;
+                }
+                bacc[bi] += rb[buf][g] * yb[buf][g][bi];
+            }
+        }
+    };
+    if (nchunk == 0) return;
+    load_ids(0, 0);
+    load_ids(1, 1);
+    load_rows(0, 0);
+    for (uint32_t ch = 0; ch < nchunk; ch += 2) {
+        load_ids(0, ch + 2);
+        load_rows(1, ch + 1);
+        compute(0);
+        if (ch + 1 >= nchunk) break;
+        load_ids(1, ch + 3);
+        load_rows(0, ch + 2);
+        compute(1);
     }
-    if (live) X[(size_t)it.row * ldx + c] = myx;
+}
+
+template <int NB, int RPW, int WPB>
+__global__ __launch_bounds__(64 * WPB) void row_fast_f32(
+    int K, float alpha, const RowItem *__restrict__ items, int64_t n_items,
+    const int32_t *__restrict__ nbr, const float *__restrict__ rc, const float *__restrict__ Y,
+    int ldy, uint32_t y_bytes, const float *__restrict__ Lam, const float *__restrict__ Lmu,
+    float *__restrict__ X, int ldx, float *__restrict__ part, uint64_t seed, uint32_t stream,
+    const uint32_t *__restrict__ ctr)
+{
+    constexpr int KP = 16 * NB;
+    constexpr int LDP = KP + 1;
+    constexpr int NBLK = NB * (NB + 1) / 2;
+    constexpr int LPR = 64 / RPW;  // lanes per row in the factorisation
+    constexpr int REGION = KP * LDP + KP;
+    extern __shared__ float smem_f[];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int64_t first = ((int64_t)blockIdx.x * WPB + wave) * RPW;
+    if (first >= n_items) return;
+    float *Ps = smem_f + wave * RPW * REGION;
+    const int col = lane & 15;
+    const int kq = lane >> 4;
+    const __amdgpu_buffer_rsrc_t ysrc = make_rsrc(Y, y_bytes);
+    const uint32_t ldy4 = (uint32_t)ldy * 4u;
+    uint32_t lane_off[NB];
+#pragma unroll
+    for (int bi = 0; bi < NB; ++bi) lane_off[bi] = 16 * bi + col < K ? (16 * bi + col) * 4u : kOOB;
+    const int KK2 = K * (K + 1) / 2;
+
+    int row_of[RPW];
+    static_for<0, RPW>([&](auto hc) {
+        constexpr int h = decltype(hc)::value;
+        row_of[h] = -1;
+        const int64_t id = first + h;
+        if (id >= n_items) return;
+        const RowItem it = items[id];
+        floatx4 acc[NBLK];
+#pragma unroll
+        for (int q = 0; q < NBLK; ++q) acc[q] = floatx4{0.f, 0.f, 0.f, 0.f};
+        float bacc[NB];
+#pragma unroll
+        for (int bi = 0; bi < NB; ++bi) bacc[bi] = 0.f;
+        gram_item<NB>(it, nbr, rc, ysrc, ldy4, lane_off, kq, acc, bacc);
+        // sum the rhs over the four rating slots of each 16-lane column
+#pragma unroll
+        for (int bi = 0; bi < NB; ++bi) {
+            bacc[bi] += __shfl_xor(bacc[bi], 16);
+            bacc[bi] += __shfl_xor(bacc[bi], 32);
+        }
+        if (it.slot >= 0) {  // segment of a split row: raw partial sums
+            float *dst = part + (size_t)it.slot * (KK2 + K);
+            int q = 0;
+#pragma unroll
+            for (int bi = 0; bi < NB; ++bi) {
+#pragma unroll
+                for (int bj = 0; bj <= bi; ++bj) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int r = 16 * bi + 4 * kq + v, c = 16 * bj + col;
+                        if (r < K && c <= r) dst[pk(r, c)] = acc[q][v];
+                    }
+                    ++q;
+                }
+                const int c = 16 * bi + col;
+                if (kq == 0 && c < K) dst[KK2 + c] = bacc[bi];
+            }
+            return;
+        }
+        float *P = Ps + h * REGION;
+        int q = 0;
+#pragma unroll
+        for (int bi = 0; bi < NB; ++bi) {
+#pragma unroll
+            for (int bj = 0; bj <= bi; ++bj) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int r = 16 * bi + 4 * kq + v, c = 16 * bj + col;
+                    P[r * LDP + c] = acc[q][v];
+                    if (bi != bj) P[c * LDP + r] = acc[q][v];
+                }
+                ++q;
+            }
+            if (kq == 0) P[KP * LDP + 16 * bi + col] = bacc[bi];
+        }
+        row_of[h] = it.row;
+    });
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+    // column-per-lane within each lane group; groups without a full row
+    // factor the identity and write nothing
+    const int grp = lane / LPR;
+    const int c = lane & (LPR - 1);
+    int my_row = row_of[0];
+#pragma unroll
+    for (int h = 1; h < RPW; ++h)
+        if (grp == h) my_row = row_of[h];
+    const bool live = my_row >= 0 && c < K;
+    const float *P = Ps + grp * REGION;
+    const int cc = c < KP ? c : 0;
+    float v[KP + 1];
+#pragma unroll
+    for (int r = 0; r < KP; ++r)
+        v[r] = (live && r < K) ? alpha * P[r * LDP + cc] + Lam[r * K + c] : (r == c ? 1.f : 0.f);
+    v[KP] = live ? alpha * P[KP * LDP + cc] + Lmu[c] : 0.f;
+    const float x = chol_sample_column<KP, RPW>(v, K, c, (uint32_t)my_row, ctr[0], seed, stream);
+    if (live) X[(size_t)my_row * ldx + c] = x;
+}
+
+// Sum the partial slots of every split row into its first slot, in slot
+// order (one thread per (row, entry)).
+__global__ __launch_bounds__(256) void part_reduce(const FinishItem *__restrict__ fin, int E,
+                                                   float *__restrict__ part)
+{
+    const FinishItem f = fin[blockIdx.x];
+    const int e = blockIdx.y * 256 + threadIdx.x;
+    if (e >= E || f.count <= 1) return;
+    float *base = part + (size_t)f.first * E + e;
+    float s = 0.f;
+    for (int q = 0; q < f.count; ++q) s += base[(size_t)q * E];
+    base[0] = s;
+}
+
+// Split rows: lane c reads column c of the row's summed partial Gram (and
+// b_c), adds the prior, then factors and samples as in the row kernel.  One
+// wavefront per split row.
+template <int NB, int WPB>
+__global__ __launch_bounds__(64 * WPB) void row_finish_fast(
+    int K, float alpha, const FinishItem *__restrict__ fin, int64_t n_fin,
+    const float *__restrict__ part, const float *__restrict__ Lam, const float *__restrict__ Lmu,
+    float *__restrict__ X, int ldx, uint64_t seed, uint32_t stream,
+    const uint32_t *__restrict__ ctr)
+{
+    constexpr int KP = 16 * NB;
+    const int c = threadIdx.x & 63;
+    const int64_t fid = (int64_t)blockIdx.x * WPB + (threadIdx.x >> 6);
+    if (fid >= n_fin) return;
+    const FinishItem f = fin[fid];
+    const int KK2 = K * (K + 1) / 2;
+    const bool live = c < K;
+    const float *src = part + (size_t)f.first * (KK2 + K);
+    float v[KP + 1];
+#pragma unroll
+    for (int r = 0; r < KP; ++r)
+        v[r] = (live && r < K) ? alpha * src[r >= c ? pk(r, c) : pk(c, r)] + Lam[r * K + c]
+                               : (r == c ? 1.f : 0.f);
+    v[KP] = live ? alpha * src[KK2 + c] + Lmu[c] : 0.f;
+    const float x = chol_sample_column<KP, 1>(v, K, c, (uint32_t)f.row, ctr[0], seed, stream);
+    if (live) X[(size_t)f.row * ldx + c] = x;
 }
 
 template <int NB, int WPB>
+hipError_t launch_finish_f32(bpmf_ctx *c, Side &sd, hipStream_t s)
+{
+    if (sd.n_fin == 0) return hipSuccess;
+    const int E = c->K * (c->K + 1) / 2 + c->K;
+    hipLaunchKernelGGL(part_reduce, dim3((unsigned)sd.n_fin, (unsigned)((E + 255) / 256)), dim3(256),
+                       0, s, sd.fin, E, (float *)c->part);
+    const unsigned grid = (unsigned)((sd.n_fin + WPB - 1) / WPB);
+    hipLaunchKernelGGL((row_finish_fast<NB, WPB>), dim3(grid), dim3(64 * WPB), 0, s, c->K,
+                       (float)c->alpha, sd.fin, sd.n_fin, (const float *)c->part,
+                       (const float *)sd.Lam_w, (const float *)sd.Lmu_w, (float *)sd.X, c->ld,
+                       c->seed, sd.stream_row, c->ctr);
+    return hipGetLastError();
+}
+
+template <int NB, int RPW, int WPB>
 hipError_t launch_f32(bpmf_ctx *c, Side &sd, Side &ot, hipStream_t s)
 {
     constexpr int KP = 16 * NB;
-    const size_t lds = sizeof(float) * WPB * (KP * (KP + 1) + KP);
-    const unsigned grid = (unsigned)((sd.n_items + WPB - 1) / WPB);
-    hipLaunchKernelGGL((row_fast_f32<NB, WPB>), dim3(grid), dim3(64 * WPB), lds, s, c->K,
+    const size_t lds = sizeof(float) * WPB * RPW * (KP * (KP + 1) + KP);
+    const int64_t per_block = (int64_t)WPB * RPW;
+    const unsigned grid = (unsigned)((sd.n_items + per_block - 1) / per_block);
+    const uint32_t y_bytes = (uint32_t)(ot.rows * c->ld * sizeof(float));
+    hipLaunchKernelGGL((row_fast_f32<NB, RPW, WPB>), dim3(grid), dim3(64 * WPB), lds, s, c->K,
                        (float)c->alpha, sd.items, sd.n_items, sd.nbr, (const float *)sd.rc,
-                       (const float *)ot.X, c->ld, (const float *)sd.Lam_w,
+                       (const float *)ot.X, c->ld, y_bytes, (const float *)sd.Lam_w,
                        (const float *)sd.Lmu_w, (float *)sd.X, c->ld, (float *)c->part, c->seed,
                        sd.stream_row, c->ctr);
     return hipGetLastError();
@@ -242,7 +404,15 @@ hipError_t launch_f32(bpmf_ctx *c, Side &sd, Side &ot, hipStream_t s)
 
 }  // namespace
 
-bool fast_path_available(const bpmf_ctx *c) { return c->prec == 1 && c->K <= 64; }
+// The matrix-core path needs FP32 factors, K <= 64, and 32-bit buffer
+// offsets for the gathered factor and every work item.
+bool fast_path_available(const bpmf_ctx *c)
+{
+    if (c->prec != 1 || c->K > 64) return false;
+    for (int s = 0; s < 2; ++s)
+        if ((uint64_t)c->side[s].rows * c->ld * sizeof(float) >= kOOB) return false;
+    return (uint64_t)c->split_threshold * 4u < kOOB;
+}
 
 hipError_t launch_row_fast(bpmf_ctx *c, int side_id, hipStream_t s, int stage, bool *handled)
 {
@@ -251,14 +421,21 @@ hipError_t launch_row_fast(bpmf_ctx *c, int side_id, hipStream_t s, int stage, b
     *handled = true;
     Side &sd = c->side[side_id];
     Side &ot = c->side[1 - side_id];
-    if (stage == 1) return launch_row_generic(c, side_id, s, 1);  // split-row finish
-    if (sd.n_items == 0) return hipSuccess;
     const int nb = (c->K + 15) / 16;
+    if (stage == 1) {
+        switch (nb) {
+        case 1: return launch_finish_f32<1, 4>(c, sd, s);
+        case 2: return launch_finish_f32<2, 4>(c, sd, s);
+        case 3: return launch_finish_f32<3, 2>(c, sd, s);
+        default: return launch_finish_f32<4, 2>(c, sd, s);
+        }
+    }
+    if (sd.n_items == 0) return hipSuccess;
     switch (nb) {
-    case 1: return launch_f32<1, 4>(c, sd, ot, s);
-    case 2: return launch_f32<2, 4>(c, sd, ot, s);
-    case 3: return launch_f32<3, 2>(c, sd, ot, s);
-    default: return launch_f32<4, 2>(c, sd, ot, s);
+    case 1: return launch_f32<1, 4, 4>(c, sd, ot, s);
+    case 2: return launch_f32<2, 2, 4>(c, sd, ot, s);
+    case 3: return launch_f32<3, 1, 2>(c, sd, ot, s);
+    default: return launch_f32<4, 1, 2>(c, sd, ot, s);
     }
 }
 

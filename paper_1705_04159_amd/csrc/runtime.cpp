@@ -412,7 +412,7 @@ int bpmf_create(int64_t M, int64_t N, const int64_t *csr_ptr, const int32_t *csr
             CK(hipMemcpy(c->test_col, test_col, sizeof(int32_t) * n_test, hipMemcpyHostToDevice));
             CK(hipMemcpy(c->test_val, test_val, sizeof(float) * n_test, hipMemcpyHostToDevice));
         }
-        c->rmse_blocks = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (n_test + 15) / 16));
+        c->rmse_blocks = (int)std::min<int64_t>(8192, std::max<int64_t>(1, (n_test + 63) / 64));
         CK(dalloc(&c->rmse_part, 2 * (size_t)c->rmse_blocks));
         c->hist_cap = 64;
         CK(dalloc(&c->rmse_hist, 2 * (size_t)c->hist_cap));
