@@ -173,7 +173,7 @@ template <typename T>
 __global__ __launch_bounds__(kThreads) void hyper_draw(
     int K, int64_t n, const double *__restrict__ stats, const double *__restrict__ mu0,
     const double *__restrict__ W0inv, double beta0, double nu0, uint64_t seed, uint32_t stream,
-    const uint32_t *__restrict__ ctr, double *__restrict__ gbuf, int n_lds_bufs,
+    const uint32_t *__restrict__ ctr, uint32_t t_off, double *__restrict__ gbuf, int n_lds_bufs,
     double *__restrict__ mu_out, double *__restrict__ Lam_out, T *__restrict__ Lam_w,
     T *__restrict__ Lmu_w, int *__restrict__ status)
 {
@@ -189,7 +189,7 @@ __global__ __launch_bounds__(kThreads) void hyper_draw(
     double *Bm = buf[2];  // B = L_W A
     __shared__ int ok;
     const int tid = threadIdx.x;
-    const uint32_t t = ctr[0];
+    const uint32_t t = ctr[0] + t_off;
     const double dn = (double)n;
     const double beta_s = beta0 + dn;
     const double nu_s = nu0 + dn;
@@ -297,16 +297,16 @@ __global__ void prior_to_working(int K, const double *__restrict__ mu, const dou
 }
 
 template <int NE>
-void launch_moments(bpmf_ctx *c, const Side &sd, int used, int64_t chunk, hipStream_t s)
+void launch_moments(bpmf_ctx *c, const Side &sd, double *part, int used, int64_t chunk, hipStream_t s)
 {
     const int tile_rows = (int)std::min<size_t>(64, 49152 / (sizeof(double) * (c->K + 1)));
     const size_t lds = sizeof(double) * tile_rows * (c->K + 1);
     if (c->prec == 0)
         hipLaunchKernelGGL((hyper_moments<NE, double>), dim3(used), dim3(kThreads), lds, s, c->K,
-                           (const double *)sd.X, c->ld, sd.rows, chunk, tile_rows, c->hyp_part);
+                           (const double *)sd.X, c->ld, sd.rows, chunk, tile_rows, part);
     else
         hipLaunchKernelGGL((hyper_moments<NE, float>), dim3(used), dim3(kThreads), lds, s, c->K,
-                           (const float *)sd.X, c->ld, sd.rows, chunk, tile_rows, c->hyp_part);
+                           (const float *)sd.X, c->ld, sd.rows, chunk, tile_rows, part);
 }
 
 int lds_buffers(int K, int lds_max)
@@ -322,8 +322,10 @@ size_t draw_lds(int K, int nb) { return sizeof(double) * (4 * (size_t)K + nb * (
 
 }  // namespace
 
-hipError_t launch_hyper(bpmf_ctx *c, int side_id, hipStream_t s)
+hipError_t launch_hyper(bpmf_ctx *c, int side_id, hipStream_t s, uint32_t t_off)
 {
+    double *part = c->hyp_part[side_id], *stats = c->hyp_stats[side_id];
+    double *scratch = c->hyp_scratch[side_id];
     Side &sd = c->side[side_id];
     const int K = c->K;
     const int E = K + K * (K + 1) / 2;
@@ -334,23 +336,22 @@ hipError_t launch_hyper(bpmf_ctx *c, int side_id, hipStream_t s)
     int used = (int)((rows + chunk - 1) / chunk);
     if (used < 1) used = 1;
     const int ne = (E + kThreads - 1) / kThreads;
-    if (ne <= 3) launch_moments<3>(c, sd, used, chunk, s);
-    else if (ne <= 9) launch_moments<9>(c, sd, used, chunk, s);
-    else if (ne <= 21) launch_moments<21>(c, sd, used, chunk, s);
-    else launch_moments<33>(c, sd, used, chunk, s);
-    hipLaunchKernelGGL(hyper_reduce, dim3((E + 3) / 4), dim3(256), 0, s, E, used, c->hyp_part,
-                       c->hyp_stats);
+    if (ne <= 3) launch_moments<3>(c, sd, part, used, chunk, s);
+    else if (ne <= 9) launch_moments<9>(c, sd, part, used, chunk, s);
+    else if (ne <= 21) launch_moments<21>(c, sd, part, used, chunk, s);
+    else launch_moments<33>(c, sd, part, used, chunk, s);
+    hipLaunchKernelGGL(hyper_reduce, dim3((E + 3) / 4), dim3(256), 0, s, E, used, part, stats);
     const int nb = lds_buffers(K, c->hyp_lds_max);
     const size_t lds2 = draw_lds(K, nb);
     if (c->prec == 0)
         hipLaunchKernelGGL((hyper_draw<double>), dim3(1), dim3(kThreads), lds2, s, K, rows,
-                           c->hyp_stats, c->d_mu0, c->d_W0inv, c->beta0, c->nu0, c->seed,
-                           sd.stream_hyp, c->ctr, c->hyp_scratch, nb, sd.mu, sd.Lam,
+                           stats, c->d_mu0, c->d_W0inv, c->beta0, c->nu0, c->seed,
+                           sd.stream_hyp, c->ctr, t_off, scratch, nb, sd.mu, sd.Lam,
                            (double *)sd.Lam_w, (double *)sd.Lmu_w, c->hyp_status);
     else
         hipLaunchKernelGGL((hyper_draw<float>), dim3(1), dim3(kThreads), lds2, s, K, rows,
-                           c->hyp_stats, c->d_mu0, c->d_W0inv, c->beta0, c->nu0, c->seed,
-                           sd.stream_hyp, c->ctr, c->hyp_scratch, nb, sd.mu, sd.Lam,
+                           stats, c->d_mu0, c->d_W0inv, c->beta0, c->nu0, c->seed,
+                           sd.stream_hyp, c->ctr, t_off, scratch, nb, sd.mu, sd.Lam,
                            (float *)sd.Lam_w, (float *)sd.Lmu_w, c->hyp_status);
     return hipGetLastError();
 }

@@ -55,6 +55,8 @@ struct Side {
 struct bpmf_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
+    hipStream_t stream2 = nullptr;          // second stream for overlapped hyper draws
+    hipEvent_t fork_ev[3] = {};             // fork/join events of the sweep graph
     int64_t M = 0, N = 0, nnz = 0, n_test = 0;
     int K = 0, ld = 0, prec = 1;
     double alpha = 2, beta0 = 2, nu0 = 0, rbar = 0;
@@ -71,11 +73,11 @@ struct bpmf_ctx {
     int rmse_blocks = 0;
     double *rmse_hist = nullptr;  // [2 * hist_cap] (avg, last) per sweep of a run
     int64_t hist_cap = 0;
-    // hyper workspace
-    double *hyp_part = nullptr;   // [hyp_blocks * (K + K(K+1)/2)]
+    // hyper workspace, one set per side so that the two draws may overlap
+    double *hyp_part[2] = {};     // [hyp_blocks * (K + K(K+1)/2)]
     int hyp_blocks = 0;
-    double *hyp_stats = nullptr;  // [K + K(K+1)/2]
-    double *hyp_scratch = nullptr;// [4 * K * K + 8 * K]
+    double *hyp_stats[2] = {};    // [K + K(K+1)/2]
+    double *hyp_scratch[2] = {};  // [4 * K * K + 8 * K]
     int *hyp_status = nullptr;    // device flag: 1 = ok
     int hyp_lds_max = 65536;      // LDS bytes the draw kernel may use
     // split partials
@@ -100,8 +102,9 @@ namespace bpmf {
 // ---- launchers (defined in the .hip files; all enqueue on `s`) ----
 // Row update of one side: items, then split-row finishes.
 hipError_t launch_row_update(bpmf_ctx *c, int side_id, hipStream_t s);
-// Hyper draw of one side (statistics, reduction, single-workgroup draw).
-hipError_t launch_hyper(bpmf_ctx *c, int side_id, hipStream_t s);
+// Hyper draw of one side (statistics, reduction, single-workgroup draw) for
+// sweep ctr[0] + t_off.
+hipError_t launch_hyper(bpmf_ctx *c, int side_id, hipStream_t s, uint32_t t_off = 0);
 // Predict the registered test set as sweep ctr[0]; writes rmse_hist[slot].
 hipError_t launch_predict_test(bpmf_ctx *c, hipStream_t s);
 hipError_t launch_predict_pairs(bpmf_ctx *c, int64_t n, hipStream_t s);

@@ -44,34 +44,50 @@ __device__ __forceinline__ double group_dot(int K, const T *u, const T *v, int g
     return as_f64(s);
 }
 
-// One group of 16 lanes per test pair (grid-stride over pairs with a fixed
-// grid).  Writes per-block sums of squared errors (running mean, sample).
-template <typename T>
+// One group of G lanes per test pair, grid-stride over pairs with a fixed
+// grid.  Writes per-block sums of squared errors (running mean, sample).
+// FP32 factors are read as float4 (rows are padded to a multiple of 4).
+template <typename T, int G>
 __global__ __launch_bounds__(256) void predict_test(
     int K, int ld, int64_t n, const int32_t *__restrict__ row, const int32_t *__restrict__ col,
     const float *__restrict__ val, const T *__restrict__ U, const T *__restrict__ V, double rbar,
     double *__restrict__ pred_sum, const uint32_t *__restrict__ ctr, int burn_in,
     double *__restrict__ part)
 {
-    __shared__ double red[2][256 / kGroup];
+    constexpr int GPB = 256 / G;  // groups per block
+    __shared__ double red[2][GPB];
     const uint32_t t = ctr[0];
     const uint32_t cnt = ctr[2];
     const bool use = (int64_t)t > (int64_t)burn_in;
-    const int g = threadIdx.x % kGroup;
-    const int grp = threadIdx.x / kGroup;
-    const int64_t groups_total = (int64_t)gridDim.x * (256 / kGroup);
+    const int g = threadIdx.x % G;
+    const int grp = threadIdx.x / G;
+    const int64_t groups_total = (int64_t)gridDim.x * GPB;
     double sa = 0.0, sl = 0.0;
-    for (int64_t e = (int64_t)blockIdx.x * (256 / kGroup) + grp; e < n; e += groups_total) {
-        double p = group_dot<T>(K, U + (size_t)row[e] * ld, V + (size_t)col[e] * ld, g) + rbar;
+    for (int64_t e = (int64_t)blockIdx.x * GPB + grp; e < n; e += groups_total) {
+        const T *u = U + (size_t)row[e] * ld;
+        const T *v = V + (size_t)col[e] * ld;
+        T s = T(0);
+        if constexpr (sizeof(T) == 4) {
+            for (int k = 4 * g; k < K; k += 4 * G) {
+                const float4 a = *reinterpret_cast<const float4 *>(u + k);
+                const float4 b = *reinterpret_cast<const float4 *>(v + k);
+                s += a.x * b.x + a.y * b.y + a.z * b.z + a.w * b.w;  // padding entries are 0
+            }
+        } else {
+            for (int k = g; k < K; k += G) s += u[k] * v[k];
+        }
+#pragma unroll
+        for (int off = G / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, G);
+        const double p = (double)s + rbar;
         double avg;
         if (use) {
-            double s = pred_sum[e] + p;
-            avg = s / (double)(cnt + 1);
-            if (g == 0) pred_sum[e] = s;
+            const double ps = pred_sum[e] + p;
+            avg = ps / (double)(cnt + 1);
+            if (g == 0) pred_sum[e] = ps;
         } else {
             avg = cnt ? pred_sum[e] / (double)cnt : p;
         }
-        double r = (double)val[e];
+        const double r = (double)val[e];
         sa += (avg - r) * (avg - r);
         sl += (p - r) * (p - r);
     }
@@ -81,9 +97,9 @@ __global__ __launch_bounds__(256) void predict_test(
     }
     __syncthreads();
     if (threadIdx.x < 2) {
-        double s = 0.0;
-        for (int q = 0; q < 256 / kGroup; ++q) s += red[threadIdx.x][q];
-        part[2 * blockIdx.x + threadIdx.x] = s;
+        double s2 = 0.0;
+        for (int q = 0; q < GPB; ++q) s2 += red[threadIdx.x][q];
+        part[2 * blockIdx.x + threadIdx.x] = s2;
     }
 }
 
@@ -177,12 +193,17 @@ hipError_t launch_predict_test(bpmf_ctx *c, hipStream_t s)
 {
     int nblk = c->rmse_blocks;
     if (c->prec == 0)
-        hipLaunchKernelGGL((predict_test<double>), dim3(nblk), dim3(256), 0, s, c->K, c->ld,
+        hipLaunchKernelGGL((predict_test<double, 16>), dim3(nblk), dim3(256), 0, s, c->K, c->ld,
                            c->n_test, c->test_row, c->test_col, c->test_val,
                            (const double *)c->side[0].X, (const double *)c->side[1].X, c->rbar,
                            c->pred_sum, c->ctr, c->burn_in, c->rmse_part);
+    else if (c->ld <= 32)
+        hipLaunchKernelGGL((predict_test<float, 8>), dim3(nblk), dim3(256), 0, s, c->K, c->ld,
+                           c->n_test, c->test_row, c->test_col, c->test_val,
+                           (const float *)c->side[0].X, (const float *)c->side[1].X, c->rbar,
+                           c->pred_sum, c->ctr, c->burn_in, c->rmse_part);
     else
-        hipLaunchKernelGGL((predict_test<float>), dim3(nblk), dim3(256), 0, s, c->K, c->ld,
+        hipLaunchKernelGGL((predict_test<float, 16>), dim3(nblk), dim3(256), 0, s, c->K, c->ld,
                            c->n_test, c->test_row, c->test_col, c->test_val,
                            (const float *)c->side[0].X, (const float *)c->side[1].X, c->rbar,
                            c->pred_sum, c->ctr, c->burn_in, c->rmse_part);

@@ -180,15 +180,30 @@ hipError_t enqueue_sweep_profiled(bpmf_ctx *c, hipStream_t s, hipEvent_t *ev)
     return hipEventRecord(ev[7], s);
 }
 
+// One sweep of Algorithm 1 as captured into the graph, for t = ctr[0].  The
+// V hyperparameters of sweep t were drawn before (by the prologue of
+// bpmf_run_sweeps, or by the previous replay).  Dependencies allow two
+// overlaps on a second stream: the U draw of sweep t needs only U of sweep
+// t-1, so it runs beside the V update; the V draw of sweep t+1 needs only V
+// of sweep t, so it runs beside the U update.  The sweep ends by advancing t.
 hipError_t enqueue_sweep(bpmf_ctx *c, hipStream_t s)
 {
     hipError_t e;
-    if ((e = launch_advance_t(c->ctr, s)) != hipSuccess) return e;
-    if ((e = launch_hyper(c, BPMF_SIDE_V, s)) != hipSuccess) return e;
+    hipStream_t s2 = c->stream2;
+    if ((e = hipEventRecord(c->fork_ev[0], s)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(s2, c->fork_ev[0], 0)) != hipSuccess) return e;
+    if ((e = launch_hyper(c, BPMF_SIDE_U, s2, 0)) != hipSuccess) return e;
+    if ((e = hipEventRecord(c->fork_ev[1], s2)) != hipSuccess) return e;
     if ((e = enqueue_update(c, BPMF_SIDE_V, s)) != hipSuccess) return e;
-    if ((e = launch_hyper(c, BPMF_SIDE_U, s)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(s, c->fork_ev[1], 0)) != hipSuccess) return e;
+    if ((e = hipEventRecord(c->fork_ev[2], s)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(s2, c->fork_ev[2], 0)) != hipSuccess) return e;
+    if ((e = launch_hyper(c, BPMF_SIDE_V, s2, 1)) != hipSuccess) return e;
+    if ((e = hipEventRecord(c->fork_ev[1], s2)) != hipSuccess) return e;
     if ((e = enqueue_update(c, BPMF_SIDE_U, s)) != hipSuccess) return e;
-    return launch_predict_test(c, s);
+    if ((e = launch_predict_test(c, s)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(s, c->fork_ev[1], 0)) != hipSuccess) return e;
+    return launch_advance_t(c->ctr, s);
 }
 
 void free_side(Side &s)
@@ -329,6 +344,8 @@ int bpmf_create(int64_t M, int64_t N, const int64_t *csr_ptr, const int32_t *csr
     {
         CK(hipGetDevice(&c->device));
         CK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+        CK(hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking));
+        for (auto &ev : c->fork_ev) CK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
         CK(hipEventCreate(&c->ev0));
         CK(hipEventCreate(&c->ev1));
         const size_t es = elem_bytes(c);
@@ -394,9 +411,11 @@ int bpmf_create(int64_t M, int64_t N, const int64_t *csr_ptr, const int32_t *csr
         CK(hipMemcpy(c->d_mu0, mu0.data(), sizeof(double) * K, hipMemcpyHostToDevice));
         CK(hipMemcpy(c->d_W0inv, W0inv.data(), sizeof(double) * K * K, hipMemcpyHostToDevice));
         c->hyp_blocks = 512;
-        CK(dalloc(&c->hyp_part, (size_t)c->hyp_blocks * (K + KK2)));
-        CK(dalloc(&c->hyp_stats, (size_t)(K + KK2)));
-        CK(dalloc(&c->hyp_scratch, (size_t)4 * K * K + 8 * K));
+        for (int sid = 0; sid < 2; ++sid) {
+            CK(dalloc(&c->hyp_part[sid], (size_t)c->hyp_blocks * (K + KK2)));
+            CK(dalloc(&c->hyp_stats[sid], (size_t)(K + KK2)));
+            CK(dalloc(&c->hyp_scratch[sid], (size_t)4 * K * K + 8 * K));
+        }
         CK(dalloc(&c->hyp_status, 1));
         {
             int one = 1;
@@ -412,7 +431,7 @@ int bpmf_create(int64_t M, int64_t N, const int64_t *csr_ptr, const int32_t *csr
             CK(hipMemcpy(c->test_col, test_col, sizeof(int32_t) * n_test, hipMemcpyHostToDevice));
             CK(hipMemcpy(c->test_val, test_val, sizeof(float) * n_test, hipMemcpyHostToDevice));
         }
-        c->rmse_blocks = (int)std::min<int64_t>(8192, std::max<int64_t>(1, (n_test + 63) / 64));
+        c->rmse_blocks = (int)std::min<int64_t>(16384, std::max<int64_t>(1, (n_test + 31) / 32));
         CK(dalloc(&c->rmse_part, 2 * (size_t)c->rmse_blocks));
         c->hist_cap = 64;
         CK(dalloc(&c->rmse_hist, 2 * (size_t)c->hist_cap));
@@ -442,9 +461,13 @@ void bpmf_destroy(bpmf_ctx *c)
     if (c->graph) (void)hipGraphExecDestroy(c->graph);
     for (auto &s : c->side) free_side(s);
     void *ps[] = {c->d_mu0, c->d_W0inv, c->test_row, c->test_col, c->test_val, c->pred_sum,
-                  c->rmse_part, c->rmse_hist, c->hyp_part, c->hyp_stats, c->hyp_scratch,
+                  c->rmse_part, c->rmse_hist, c->hyp_part[0], c->hyp_stats[0], c->hyp_scratch[0],
+                  c->hyp_part[1], c->hyp_stats[1], c->hyp_scratch[1],
                   c->hyp_status, c->part, c->ctr, c->q_row, c->q_col, c->q_out};
     for (void *p : ps) (void)hipFree(p);
+    for (auto &ev : c->fork_ev)
+        if (ev) (void)hipEventDestroy(ev);
+    if (c->stream2) (void)hipStreamDestroy(c->stream2);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     if (c->stream) (void)hipStreamDestroy(c->stream);
@@ -534,9 +557,10 @@ int bpmf_run_sweeps(bpmf_ctx *c, uint32_t t0, uint32_t n, double *rmse_avg, doub
             return fail(c, BPMF_E_DEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
         }
     }
-    HIPCK(c, launch_set_counter(c->ctr, 0, t0 - 1, c->stream));
-    HIPCK(c, launch_set_counter(c->ctr, 1, t0, c->stream));
     HIPCK(c, hipEventRecord(c->ev0, c->stream));
+    HIPCK(c, launch_set_counter(c->ctr, 0, t0, c->stream));
+    HIPCK(c, launch_set_counter(c->ctr, 1, t0, c->stream));
+    HIPCK(c, launch_hyper(c, BPMF_SIDE_V, c->stream, 0));
     for (uint32_t i = 0; i < n; ++i) HIPCK(c, hipGraphLaunch(c->graph, c->stream));
     if (int r = timed_end(c)) return r;
     if (int r = check_hyper_status(c)) return r;
