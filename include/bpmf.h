@@ -174,6 +174,59 @@ int bpmf_synchronize(bpmf_ctx *c);
  * bpmf_update_side / bpmf_sample_hyper / bpmf_run_sweeps call. */
 int bpmf_last_time_ms(bpmf_ctx *c, double *ms);
 
+/* ---- Fold-in serving (not a step of Algorithm 1: new users against stored
+ * posterior samples; requires BPMF_FP32 and K <= 64) ----
+ *
+ * For a new user with ratings {(j, r_j)}, each stored sample s gives one draw
+ * from the same row conditional as Algorithm 1's user loop,
+ *   P = Lambda_U^(s) + alpha sum_j v_j^(s) v_j^(s)T,
+ *   b = Lambda_U^(s) mu_U^(s) + alpha sum_j (r_j - rbar) v_j^(s),
+ *   u_s = L^-T (L^-1 b + z_s),  P = L L^T,
+ * with z_s the Philox normals of counter (lo32(id), s, 7<<24 | block, hi32(id))
+ * (id = the request id), then scores p_sj = u_s . v_j^(s) + rbar for every
+ * movie.  The result is the top_n unrated movies by mean_j = (1/S) sum_s p_sj
+ * (descending, ties to the smaller id), with mean_j and the predictive
+ * variance var_j = 1/alpha + (1/S) sum_s (p_sj - mean_j)^2. */
+
+/* Snapshot the current V and the user-side (mu_U, Lambda_U) into the next
+ * slot of a device-resident ring of params.foldin_S samples (the oldest is
+ * overwritten).  The first call allocates the ring and two batch slots and
+ * starts the scheduler thread; params.foldin_pool_bytes (default 256 MiB)
+ * bounds the rated movies in flight: each batch admits requests while their
+ * ratings fit pool/16 (8 B per rating, two batches).  Blocks until in-flight fold-in
+ * batches finished.  A Gibbs call: not concurrent with other Gibbs calls on
+ * c, and the first call must return before any bpmf_foldin_submit. */
+int bpmf_store_sample(bpmf_ctx *c);
+
+/* Queue a request: n distinct movie ids in [0, N) with their ratings (host
+ * arrays, copied), 1 <= top_n <= 1024.  *req_id receives the request id
+ * (1, 2, ... in submission order on this context; also the noise key).
+ * Thread-safe.  Errors: BPMF_E_NOSAMPLES before any stored sample,
+ * BPMF_E_RANGE / BPMF_E_FORMAT for bad ids, duplicates or non-finite
+ * ratings, BPMF_E_TOOBIG if n exceeds one batch's rating capacity,
+ * BPMF_E_BUSY if 2^20 requests are pending.  Requests are batched as they
+ * arrive (continuous batching on a separate stream); a request's result does
+ * not depend on what it is batched with. */
+int bpmf_foldin_submit(bpmf_ctx *c, int32_t n, const int32_t *movie, const float *rating,
+                       int32_t top_n, uint64_t *req_id);
+
+/* Thread-safe.  BPMF_PENDING while the request runs; BPMF_OK once done, after
+ * copying top_n entries into movie_out / mean_out / var_out (caller-allocated,
+ * any may be NULL; entries beyond the number of unrated movies are -1 / 0)
+ * and the time from submission to completion into *latency_s; the request is
+ * then forgotten (a second poll gives BPMF_E_NOTFOUND). */
+int bpmf_foldin_poll(bpmf_ctx *c, uint64_t req_id, int32_t *movie_out, float *mean_out,
+                     float *var_out, double *latency_s);
+
+/* Block until every submitted request has completed. */
+int bpmf_foldin_drain(bpmf_ctx *c);
+
+/* Number of samples currently in the ring. */
+int bpmf_foldin_samples(const bpmf_ctx *c);
+
+/* Ratings one batch can hold (0 before the first bpmf_store_sample). */
+int64_t bpmf_foldin_capacity(const bpmf_ctx *c);
+
 /* Message of the last failed call on c (or of the last failed create when c
  * is NULL). */
 const char *bpmf_last_error(const bpmf_ctx *c);

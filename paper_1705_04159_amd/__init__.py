@@ -33,7 +33,9 @@ EXPORTS = [
     "bpmf_run_sweeps", "bpmf_profile_sweeps", "bpmf_predict", "bpmf_get_factor", "bpmf_set_factor",
     "bpmf_get_factor_f64", "bpmf_set_factor_f64", "bpmf_get_hyper", "bpmf_set_hyper",
     "bpmf_get_csc", "bpmf_get_plan", "bpmf_mean_rating", "bpmf_synchronize",
-    "bpmf_last_time_ms", "bpmf_last_error", "bpmf_destroy",
+    "bpmf_last_time_ms", "bpmf_last_error", "bpmf_destroy", "bpmf_store_sample",
+    "bpmf_foldin_submit", "bpmf_foldin_poll", "bpmf_foldin_drain", "bpmf_foldin_samples",
+    "bpmf_foldin_capacity",
 ]
 
 
@@ -97,6 +99,13 @@ def lib() -> ctypes.CDLL:
         L.bpmf_last_error.restype = ctypes.c_char_p
         L.bpmf_destroy.argtypes = [P]
         L.bpmf_destroy.restype = None
+        L.bpmf_store_sample.argtypes = [P]
+        L.bpmf_foldin_submit.argtypes = [P, i32, P, P, i32, P]
+        L.bpmf_foldin_poll.argtypes = [P, ctypes.c_uint64, P, P, P, P]
+        L.bpmf_foldin_drain.argtypes = [P]
+        L.bpmf_foldin_samples.argtypes = [P]
+        L.bpmf_foldin_capacity.argtypes = [P]
+        L.bpmf_foldin_capacity.restype = i64
         _lib = L
     return _lib
 
@@ -116,7 +125,8 @@ class Sampler:
     test_col, test_val (e.g. ``synth.Ratings``)."""
 
     def __init__(self, ratings, K, prec="fp32", alpha=2.0, beta0=2.0, nu0=None, mu0=None,
-                 W0=None, seed=0, center=True, burn_in=0, split_threshold=0, csc=None):
+                 W0=None, seed=0, center=True, burn_in=0, split_threshold=0, csc=None,
+                 foldin_S=16, foldin_pool_bytes=0):
         L = lib()
         self.M, self.N, self.K = int(ratings.M), int(ratings.N), int(K)
         self.prec = PRECISIONS[prec] if isinstance(prec, str) else int(prec)
@@ -133,6 +143,8 @@ class Sampler:
         p.center = 1 if center else 0
         p.burn_in = int(burn_in)
         p.split_threshold = int(split_threshold)
+        p.foldin_S = int(foldin_S)
+        p.foldin_pool_bytes = int(foldin_pool_bytes)
         ptr = _c(ratings.csr_ptr, np.int64)
         col = _c(ratings.csr_col, np.int32)
         val = _c(ratings.csr_val, np.float32)
@@ -257,6 +269,40 @@ class Sampler:
 
     def synchronize(self):
         self._check(lib().bpmf_synchronize(self._ctx))
+
+    # -- fold-in serving ------------------------------------------------------
+    def store_sample(self):
+        self._check(lib().bpmf_store_sample(self._ctx))
+
+    def foldin_samples(self):
+        return int(lib().bpmf_foldin_samples(self._ctx))
+
+    def foldin_submit(self, movie, rating, top_n=100):
+        movie = _c(movie, np.int32)
+        rating = _c(rating, np.float32)
+        rid = ctypes.c_uint64()
+        self._check(lib().bpmf_foldin_submit(self._ctx, len(movie), _ptr(movie), _ptr(rating),
+                                             int(top_n), ctypes.byref(rid)))
+        return rid.value
+
+    def foldin_poll(self, req_id, top_n=100):
+        """None while pending, else (movie ids, mean, var, latency seconds)."""
+        ids = np.zeros(top_n, np.int32)
+        mean = np.zeros(top_n, np.float32)
+        var = np.zeros(top_n, np.float32)
+        lat = ctypes.c_double()
+        rc = lib().bpmf_foldin_poll(self._ctx, req_id, _ptr(ids), _ptr(mean), _ptr(var),
+                                    ctypes.byref(lat))
+        if rc == PENDING:
+            return None
+        self._check(rc)
+        return ids, mean, var, lat.value
+
+    def foldin_capacity(self):
+        return int(lib().bpmf_foldin_capacity(self._ctx))
+
+    def foldin_drain(self):
+        self._check(lib().bpmf_foldin_drain(self._ctx))
 
     def last_time_ms(self):
         ms = ctypes.c_double()

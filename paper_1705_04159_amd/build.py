@@ -15,7 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "libbpmf.so")
-SOURCES = ["runtime.cpp", "row_generic.hip", "row_fast.hip", "hyper.hip", "misc.hip"]
+SOURCES = ["runtime.cpp", "row_generic.hip", "row_fast.hip", "hyper.hip", "misc.hip", "foldin.hip",
+           "foldin.cpp"]
 ARCH = os.environ.get("BPMF_OFFLOAD_ARCH", "gfx950")
 
 COMMON = [

@@ -29,6 +29,17 @@ struct FinishItem {
     int32_t pad;
 };
 
+// One fold-in draw: request `req` (index into the batch) against stored
+// sample `s`; its ratings are [beg, end) of the batch arrays.
+struct FoldItem {
+    int32_t req;
+    int32_t s;
+    int64_t beg;
+    int64_t end;
+};
+
+struct FoldinState;  // fold-in server (foldin.cpp)
+
 struct Side {
     int64_t rows = 0;
     int64_t *ptr = nullptr;  // device [rows + 1] neighbour offsets
@@ -95,6 +106,9 @@ struct bpmf_ctx {
     double last_ms = 0;
     std::string err;
     bool sticky = false;
+    int foldin_S = 16;
+    uint64_t foldin_pool = 0;
+    bpmf::FoldinState *foldin = nullptr;
 };
 
 namespace bpmf {
@@ -120,5 +134,18 @@ hipError_t launch_prior_to_working(bpmf_ctx *c, int side_id, hipStream_t s);
 hipError_t launch_to_bf16(bpmf_ctx *c, int side_id, hipStream_t s);
 // Largest dynamic LDS a generic row kernel needs for K (bytes).
 size_t row_generic_lds_bytes(int K, int prec);
+// Fold-in kernels (FP32 factors, K <= 64).
+bool fast_path_available(const bpmf_ctx *c);
+hipError_t launch_foldin_draw(const bpmf_ctx *c, const FoldItem *items, int64_t n_items,
+                              const int32_t *nbr, const float *rc, const float *Vring,
+                              const float *Lam_ring, const float *Lmu_ring, const uint64_t *req_ids,
+                              int n_samples, float *U, hipStream_t s);
+hipError_t launch_foldin_score(const bpmf_ctx *c, int n_req, int S, const float *Vring,
+                               const float *U, float *mean, float *var, hipStream_t s);
+hipError_t launch_foldin_topk(const bpmf_ctx *c, int n_req, const float *mean, const float *var,
+                              const int32_t *req_beg, const int32_t *nbr, const int32_t *top_n,
+                              int top_max, int32_t *out_ids, float *out_mean, float *out_var,
+                              hipStream_t s);
+void foldin_destroy(bpmf_ctx *c);
 
 }  // namespace bpmf

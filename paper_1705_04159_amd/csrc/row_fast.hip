@@ -114,10 +114,12 @@ __device__ __forceinline__ float bm_normal_f32(uint32_t wr, uint32_t wa, bool si
 
 // Factor and sample one row held column-per-lane: lane c of the group has
 // v[r] = P[r][c] for r < KP (identity outside the leading K x K block) and
-// v[KP] = b_c.  Returns x_c (meaningful for c < K).
+// v[KP] = b_c.  The normals come from Philox counters (c0, c1, stream<<24 |
+// block, c3).  Returns x_c (meaningful for c < K).
 template <int KP, int RPW>
-__device__ __forceinline__ float chol_sample_column(float (&v)[KP + 1], int K, int c, uint32_t row,
-                                                    uint32_t t, uint64_t seed, uint32_t stream)
+__device__ __forceinline__ float chol_sample_column(float (&v)[KP + 1], int K, int c, uint32_t c0,
+                                                    uint32_t c1, uint32_t c3, uint64_t seed,
+                                                    uint32_t stream)
 {
     float mydiag = 1.f;
     static_for<0, KP>([&](auto kc) {
@@ -144,7 +146,7 @@ __device__ __forceinline__ float chol_sample_column(float (&v)[KP + 1], int K, i
     float w = v[KP] * inv_s;
     {
         const uint32_t blk = (uint32_t)(c >> 2);
-        const Block4 bl = philox4x32_10(row, t, (stream << 24) | blk, 0u, seed);
+        const Block4 bl = philox4x32_10(c0, c1, (stream << 24) | blk, c3, seed);
         const int m = c & 3;
         const uint32_t wr = m < 2 ? bl.w0 : bl.w2;
         const uint32_t wa = m < 2 ? bl.w1 : bl.w3;
@@ -325,8 +327,107 @@ __global__ __launch_bounds__(64 * WPB) void row_fast_f32(
     for (int r = 0; r < KP; ++r)
         v[r] = (live && r < K) ? alpha * P[r * LDP + cc] + Lam[r * K + c] : (r == c ? 1.f : 0.f);
     v[KP] = live ? alpha * P[KP * LDP + cc] + Lmu[c] : 0.f;
-    const float x = chol_sample_column<KP, RPW>(v, K, c, (uint32_t)my_row, ctr[0], seed, stream);
+    const float x = chol_sample_column<KP, RPW>(v, K, c, (uint32_t)my_row, ctr[0], 0u, seed, stream);
     if (live) X[(size_t)my_row * ldx + c] = x;
+}
+
+// Fold-in draws: item q is (request, stored sample s); its neighbour list is
+// the request's rated movies, the gathered factor is V of sample s and the
+// prior is (mu_U, Lambda_U) of sample s; the noise counter is
+// (lo32(req id), s, stream<<24 | block, hi32(req id)).  Output row q of U.
+template <int NB, int RPW, int WPB>
+__global__ __launch_bounds__(64 * WPB) void foldin_draw_f32(
+    int K, float alpha, const FoldItem *__restrict__ items, int64_t n_items,
+    const int32_t *__restrict__ nbr, const float *__restrict__ rc, const float *__restrict__ Vring,
+    int64_t v_stride, int ldy, uint32_t y_bytes, const float *__restrict__ Lam_ring,
+    const float *__restrict__ Lmu_ring, const uint64_t *__restrict__ req_ids, int n_samples,
+    float *__restrict__ U, int ldu, uint64_t seed, uint32_t stream)
+{
+    constexpr int KP = 16 * NB;
+    constexpr int LDP = KP + 1;
+    constexpr int NBLK = NB * (NB + 1) / 2;
+    constexpr int LPR = 64 / RPW;
+    constexpr int REGION = KP * LDP + KP;
+    extern __shared__ float smem_f[];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int64_t first = ((int64_t)blockIdx.x * WPB + wave) * RPW;
+    if (first >= n_items) return;
+    float *Ps = smem_f + wave * RPW * REGION;
+    const int col = lane & 15;
+    const int kq = lane >> 4;
+    const uint32_t ldy4 = (uint32_t)ldy * 4u;
+    uint32_t lane_off[NB];
+#pragma unroll
+    for (int bi = 0; bi < NB; ++bi) lane_off[bi] = 16 * bi + col < K ? (16 * bi + col) * 4u : kOOB;
+    int s_of[RPW], req_of[RPW];
+    static_for<0, RPW>([&](auto hc) {
+        constexpr int h = decltype(hc)::value;
+        req_of[h] = -1;
+        s_of[h] = 0;
+        const int64_t id = first + h;
+        if (id >= n_items) return;
+        const FoldItem f = items[id];
+        const RowItem it{f.req, -1, f.beg, f.end};
+        const __amdgpu_buffer_rsrc_t ysrc = make_rsrc(Vring + (size_t)f.s * v_stride, y_bytes);
+        floatx4 acc[NBLK];
+#pragma unroll
+        for (int q = 0; q < NBLK; ++q) acc[q] = floatx4{0.f, 0.f, 0.f, 0.f};
+        float bacc[NB];
+#pragma unroll
+        for (int bi = 0; bi < NB; ++bi) bacc[bi] = 0.f;
+        gram_item<NB>(it, nbr, rc, ysrc, ldy4, lane_off, kq, acc, bacc);
+#pragma unroll
+        for (int bi = 0; bi < NB; ++bi) {
+            bacc[bi] += __shfl_xor(bacc[bi], 16);
+            bacc[bi] += __shfl_xor(bacc[bi], 32);
+        }
+        float *P = Ps + h * REGION;
+        int q = 0;
+#pragma unroll
+        for (int bi = 0; bi < NB; ++bi) {
+#pragma unroll
+            for (int bj = 0; bj <= bi; ++bj) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int r = 16 * bi + 4 * kq + v, c = 16 * bj + col;
+                    P[r * LDP + c] = acc[q][v];
+                    if (bi != bj) P[c * LDP + r] = acc[q][v];
+                }
+                ++q;
+            }
+            if (kq == 0) P[KP * LDP + 16 * bi + col] = bacc[bi];
+        }
+        req_of[h] = f.req;
+        s_of[h] = f.s;
+    });
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int grp = lane / LPR;
+    const int c = lane & (LPR - 1);
+    int my_req = req_of[0], my_s = s_of[0];
+#pragma unroll
+    for (int h = 1; h < RPW; ++h)
+        if (grp == h) {
+            my_req = req_of[h];
+            my_s = s_of[h];
+        }
+    const bool live = my_req >= 0 && c < K;
+    const float *P = Ps + grp * REGION;
+    const float *Lam = Lam_ring + (size_t)my_s * K * K;
+    const float *Lmu = Lmu_ring + (size_t)my_s * K;
+    const int cc = c < KP ? c : 0;
+    float v[KP + 1];
+#pragma unroll
+    for (int r = 0; r < KP; ++r)
+        v[r] = (live && r < K) ? alpha * P[r * LDP + cc] + Lam[r * K + c] : (r == c ? 1.f : 0.f);
+    v[KP] = live ? alpha * P[KP * LDP + cc] + Lmu[c] : 0.f;
+    const uint64_t key = my_req >= 0 ? req_ids[my_req] : 0ull;
+    const float x = chol_sample_column<KP, RPW>(v, K, c, (uint32_t)key, (uint32_t)my_s,
+                                                (uint32_t)(key >> 32), seed, stream);
+    const int64_t out_row = (int64_t)my_req * n_samples + my_s;
+    if (live) U[(size_t)out_row * ldu + c] = x;
 }
 
 // Sum the partial slots of every split row into its first slot, in slot
@@ -367,7 +468,7 @@ __global__ __launch_bounds__(64 * WPB) void row_finish_fast(
         v[r] = (live && r < K) ? alpha * src[r >= c ? pk(r, c) : pk(c, r)] + Lam[r * K + c]
                                : (r == c ? 1.f : 0.f);
     v[KP] = live ? alpha * src[KK2 + c] + Lmu[c] : 0.f;
-    const float x = chol_sample_column<KP, 1>(v, K, c, (uint32_t)f.row, ctr[0], seed, stream);
+    const float x = chol_sample_column<KP, 1>(v, K, c, (uint32_t)f.row, ctr[0], 0u, seed, stream);
     if (live) X[(size_t)f.row * ldx + c] = x;
 }
 
@@ -403,6 +504,38 @@ hipError_t launch_f32(bpmf_ctx *c, Side &sd, Side &ot, hipStream_t s)
 }
 
 }  // namespace
+
+hipError_t launch_foldin_draw(const bpmf_ctx *c, const FoldItem *items, int64_t n_items,
+                              const int32_t *nbr, const float *rc, const float *Vring,
+                              const float *Lam_ring, const float *Lmu_ring, const uint64_t *req_ids,
+                              int n_samples, float *U, hipStream_t s)
+{
+    if (n_items == 0) return hipSuccess;
+    const int nb = (c->K + 15) / 16;
+    const int64_t v_stride = c->N * (int64_t)c->ld;
+    const uint32_t y_bytes = (uint32_t)(v_stride * sizeof(float));
+    auto go = [&](auto nbc, auto rpwc, auto wpbc) {
+        constexpr int NB = decltype(nbc)::value, RPW = decltype(rpwc)::value, WPB = decltype(wpbc)::value;
+        constexpr int KP = 16 * NB;
+        const size_t lds = sizeof(float) * WPB * RPW * (KP * (KP + 1) + KP);
+        const int64_t per_block = (int64_t)WPB * RPW;
+        const unsigned grid = (unsigned)((n_items + per_block - 1) / per_block);
+        hipLaunchKernelGGL((foldin_draw_f32<NB, RPW, WPB>), dim3(grid), dim3(64 * WPB), lds, s, c->K,
+                           (float)c->alpha, items, n_items, nbr, rc, Vring, v_stride, c->ld, y_bytes,
+                           Lam_ring, Lmu_ring, req_ids, n_samples, U, c->ld, c->seed, 7u);
+    };
+    using I = std::integral_constant<int, 1>;
+    using II = std::integral_constant<int, 2>;
+    using III = std::integral_constant<int, 3>;
+    using IV = std::integral_constant<int, 4>;
+    switch (nb) {
+    case 1: go(I{}, IV{}, IV{}); break;
+    case 2: go(II{}, II{}, IV{}); break;
+    case 3: go(III{}, I{}, II{}); break;
+    default: go(IV{}, I{}, II{}); break;
+    }
+    return hipGetLastError();
+}
 
 // The matrix-core path needs FP32 factors, K <= 64, and 32-bit buffer
 // offsets for the gathered factor and every work item.

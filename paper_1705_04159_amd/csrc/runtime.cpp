@@ -248,6 +248,9 @@ int bpmf_create(int64_t M, int64_t N, const int64_t *csr_ptr, const int32_t *csr
     if (K < 1 || K > 128) return fail(nullptr, BPMF_E_INVAL, "K=%d outside 1..128", K);
     if (p->prec < 0 || p->prec > 2) return fail(nullptr, BPMF_E_INVAL, "bad precision %d", p->prec);
     if (p->prec == BPMF_FP64 && K > 64) return fail(nullptr, BPMF_E_INVAL, "FP64 mode supports K <= 64");
+    if (p->foldin_S < 0 || p->foldin_S > 64) return fail(nullptr, BPMF_E_INVAL, "foldin_S outside 0..64");
+    if (p->split_threshold < 0 || p->split_threshold > (1 << 24))
+        return fail(nullptr, BPMF_E_INVAL, "split_threshold outside 0..2^24");
     if (!(p->alpha > 0) || !(p->beta0 > 0) || !(p->nu0 > K - 1))
         return fail(nullptr, BPMF_E_INVAL, "need alpha > 0, beta0 > 0, nu0 > K - 1");
     if (M < 1 || N < 1 || M > INT32_MAX || N > INT32_MAX || nnz < 0)
@@ -324,6 +327,8 @@ int bpmf_create(int64_t M, int64_t N, const int64_t *csr_ptr, const int32_t *csr
     c->seed = p->seed;
     c->burn_in = p->burn_in;
     c->split_threshold = p->split_threshold > 0 ? p->split_threshold : 2048;
+    c->foldin_S = p->foldin_S > 0 ? p->foldin_S : 16;
+    c->foldin_pool = p->foldin_pool_bytes;
     double rbar = 0.0;
     if (p->center) {
         double s = 0.0;
@@ -457,6 +462,7 @@ error:
 void bpmf_destroy(bpmf_ctx *c)
 {
     if (!c) return;
+    foldin_destroy(c);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     if (c->graph) (void)hipGraphExecDestroy(c->graph);
     for (auto &s : c->side) free_side(s);
