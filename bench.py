@@ -89,6 +89,72 @@ def cpu_baseline(r, K, seconds, seed):
                       "workload (%d rows per sweep), %.1f s" % (done, r.M + r.N, el)}
 
 
+def foldin_requests(r, n_req, seed, max_n=5000):
+    """Synthetic new users: sizes log-uniform on [1, max_n], movies drawn by
+    training popularity without repetition, ratings N(mean, 1) clipped to the
+    training range (the values only matter for the arithmetic, not the load)."""
+    rng = np.random.default_rng(seed)
+    pop = np.bincount(r.csr_col, minlength=r.N).astype(np.float64) + 1.0
+    cdf = np.cumsum(pop / pop.sum())
+    lo, hi = float(r.csr_val.min()), float(r.csr_val.max())
+    mu = float(r.csr_val.mean())
+    sizes = np.minimum(np.round(np.exp(rng.uniform(0.0, np.log(max_n), n_req))).astype(np.int64),
+                       r.N - 1)
+    reqs = []
+    for n in sizes:
+        got = np.zeros(0, np.int64)
+        while len(got) < n:
+            draw = np.minimum(np.searchsorted(cdf, rng.random(int(1.3 * (n - len(got))) + 8)), r.N - 1)
+            _, first = np.unique(np.concatenate([got, draw]), return_index=True)
+            got = np.concatenate([got, draw])[np.sort(first)]
+        movie = got[:n].astype(np.int32)
+        rating = np.clip(rng.normal(mu, 1.0, n), lo, hi).astype(np.float32)
+        reqs.append((movie, rating))
+    return reqs, sizes
+
+
+def foldin_bench(s, r, rate, seconds, seed, top_n=100):
+    """Open-loop Poisson arrivals at `rate` req/s for `seconds`; latency is
+    completion (seen by the scheduler) minus the scheduled arrival time."""
+    rng = np.random.default_rng(seed + 1)
+    n_req = int(rate * seconds)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, n_req))
+    reqs, sizes = foldin_requests(r, n_req, seed)
+    # warm the path (first batch allocations, kernel loads)
+    for movie, rating in reqs[:8]:
+        s.foldin_submit(movie, rating, top_n)
+    s.foldin_drain()
+    lag = np.zeros(n_req)
+    ids = np.zeros(n_req, np.uint64)
+    t0 = time.perf_counter()
+    for i in range(n_req):
+        while True:
+            now = time.perf_counter() - t0
+            if now >= arrivals[i]:
+                break
+            if arrivals[i] - now > 2e-4:
+                time.sleep(min(arrivals[i] - now - 1e-4, 1e-3))
+        lag[i] = (time.perf_counter() - t0) - arrivals[i]
+        ids[i] = s.foldin_submit(reqs[i][0], reqs[i][1], top_n)
+    s.foldin_drain()
+    t_end = time.perf_counter() - t0
+    lat = np.zeros(n_req)
+    for i in range(n_req):
+        res = s.foldin_poll(int(ids[i]), top_n)
+        lat[i] = res[3] + lag[i]
+    return {
+        "offered_req_per_s": rate,
+        "completed_req_per_s": round(n_req / t_end, 1),
+        "n_requests": n_req,
+        "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 3),
+        "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 3),
+        "p999_ms": round(1e3 * float(np.percentile(lat, 99.9)), 3),
+        "mean_ratings_per_request": round(float(sizes.mean()), 1),
+        "samples": s.foldin_samples(),
+        "top_n": top_n,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,6 +166,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=5)
+    ap.add_argument("--foldin-rate", type=float, default=5000.0)
+    ap.add_argument("--foldin-seconds", type=float, default=3.0)
+    ap.add_argument("--no-foldin", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (torch), the "
                          "reference kernel for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE")
@@ -197,6 +266,15 @@ def main():
         "phase_ms": phase,
         "roofline": roof,
     }
+    if not args.no_foldin and prec == "fp32" and K <= 64:
+        # 16 posterior samples from the running chain, then open-loop serving
+        t = warm + steps + pn + 1
+        for _ in range(16):
+            s.run_sweeps(t, 1)
+            t += 1
+            s.store_sample()
+        out["foldin"] = foldin_bench(s, r, args.foldin_rate, args.foldin_seconds, args.seed)
+        log("fold-in: %s" % out["foldin"])
     s.close()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(r, K, args.cpu_seconds, args.seed)
