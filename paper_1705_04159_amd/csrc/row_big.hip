@@ -1,0 +1,512 @@
+// row_big.hip -- matrix-core row update for FP32 factors with 64 < K <= 128.
+//
+// Per row (Algorithm 1's item body with BPMF's conditional):
+//   P = Lambda + alpha sum_j y_j y_j^T,  b = Lambda mu + alpha sum_j r'_j y_j,
+//   P = L L^T,  y = L^-1 b,  x = L^-T (y + z).
+// One wavefront per work item.
+//
+// Gram: FP32 rows on v_mfma_f32_16x16x4_f32 (as for K <= 64), or -- in the
+// BF16-Gram mode -- BF16 copies of the neighbour rows on
+// v_mfma_f32_16x16x32_bf16, where lane l supplies component 16*bi + (l % 16)
+// of the 8 ratings 8*(l / 16) .. +7 of a 32-rating chunk; both accumulate in
+// FP32 and only the nb(nb+1)/2 lower 16x16 blocks of P are formed.
+//
+// Factorisation: blocked right-looking Cholesky with 16x16 blocks, the
+// trailing matrix kept in the MFMA accumulators.  For each block column kb:
+// the column goes to LDS; the diagonal block is factored column-per-lane
+// (16 lanes, pivot columns broadcast by v_readlane); every row below it,
+// and b's segment as one extra row, is solved against L_kk^T (one row per
+// lane; L_kk read by broadcast from LDS), which also yields y_kb = L_kk^-1 b_kb
+// and lets each row update b; the solved panel returns to the accumulators
+// (they end up holding L) and the trailing blocks are updated by
+// v_mfma_f32_16x16x4_f32 with the panel as both operands (negated A).
+// Back solve by block rows from the last, with the off-diagonal products
+// taken from the accumulators and reduced across lanes.
+//
+// Noise as in the other row kernels: Philox4x32-10 normal c of the row from
+// block c/4 of counter (row, t, stream<<24 | block, 0), Box-Muller in FP32.
+#include "internal.h"
+#include "rng_device.h"
+#include "row_common.h"
+
+namespace bpmf {
+
+hipError_t launch_part_reduce(bpmf_ctx *c, Side &sd, hipStream_t s);
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kBigWPB = 2;     // waves per workgroup (independent)
+constexpr int kBigUnroll = 2;  // FP32 Gram: groups of 4 ratings per chunk
+constexpr int kPS = 17;        // panel row stride (floats)
+
+template <int NB>
+struct BigLds {
+    static constexpr int PAN = NB * 16 * kPS;  // block column kb, rows of all blocks below
+    static constexpr int LDG = 256;            // L_kk, row-major 16 x 16
+    static constexpr int INVD = 16;            // 1 / L_kk[c][c]
+    static constexpr int VEC = 128;            // b, y, w, x
+    static constexpr int TOTAL = PAN + LDG + INVD + 4 * VEC;
+};
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ uint32_t buf_u16(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    return (uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, (int)off, 0, 0);
+}
+
+// Gram and rhs of one work item from BF16 rows (whole wave).  Chunks of 32
+// ratings; lane l takes ratings 8*(l/16) + e, e = 0..7, of each chunk.
+template <int NB>
+__device__ __forceinline__ void gram_item_bf16(const RowItem &it, const int32_t *__restrict__ nbr,
+                                               const float *__restrict__ rc,
+                                               __amdgpu_buffer_rsrc_t ysrc, uint32_t ldy2,
+                                               const uint32_t (&lane_off)[NB], int kq,
+                                               floatx4 (&acc)[NB * (NB + 1) / 2],
+                                               float (&bacc)[NB])
+{
+    const uint32_t cnt = (uint32_t)(it.end - it.beg);
+    const __amdgpu_buffer_rsrc_t jsrc = make_rsrc(nbr + it.beg, cnt * 4u);
+    const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(rc + it.beg, cnt * 4u);
+    const uint32_t nchunk = (cnt + 31) / 32;
+    for (uint32_t ch = 0; ch < nchunk; ++ch) {
+        uint32_t base[8];
+        float r[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const uint32_t t = ch * 32 + 8 * kq + e;
+            const uint32_t j = buf_u32(jsrc, t * 4u);
+            r[e] = buf_f32(rsrc, t * 4u);
+            base[e] = t < cnt ? j * ldy2 : kOOB;
+        }
+        // raw BF16 bits; pairs packed into dwords form the MFMA operand
+        uint32_t yr[NB][8];
+#pragma unroll
+        for (int bi = 0; bi < NB; ++bi)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) yr[bi][e] = buf_u16(ysrc, base[e] + lane_off[bi]) & 0xFFFFu;
+        bf16x8 y[NB];
+#pragma unroll
+        for (int bi = 0; bi < NB; ++bi) {
+            u32x4 w;
+#pragma unroll
+            for (int h = 0; h < 4; ++h) w[h] = yr[bi][2 * h] | (yr[bi][2 * h + 1] << 16);
+            y[bi] = __builtin_bit_cast(bf16x8, w);
+        }
+        int q = 0;
+#pragma unroll
+        for (int bi = 0; bi < NB; ++bi) {
+#pragma unroll
+            for (int bj = 0; bj <= bi; ++bj) {
+                acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(y[bi], y[bj], acc[q], 0, 0, 0);
+                ++q;
+            }
+            float s = 0.f;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) s += r[e] * __uint_as_float(yr[bi][e] << 16);
+            bacc[bi] += s;
+        }
+    }
+}
+
+// Blocked factorisation and draw for one row held in the accumulators (raw
+// Gram) and b in LDS (b = alpha * rhs + Lambda mu already).  Writes x_c.
+template <int NB>
+__device__ __forceinline__ void blocked_chol_sample(floatx4 (&acc)[NB * (NB + 1) / 2], float *lds,
+                                                    int K, float alpha,
+                                                    const float *__restrict__ Lam, uint32_t row,
+                                                    uint32_t t, uint64_t seed, uint32_t stream,
+                                                    float *__restrict__ xrow)
+{
+    using L = BigLds<NB>;
+    float *pan = lds;
+    float *ldg = pan + L::PAN;
+    float *invd = ldg + L::LDG;
+    float *bv = invd + L::INVD;
+    float *yv = bv + L::VEC;
+    float *wv = yv + L::VEC;
+    float *xv = wv + L::VEC;
+    const int lane = threadIdx.x & 63;
+    const int col = lane & 15;
+    const int kq = lane >> 4;
+
+    // P = alpha G + Lambda; identity on the padding
+    static_for<0, NB>([&](auto bic) {
+        constexpr int bi = decltype(bic)::value;
+        static_for<0, bi + 1>([&](auto bjc) {
+            constexpr int bj = decltype(bjc)::value;
+            constexpr int q = bi * (bi + 1) / 2 + bj;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = 16 * bi + 4 * kq + v, c = 16 * bj + col;
+                const float prior = (r < K && c < K) ? Lam[r * K + c] : (r == c ? 1.f : 0.f);
+                acc[q][v] = alpha * acc[q][v] + prior;
+            }
+        });
+    });
+
+    static_for<0, NB>([&](auto kbc) {
+        constexpr int kb = decltype(kbc)::value;
+        constexpr int R = 16 * (NB - 1 - kb);  // panel rows below the diagonal block
+        // (1) block column kb to LDS
+        static_for<kb, NB>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            constexpr int q = i * (i + 1) / 2 + kb;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) pan[((i - kb) * 16 + 4 * kq + v) * kPS + col] = acc[q][v];
+        });
+        wave_sync();
+        // (2) diagonal block, column-per-lane on 16 lanes (the other lanes
+        // compute copies)
+        {
+            float d[16];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) d[r] = pan[r * kPS + col];
+            float mydiag = 1.f;
+            static_for<0, 16>([&](auto kc) {
+                constexpr int k = decltype(kc)::value;
+                const float dk = readlane_f(d[k], k);
+                if (col == k) mydiag = dk;
+                const float f = col > k ? d[k] * __builtin_amdgcn_rcpf(dk) : 0.f;
+                float prk[16];
+                static_for<k + 1, 16>([&](auto rc) {
+                    constexpr int r = decltype(rc)::value;
+                    prk[r] = readlane_f(d[r], k);
+                });
+                static_for<k + 1, 16>([&](auto rc) {
+                    constexpr int r = decltype(rc)::value;
+                    d[r] -= f * prk[r];
+                });
+            });
+            const float inv_s = __builtin_amdgcn_rsqf(mydiag);
+            if (lane < 16) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) ldg[r * 16 + col] = r >= col ? d[r] * inv_s : 0.f;
+                invd[col] = inv_s;
+            }
+        }
+        wave_sync();
+        // (3) rows below, and b's segment as row R: solve x L_kk^T = a
+        float xs[2][16];
+        static_for<0, 2>([&](auto hc) {
+            constexpr int h = decltype(hc)::value;
+            const int rr = lane + 64 * h;
+            if (rr <= R) {
+                float a[16];
+                if (rr < R) {
+                    const int off = (16 + rr) * kPS;
+#pragma unroll
+                    for (int cc = 0; cc < 16; ++cc) a[cc] = pan[off + cc];
+                } else {
+#pragma unroll
+                    for (int cc = 0; cc < 16; ++cc) a[cc] = bv[16 * kb + cc];
+                }
+#pragma unroll
+                for (int cc = 0; cc < 16; ++cc) {
+                    float sacc = a[cc];
+#pragma unroll
+                    for (int m = 0; m < cc; ++m) sacc -= xs[h][m] * ldg[cc * 16 + m];
+                    xs[h][cc] = sacc * invd[cc];
+                }
+                if (rr < R) {
+                    const int off = (16 + rr) * kPS;
+#pragma unroll
+                    for (int cc = 0; cc < 16; ++cc) pan[off + cc] = xs[h][cc];
+                } else {
+#pragma unroll
+                    for (int cc = 0; cc < 16; ++cc) yv[16 * kb + cc] = xs[h][cc];
+                }
+            }
+        });
+        wave_sync();
+        // (4) b of the rows below: b_r -= L_r,kb . y_kb
+        static_for<0, 2>([&](auto hc) {
+            constexpr int h = decltype(hc)::value;
+            const int rr = lane + 64 * h;
+            if (rr < R) {
+                float sacc = 0.f;
+#pragma unroll
+                for (int cc = 0; cc < 16; ++cc) sacc += xs[h][cc] * yv[16 * kb + cc];
+                bv[16 * (kb + 1) + rr] -= sacc;
+            }
+        });
+        // (5) L back into the accumulators of block column kb
+        static_for<kb, NB>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            constexpr int q = i * (i + 1) / 2 + kb;
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                acc[q][v] = i == kb ? ldg[(4 * kq + v) * 16 + col]
+                                    : pan[((i - kb) * 16 + 4 * kq + v) * kPS + col];
+        });
+        // (6) trailing update A_ij -= L_i,kb L_j,kb^T on the matrix cores
+        static_for<kb + 1, NB>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            float na[4];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) na[s] = -pan[((i - kb) * 16 + col) * kPS + 4 * s + kq];
+            static_for<kb + 1, i + 1>([&](auto jc) {
+                constexpr int j = decltype(jc)::value;
+                constexpr int q = i * (i + 1) / 2 + j;
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const float bo = pan[((j - kb) * 16 + col) * kPS + 4 * s + kq];
+                    acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(na[s], bo, acc[q], 0, 0, 0);
+                }
+            });
+        });
+        wave_sync();
+    });
+
+    // w = y + z for components lane and lane + 64
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int cc = lane + 64 * h;
+        if (cc < 16 * NB) {
+            float w = yv[cc];
+            if (cc < K) {
+                const Block4 bl = philox4x32_10(row, t, (stream << 24) | (uint32_t)(cc >> 2), 0u, seed);
+                const int m = cc & 3;
+                w += bm_normal_f32(m < 2 ? bl.w0 : bl.w2, m < 2 ? bl.w1 : bl.w3, (m & 1) != 0);
+            }
+            wv[cc] = w;
+        }
+    }
+    wave_sync();
+    // x = L^-T w by block rows from the last
+    static_for<0, NB>([&](auto qc) {
+        constexpr int kb = NB - 1 - decltype(qc)::value;
+        float part = 0.f;
+        static_for<kb + 1, NB>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            constexpr int q = i * (i + 1) / 2 + kb;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) part += acc[q][v] * xv[16 * i + 4 * kq + v];
+        });
+        part += __shfl_xor(part, 16);
+        part += __shfl_xor(part, 32);
+        const float wc = wv[16 * kb + col] - part;
+        // L_kk column col from the accumulators via LDS
+        constexpr int qd = kb * (kb + 1) / 2 + kb;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) ldg[(4 * kq + v) * 16 + col] = acc[qd][v];
+        wave_sync();
+        float d[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) d[r] = ldg[r * 16 + col];
+        const float inv = 1.0f / ldg[col * 16 + col];
+        float accx = 0.f, myx = 0.f;
+        static_for<0, 16>([&](auto rc) {
+            constexpr int r = 15 - decltype(rc)::value;
+            const float xr = readlane_f((wc - accx) * inv, r);
+            if (col == r) myx = xr;
+            if (col < r) accx += d[r] * xr;
+        });
+        if (lane < 16) xv[16 * kb + col] = myx;
+        wave_sync();
+    });
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int cc = lane + 64 * h;
+        if (cc < K) xrow[cc] = xv[cc];
+    }
+}
+
+template <int NB>
+__device__ __forceinline__ void write_partial(const floatx4 (&acc)[NB * (NB + 1) / 2],
+                                              const float (&bacc)[NB], int K, int kq, int col,
+                                              float *__restrict__ dst)
+{
+    const int KK2 = K * (K + 1) / 2;
+    int q = 0;
+#pragma unroll
+    for (int bi = 0; bi < NB; ++bi) {
+#pragma unroll
+        for (int bj = 0; bj <= bi; ++bj) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = 16 * bi + 4 * kq + v, c = 16 * bj + col;
+                if (r < K && c <= r) dst[pk(r, c)] = acc[q][v];
+            }
+            ++q;
+        }
+        const int c = 16 * bi + col;
+        if (kq == 0 && c < K) dst[KK2 + c] = bacc[bi];
+    }
+}
+
+template <int NB, bool BF16>
+__global__ __launch_bounds__(64 * kBigWPB) void row_big(
+    int K, float alpha, const RowItem *__restrict__ items, int64_t n_items,
+    const int32_t *__restrict__ nbr, const float *__restrict__ rc, const void *__restrict__ Y,
+    int ldy, uint32_t y_bytes, const float *__restrict__ Lam, const float *__restrict__ Lmu,
+    float *__restrict__ X, int ldx, float *__restrict__ part, uint64_t seed, uint32_t stream,
+    const uint32_t *__restrict__ ctr)
+{
+    constexpr int NBLK = NB * (NB + 1) / 2;
+    extern __shared__ float smem_f[];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int64_t id = (int64_t)blockIdx.x * kBigWPB + wave;
+    if (id >= n_items) return;
+    float *lds = smem_f + wave * BigLds<NB>::TOTAL;
+    const int col = lane & 15;
+    const int kq = lane >> 4;
+    const RowItem it = items[id];
+    const __amdgpu_buffer_rsrc_t ysrc = make_rsrc(Y, y_bytes);
+    const uint32_t esz = BF16 ? 2u : 4u;
+    uint32_t lane_off[NB];
+#pragma unroll
+    for (int bi = 0; bi < NB; ++bi) lane_off[bi] = 16 * bi + col < K ? (16 * bi + col) * esz : kOOB;
+    floatx4 acc[NBLK];
+#pragma unroll
+    for (int q = 0; q < NBLK; ++q) acc[q] = floatx4{0.f, 0.f, 0.f, 0.f};
+    float bacc[NB];
+#pragma unroll
+    for (int bi = 0; bi < NB; ++bi) bacc[bi] = 0.f;
+    if constexpr (BF16)
+        gram_item_bf16<NB>(it, nbr, rc, ysrc, (uint32_t)ldy * 2u, lane_off, kq, acc, bacc);
+    else
+        gram_item<NB, kBigUnroll>(it, nbr, rc, ysrc, (uint32_t)ldy * 4u, lane_off, kq, acc, bacc);
+#pragma unroll
+    for (int bi = 0; bi < NB; ++bi) {
+        bacc[bi] += __shfl_xor(bacc[bi], 16);
+        bacc[bi] += __shfl_xor(bacc[bi], 32);
+    }
+    if (it.slot >= 0) {
+        write_partial<NB>(acc, bacc, K, kq, col, part + (size_t)it.slot * (K * (K + 1) / 2 + K));
+        return;
+    }
+    float *bv = lds + BigLds<NB>::PAN + BigLds<NB>::LDG + BigLds<NB>::INVD;
+    if (kq == 0)
+#pragma unroll
+        for (int bi = 0; bi < NB; ++bi) {
+            const int c = 16 * bi + col;
+            bv[c] = c < K ? alpha * bacc[bi] + Lmu[c] : 0.f;
+        }
+    wave_sync();
+    blocked_chol_sample<NB>(acc, lds, K, alpha, Lam, (uint32_t)it.row, ctr[0], seed, stream,
+                            X + (size_t)it.row * ldx);
+}
+
+// Split rows: the summed partial Gram (first slot) into the accumulators,
+// then the same factorisation.
+template <int NB>
+__global__ __launch_bounds__(64 * kBigWPB) void row_finish_big(
+    int K, float alpha, const FinishItem *__restrict__ fin, int64_t n_fin,
+    const float *__restrict__ part, const float *__restrict__ Lam, const float *__restrict__ Lmu,
+    float *__restrict__ X, int ldx, uint64_t seed, uint32_t stream,
+    const uint32_t *__restrict__ ctr)
+{
+    constexpr int NBLK = NB * (NB + 1) / 2;
+    extern __shared__ float smem_f[];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int64_t fid = (int64_t)blockIdx.x * kBigWPB + wave;
+    if (fid >= n_fin) return;
+    float *lds = smem_f + wave * BigLds<NB>::TOTAL;
+    const int col = lane & 15;
+    const int kq = lane >> 4;
+    const FinishItem f = fin[fid];
+    const int KK2 = K * (K + 1) / 2;
+    const float *src = part + (size_t)f.first * (KK2 + K);
+    floatx4 acc[NBLK];
+    static_for<0, NB>([&](auto bic) {
+        constexpr int bi = decltype(bic)::value;
+        static_for<0, bi + 1>([&](auto bjc) {
+            constexpr int bj = decltype(bjc)::value;
+            constexpr int q = bi * (bi + 1) / 2 + bj;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = 16 * bi + 4 * kq + v, c = 16 * bj + col;
+                acc[q][v] = (r < K && c < K) ? src[r >= c ? pk(r, c) : pk(c, r)] : 0.f;
+            }
+        });
+    });
+    float *bv = lds + BigLds<NB>::PAN + BigLds<NB>::LDG + BigLds<NB>::INVD;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int c = lane + 64 * h;
+        if (c < 16 * NB) bv[c] = c < K ? alpha * src[KK2 + c] + Lmu[c] : 0.f;
+    }
+    wave_sync();
+    blocked_chol_sample<NB>(acc, lds, K, alpha, Lam, (uint32_t)f.row, ctr[0], seed, stream,
+                            X + (size_t)f.row * ldx);
+}
+
+template <int NB>
+hipError_t launch_big(bpmf_ctx *c, Side &sd, Side &ot, hipStream_t s, int stage)
+{
+    const size_t lds = sizeof(float) * kBigWPB * BigLds<NB>::TOTAL;
+    if (stage == 1) {
+        if (sd.n_fin == 0) return hipSuccess;
+        hipError_t e = launch_part_reduce(c, sd, s);
+        if (e != hipSuccess) return e;
+        const unsigned grid = (unsigned)((sd.n_fin + kBigWPB - 1) / kBigWPB);
+        hipLaunchKernelGGL((row_finish_big<NB>), dim3(grid), dim3(64 * kBigWPB), lds, s, c->K,
+                           (float)c->alpha, sd.fin, sd.n_fin, (const float *)c->part,
+                           (const float *)sd.Lam_w, (const float *)sd.Lmu_w, (float *)sd.X, c->ld,
+                           c->seed, sd.stream_row, c->ctr);
+        return hipGetLastError();
+    }
+    if (sd.n_items == 0) return hipSuccess;
+    const unsigned grid = (unsigned)((sd.n_items + kBigWPB - 1) / kBigWPB);
+    if (c->prec == 2) {
+        const uint32_t y_bytes = (uint32_t)(ot.rows * c->ld * 2);
+        hipLaunchKernelGGL((row_big<NB, true>), dim3(grid), dim3(64 * kBigWPB), lds, s, c->K,
+                           (float)c->alpha, sd.items, sd.n_items, sd.nbr, (const float *)sd.rc,
+                           (const void *)ot.Xbf, c->ld, y_bytes, (const float *)sd.Lam_w,
+                           (const float *)sd.Lmu_w, (float *)sd.X, c->ld, (float *)c->part,
+                           c->seed, sd.stream_row, c->ctr);
+    } else {
+        const uint32_t y_bytes = (uint32_t)(ot.rows * c->ld * 4);
+        hipLaunchKernelGGL((row_big<NB, false>), dim3(grid), dim3(64 * kBigWPB), lds, s, c->K,
+                           (float)c->alpha, sd.items, sd.n_items, sd.nbr, (const float *)sd.rc,
+                           (const void *)ot.X, c->ld, y_bytes, (const float *)sd.Lam_w,
+                           (const float *)sd.Lmu_w, (float *)sd.X, c->ld, (float *)c->part,
+                           c->seed, sd.stream_row, c->ctr);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+// FP32 or BF16-Gram factors, 64 < K <= 128 (BF16-Gram also below), with
+// 32-bit buffer offsets.
+bool big_path_available(const bpmf_ctx *c)
+{
+    if (c->prec == 0 || c->K > 128) return false;
+    if (c->prec == 1 && c->K <= 64) return false;  // the K <= 64 kernels take it
+    for (int s = 0; s < 2; ++s)
+        if ((uint64_t)c->side[s].rows * c->ld * sizeof(float) >= kOOB) return false;
+    return (uint64_t)c->split_threshold * 4u < kOOB;
+}
+
+hipError_t launch_row_big(bpmf_ctx *c, int side_id, hipStream_t s, int stage, bool *handled)
+{
+    *handled = false;
+    if (!big_path_available(c)) return hipSuccess;
+    *handled = true;
+    Side &sd = c->side[side_id];
+    Side &ot = c->side[1 - side_id];
+    switch ((c->K + 15) / 16) {
+    case 1: return launch_big<1>(c, sd, ot, s, stage);
+    case 2: return launch_big<2>(c, sd, ot, s, stage);
+    case 3: return launch_big<3>(c, sd, ot, s, stage);
+    case 4: return launch_big<4>(c, sd, ot, s, stage);
+    case 5: return launch_big<5>(c, sd, ot, s, stage);
+    case 6: return launch_big<6>(c, sd, ot, s, stage);
+    case 7: return launch_big<7>(c, sd, ot, s, stage);
+    default: return launch_big<8>(c, sd, ot, s, stage);
+    }
+}
+
+}  // namespace bpmf

@@ -1,0 +1,146 @@
+// row_common.h -- device helpers shared by the matrix-core row kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "internal.h"
+
+namespace bpmf {
+namespace {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr uint32_t kOOB = 0x40000000u;  // offset beyond every buffer read here
+
+template <int I, int N, typename F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for<I + 1, N>(f);
+    }
+}
+
+__device__ __forceinline__ int pk(int i, int j) { return i * (i + 1) / 2 + j; }
+
+__device__ __forceinline__ float readlane_f(float x, int src)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), src));
+}
+
+// x from lane k of the caller's lane group (the whole wave for RPW = 1,
+// 32 lanes for RPW = 2, 16 lanes for RPW = 4).
+template <int RPW, int k>
+__device__ __forceinline__ float bcast(float x)
+{
+    if constexpr (RPW == 1)
+        return readlane_f(x, k);
+    else if constexpr (RPW == 2)
+        return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(x), k << 5));
+    else
+        return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(x), 0x10 | (k << 5)));
+}
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *p, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+__device__ __forceinline__ uint32_t buf_u32(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    return __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0);
+}
+
+__device__ __forceinline__ float buf_f32(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    return __uint_as_float(buf_u32(r, off));
+}
+
+// Standard normal from Philox words: the pair (wr, wa) gives radius and
+// angle; `sine` picks the sine branch.  FP32 evaluation.
+__device__ __forceinline__ float bm_normal_f32(uint32_t wr, uint32_t wa, bool sine)
+{
+    float lnu;
+    if (wr < 0x80000000u) {
+        const float u = ((float)wr + 0.5f) * 2.3283064365386963e-10f;
+        lnu = logf(u);
+    } else {
+        const float v = ((float)(0xFFFFFFFFu - wr) + 0.5f) * 2.3283064365386963e-10f;  // 1 - u
+        lnu = log1pf(-v);
+    }
+    const float rho = sqrtf(-2.0f * lnu);
+    const float ua = ((float)wa + 0.5f) * 2.3283064365386963e-10f;
+    float sv, cv;
+    sincospif(2.0f * ua, &sv, &cv);
+    return rho * (sine ? sv : cv);
+}
+
+// Gram and rhs of one work item into the accumulators (whole wave), FP32
+// rows on v_mfma_f32_16x16x4_f32: lane l holds component 16*bi + (l % 16)
+// of the neighbour row of rating 4g + l / 16, which is both the A operand of
+// block row bi and the B operand of block column bj.  Software-pipelined:
+// ids of chunk c+2 and rows of chunk c+1 are in flight while chunk c is
+// multiplied.  Ratings past the end read as 0 (buffer range check).
+template <int NB, int kUnroll>
+__device__ __forceinline__ void gram_item(const RowItem &it, const int32_t *__restrict__ nbr,
+                                          const float *__restrict__ rc,
+                                          __amdgpu_buffer_rsrc_t ysrc, uint32_t ldy4,
+                                          const uint32_t (&lane_off)[NB], int kq,
+                                          floatx4 (&acc)[NB * (NB + 1) / 2], float (&bacc)[NB])
+{
+    const uint32_t cnt = (uint32_t)(it.end - it.beg);
+    const __amdgpu_buffer_rsrc_t jsrc = make_rsrc(nbr + it.beg, cnt * 4u);
+    const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(rc + it.beg, cnt * 4u);
+    constexpr int kChunk = 4 * kUnroll;
+    const uint32_t nchunk = (cnt + kChunk - 1) / kChunk;
+    uint32_t jb[2][kUnroll];
+    float yb[2][kUnroll][NB];
+    float rb[2][kUnroll];
+    auto load_ids = [&](int buf, uint32_t ch) {
+#pragma unroll
+        for (int g = 0; g < kUnroll; ++g) jb[buf][g] = buf_u32(jsrc, (ch * kChunk + 4 * g + kq) * 4u);
+    };
+    auto load_rows = [&](int buf, uint32_t ch) {
+#pragma unroll
+        for (int g = 0; g < kUnroll; ++g) {
+            const uint32_t t = ch * kChunk + 4 * g + kq;
+            rb[buf][g] = buf_f32(rsrc, t * 4u);  // 0 past the end
+            const uint32_t base = t < cnt ? jb[buf][g] * ldy4 : kOOB;
+#pragma unroll
+            for (int bi = 0; bi < NB; ++bi) yb[buf][g][bi] = buf_f32(ysrc, base + lane_off[bi]);
+        }
+    };
+    auto compute = [&](int buf) {
+#pragma unroll
+        for (int g = 0; g < kUnroll; ++g) {
+            int q = 0;
+#pragma unroll
+            for (int bi = 0; bi < NB; ++bi) {
+#pragma unroll
+                for (int bj = 0; bj <= bi; ++bj) {
+                    acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(yb[buf][g][bi], yb[buf][g][bj], acc[q], 0, 0, 0);
+                    ++q;
+                }
+                bacc[bi] += rb[buf][g] * yb[buf][g][bi];
+            }
+        }
+    };
+    if (nchunk == 0) return;
+    load_ids(0, 0);
+    load_ids(1, 1);
+    load_rows(0, 0);
+    for (uint32_t ch = 0; ch < nchunk; ch += 2) {
+        load_ids(0, ch + 2);
+        load_rows(1, ch + 1);
+        compute(0);
+        if (ch + 1 >= nchunk) break;
+        load_ids(1, ch + 3);
+        load_rows(0, ch + 2);
+        compute(1);
+    }
+}
+
+}  // namespace
+}  // namespace bpmf

@@ -36,81 +36,17 @@
 
 #include "internal.h"
 #include "rng_device.h"
+#include "row_common.h"
 
 namespace bpmf {
 
 hipError_t prepare_hyper(bpmf_ctx *c);
+hipError_t launch_part_reduce(bpmf_ctx *c, Side &sd, hipStream_t s);
 
 namespace {
 
-typedef float floatx4 __attribute__((ext_vector_type(4)));
-
-constexpr int kUnroll = 4;              // groups of 4 ratings per chunk
-constexpr int kChunk = 4 * kUnroll;     // ratings per pipeline chunk
-constexpr uint32_t kOOB = 0x40000000u;  // offset beyond every buffer read here
-
-template <int I, int N, typename F>
-__device__ __forceinline__ void static_for(F &&f)
-{
-    if constexpr (I < N) {
-        f(std::integral_constant<int, I>{});
-        static_for<I + 1, N>(f);
-    }
-}
-
-__device__ __forceinline__ int pk(int i, int j) { return i * (i + 1) / 2 + j; }
-
-__device__ __forceinline__ float readlane_f(float x, int src)
-{
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), src));
-}
-
-// x from lane k of the caller's lane group (the whole wave for RPW = 1,
-// 32 lanes for RPW = 2, 16 lanes for RPW = 4).
-template <int RPW, int k>
-__device__ __forceinline__ float bcast(float x)
-{
-    if constexpr (RPW == 1)
-        return readlane_f(x, k);
-    else if constexpr (RPW == 2)
-        return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(x), k << 5));
-    else
-        return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(x), 0x10 | (k << 5)));
-}
-
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *p, uint32_t bytes)
-{
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
-}
-
-__device__ __forceinline__ uint32_t buf_u32(__amdgpu_buffer_rsrc_t r, uint32_t off)
-{
-    return __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0);
-}
-
-__device__ __forceinline__ float buf_f32(__amdgpu_buffer_rsrc_t r, uint32_t off)
-{
-    return __uint_as_float(buf_u32(r, off));
-}
-
-// Standard normal from Philox words: the pair (wr, wa) gives radius and
-// angle; `sine` picks the sine branch.  FP32 evaluation.
-__device__ __forceinline__ float bm_normal_f32(uint32_t wr, uint32_t wa, bool sine)
-{
-    float lnu;
-    if (wr < 0x80000000u) {
-        const float u = ((float)wr + 0.5f) * 2.3283064365386963e-10f;
-        lnu = logf(u);
-    } else {
-        const float v = ((float)(0xFFFFFFFFu - wr) + 0.5f) * 2.3283064365386963e-10f;  // 1 - u
-        lnu = log1pf(-v);
-    }
-    const float rho = sqrtf(-2.0f * lnu);
-    const float ua = ((float)wa + 0.5f) * 2.3283064365386963e-10f;
-    float sv, cv;
-    sincospif(2.0f * ua, &sv, &cv);
-    return rho * (sine ? sv : cv);
-}
+constexpr int kUnroll = 4;           // groups of 4 ratings per chunk
+constexpr int kChunk = 4 * kUnroll;  // ratings per pipeline chunk
 
 // Factor and sample one row held column-per-lane: lane c of the group has
 // v[r] = P[r][c] for r < KP (identity outside the leading K x K block) and
@@ -163,65 +99,6 @@ __device__ __forceinline__ float chol_sample_column(float (&v)[KP + 1], int K, i
     return myx;
 }
 
-// Gram and rhs of one work item into the accumulators (whole wave).
-template <int NB>
-__device__ __forceinline__ void gram_item(const RowItem &it, const int32_t *__restrict__ nbr,
-                                          const float *__restrict__ rc,
-                                          __amdgpu_buffer_rsrc_t ysrc, uint32_t ldy4,
-                                          const uint32_t (&lane_off)[NB], int kq,
-                                          floatx4 (&acc)[NB * (NB + 1) / 2], float (&bacc)[NB])
-{
-    const uint32_t cnt = (uint32_t)(it.end - it.beg);
-    const __amdgpu_buffer_rsrc_t jsrc = make_rsrc(nbr + it.beg, cnt * 4u);
-    const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(rc + it.beg, cnt * 4u);
-    const uint32_t nchunk = (cnt + kChunk - 1) / kChunk;
-    uint32_t jb[2][kUnroll];
-    float yb[2][kUnroll][NB];
-    float rb[2][kUnroll];
-    auto load_ids = [&](int buf, uint32_t ch) {
-#pragma unroll
-        for (int g = 0; g < kUnroll; ++g) jb[buf][g] = buf_u32(jsrc, (ch * kChunk + 4 * g + kq) * 4u);
-    };
-    auto load_rows = [&](int buf, uint32_t ch) {
-#pragma unroll
-        for (int g = 0; g < kUnroll; ++g) {
-            const uint32_t t = ch * kChunk + 4 * g + kq;
-            rb[buf][g] = buf_f32(rsrc, t * 4u);  // 0 past the end
-            const uint32_t base = t < cnt ? jb[buf][g] * ldy4 : kOOB;
-#pragma unroll
-            for (int bi = 0; bi < NB; ++bi) yb[buf][g][bi] = buf_f32(ysrc, base + lane_off[bi]);
-        }
-    };
-    auto compute = [&](int buf) {
-#pragma unroll
-        for (int g = 0; g < kUnroll; ++g) {
-            int q = 0;
-#pragma unroll
-            for (int bi = 0; bi < NB; ++bi) {
-#pragma unroll
-                for (int bj = 0; bj <= bi; ++bj) {
-                    acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(yb[buf][g][bi], yb[buf][g][bj], acc[q], 0, 0, 0);
-                    ++q;
-                }
-                bacc[bi] += rb[buf][g] * yb[buf][g][bi];
-            }
-        }
-    };
-    if (nchunk == 0) return;
-    load_ids(0, 0);
-    load_ids(1, 1);
-    load_rows(0, 0);
-    for (uint32_t ch = 0; ch < nchunk; ch += 2) {
-        load_ids(0, ch + 2);
-        load_rows(1, ch + 1);
-        compute(0);
-        if (ch + 1 >= nchunk) break;
-        load_ids(1, ch + 3);
-        load_rows(0, ch + 2);
-        compute(1);
-    }
-}
-
 template <int NB, int RPW, int WPB>
 __global__ __launch_bounds__(64 * WPB) void row_fast_f32(
     int K, float alpha, const RowItem *__restrict__ items, int64_t n_items,
@@ -263,7 +140,7 @@ __global__ __launch_bounds__(64 * WPB) void row_fast_f32(
         float bacc[NB];
 #pragma unroll
         for (int bi = 0; bi < NB; ++bi) bacc[bi] = 0.f;
-        gram_item<NB>(it, nbr, rc, ysrc, ldy4, lane_off, kq, acc, bacc);
+        gram_item<NB, kUnroll>(it, nbr, rc, ysrc, ldy4, lane_off, kq, acc, bacc);
         // sum the rhs over the four rating slots of each 16-lane column
 #pragma unroll
         for (int bi = 0; bi < NB; ++bi) {
@@ -376,7 +253,7 @@ __global__ __launch_bounds__(64 * WPB) void foldin_draw_f32(
         float bacc[NB];
 #pragma unroll
         for (int bi = 0; bi < NB; ++bi) bacc[bi] = 0.f;
-        gram_item<NB>(it, nbr, rc, ysrc, ldy4, lane_off, kq, acc, bacc);
+        gram_item<NB, kUnroll>(it, nbr, rc, ysrc, ldy4, lane_off, kq, acc, bacc);
 #pragma unroll
         for (int bi = 0; bi < NB; ++bi) {
             bacc[bi] += __shfl_xor(bacc[bi], 16);
@@ -476,9 +353,8 @@ template <int NB, int WPB>
 hipError_t launch_finish_f32(bpmf_ctx *c, Side &sd, hipStream_t s)
 {
     if (sd.n_fin == 0) return hipSuccess;
-    const int E = c->K * (c->K + 1) / 2 + c->K;
-    hipLaunchKernelGGL(part_reduce, dim3((unsigned)sd.n_fin, (unsigned)((E + 255) / 256)), dim3(256),
-                       0, s, sd.fin, E, (float *)c->part);
+    hipError_t e = launch_part_reduce(c, sd, s);
+    if (e != hipSuccess) return e;
     const unsigned grid = (unsigned)((sd.n_fin + WPB - 1) / WPB);
     hipLaunchKernelGGL((row_finish_fast<NB, WPB>), dim3(grid), dim3(64 * WPB), 0, s, c->K,
                        (float)c->alpha, sd.fin, sd.n_fin, (const float *)c->part,
@@ -504,6 +380,16 @@ hipError_t launch_f32(bpmf_ctx *c, Side &sd, Side &ot, hipStream_t s)
 }
 
 }  // namespace
+
+// Sum each split row's FP32 partial slots into its first slot.
+hipError_t launch_part_reduce(bpmf_ctx *c, Side &sd, hipStream_t s)
+{
+    if (sd.n_fin == 0) return hipSuccess;
+    const int E = c->K * (c->K + 1) / 2 + c->K;
+    hipLaunchKernelGGL(part_reduce, dim3((unsigned)sd.n_fin, (unsigned)((E + 255) / 256)), dim3(256),
+                       0, s, sd.fin, E, (float *)c->part);
+    return hipGetLastError();
+}
 
 hipError_t launch_foldin_draw(const bpmf_ctx *c, const FoldItem *items, int64_t n_items,
                               const int32_t *nbr, const float *rc, const float *Vring,

@@ -17,6 +17,7 @@
 namespace bpmf {
 hipError_t launch_row_generic(bpmf_ctx *c, int side_id, hipStream_t s, int stage);
 hipError_t launch_row_fast(bpmf_ctx *c, int side_id, hipStream_t s, int stage, bool *handled);
+hipError_t launch_row_big(bpmf_ctx *c, int side_id, hipStream_t s, int stage, bool *handled);
 hipError_t prepare_kernels(bpmf_ctx *c);
 }  // namespace bpmf
 
@@ -146,6 +147,8 @@ hipError_t enqueue_update_stage(bpmf_ctx *c, int side_id, hipStream_t s, int sta
 {
     bool handled = false;
     hipError_t e = launch_row_fast(c, side_id, s, stage, &handled);
+    if (e != hipSuccess) return e;
+    if (!handled) e = launch_row_big(c, side_id, s, stage, &handled);
     if (e != hipSuccess) return e;
     if (!handled) e = launch_row_generic(c, side_id, s, stage);
     if (e != hipSuccess) return e;
