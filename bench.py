@@ -24,6 +24,7 @@ sys.path.insert(0, ROOT)
 import synth  # noqa: E402
 
 PEAK_FP32_TFLOPS = 157.3  # MI355X dense FP32 (matrix cores), TFLOP/s
+PEAK_BF16_TFLOPS = 2500.0  # MI355X dense BF16 (matrix cores), TFLOP/s
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, GB/s
 L2_BYTES = 4 << 20  # one XCD's L2
 
@@ -48,11 +49,36 @@ def algorithmic(K, nnz, rows_finished, rows_written, gather_row_bytes, src_bytes
     K^3/3 + 2K^2 per finished row (Cholesky + two triangular solves).
     Bytes: 8 per rating (neighbour id + rating), the gathered row (K x
     element size) per rating when the gathered factor exceeds one L2, and
-    the written row."""
-    flops = nnz * (K * (K + 1) + 2 * K) + rows_finished * (K ** 3 / 3.0 + 2 * K * K)
+    the written row.  Returns (Gram flops, factorisation flops, bytes)."""
+    gram = nnz * (K * (K + 1) + 2 * K)
+    fact = rows_finished * (K ** 3 / 3.0 + 2 * K * K)
     gather = gather_row_bytes * nnz if src_bytes > L2_BYTES else 0
     byts = 8 * nnz + gather + 4 * K * rows_written
-    return flops, byts
+    return gram, fact, byts
+
+
+def profiled_traffic(workload, K, prec, side):
+    """HBM bytes per launch of the row kernel from the committed rocprofv3
+    counter summaries (FETCH_SIZE and WRITE_SIZE, each scaled by the same
+    counter on a copy of known size), or None when no summary covers this
+    workload or a source file of the kernel changed since it was taken."""
+    import glob
+    import hashlib
+
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*traffic*.md"))):
+        for line in open(path):
+            if not line.startswith("traffic-json: "):
+                continue
+            rec = json.loads(line[len("traffic-json: "):])
+            if (rec["workload"], rec["K"], rec["prec"], rec["side"]) != (workload, K, prec, side):
+                continue
+            h = hashlib.sha256()
+            for f in rec["sources"]:
+                h.update(open(os.path.join(ROOT, f), "rb").read())
+            if h.hexdigest() != rec["sources_sha256"]:
+                return None
+            return int(rec["fetch_bytes"] + rec["write_bytes"])
+    return None
 
 
 def cpu_baseline(r, K, seconds, seed):
@@ -222,6 +248,10 @@ def main():
     names = ["hyper_V", "rows_V", "split_V", "hyper_U", "rows_U", "split_U", "predict"]
     phase = {n: round(float(v), 4) for n, v in zip(names, ph)}
     log("phases (ms): %s" % phase)
+    # row-kernel launch time measured inside the timed sweeps (HIP events on
+    # the kernel's stream, one pair per replay)
+    k_ms = dict(zip(["rows_V", "rows_U"], s.row_kernel_ms()))
+    log("row kernel per launch (ms, timed sweeps): %s" % {k: round(v, 4) for k, v in k_ms.items()})
     esize = 8 if prec == "fp64" else (2 if prec == "bf16" else 4)
     _, ns_u = s.get_plan(bp.SIDE_U)
     _, ns_v = s.get_plan(bp.SIDE_V)
@@ -229,20 +259,27 @@ def main():
         "rows_V": algorithmic(K, r.nnz, r.N - ns_v, r.N, K * esize, r.M * K * esize),
         "rows_U": algorithmic(K, r.nnz, r.M - ns_u, r.M, K * esize, r.N * K * esize),
     }
-    dom = max(cand, key=lambda n: phase[n])
-    flops, byts = cand[dom]
-    sec = phase[dom] / 1000.0
-    t_mfma = flops / (PEAK_FP32_TFLOPS * 1e12)
+    dom = max(cand, key=lambda n: k_ms[n])
+    gram, fact, byts = cand[dom]
+    flops = gram + fact
+    sec = k_ms[dom] / 1000.0
+    # peak of the contraction's own type: in the BF16-Gram mode the Gram runs
+    # at the BF16 peak and the factorisation at the FP32 one (time-weighted)
+    peak = PEAK_FP32_TFLOPS
+    if prec == "bf16":
+        peak = flops / (gram / PEAK_BF16_TFLOPS + fact / PEAK_FP32_TFLOPS)
+    t_mfma = flops / (peak * 1e12)
     t_hbm = byts / (PEAK_HBM_GBS * 1e9)
     if t_hbm > t_mfma:
         roof = {"bound": "hbm", "achieved": round(byts / sec / 1e9, 1), "peak": PEAK_HBM_GBS,
                 "unit": "GB/s"}
     else:
-        roof = {"bound": "mfma", "achieved": round(flops / sec / 1e12, 3), "peak": PEAK_FP32_TFLOPS,
+        roof = {"bound": "mfma", "achieved": round(flops / sec / 1e12, 3), "peak": round(peak, 1),
                 "unit": "TFLOP/s"}
     roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
-    roof["traffic"] = None
-    roof["kernel"] = "row update, side %s (mean of %d launches, %.4f ms)" % (dom[-1], pn, phase[dom])
+    roof["traffic"] = profiled_traffic(r.name, K, prec, dom[-1])
+    roof["kernel"] = "row update, side %s (mean of %d launches in the timed sweeps, %.4f ms)" % (
+        dom[-1], steps, k_ms[dom])
 
     out = {
         "metric": "Gibbs row-updates/s",
@@ -264,6 +301,7 @@ def main():
         "rmse_avg": round(float(avg[-1]), 5),
         "rmse_last": round(float(last[-1]), 5),
         "phase_ms": phase,
+        "row_kernel_ms": {k: round(v, 4) for k, v in k_ms.items()},
         "roofline": roof,
     }
     if not args.no_foldin and prec == "fp32" and K <= 64:

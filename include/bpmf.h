@@ -174,6 +174,15 @@ int bpmf_synchronize(bpmf_ctx *c);
  * bpmf_update_side / bpmf_sample_hyper / bpmf_run_sweeps call. */
 int bpmf_last_time_ms(bpmf_ctx *c, double *ms);
 
+/* Mean device time (ms) of one launch of the row-update kernel (the work
+ * items of the row loops of Algorithm 1, split-row finishing excluded) over
+ * the sweeps of the most recent bpmf_run_sweeps call: ms[0] for the V side,
+ * ms[1] for the U side.  Measured inside the sweep graph with HIP events
+ * recorded on the kernel's own stream just before and after it, one set per
+ * replay (the first 1023 replays and the last).  Caller-owned ms[2].
+ * BPMF_E_INVAL if no sweeps were timed. */
+int bpmf_row_kernel_ms(bpmf_ctx *c, double *ms);
+
 /* ---- Fold-in serving (not a step of Algorithm 1: new users against stored
  * posterior samples; requires BPMF_FP32 and K <= 64) ----
  *

@@ -33,7 +33,7 @@ EXPORTS = [
     "bpmf_run_sweeps", "bpmf_profile_sweeps", "bpmf_predict", "bpmf_get_factor", "bpmf_set_factor",
     "bpmf_get_factor_f64", "bpmf_set_factor_f64", "bpmf_get_hyper", "bpmf_set_hyper",
     "bpmf_get_csc", "bpmf_get_plan", "bpmf_mean_rating", "bpmf_synchronize",
-    "bpmf_last_time_ms", "bpmf_last_error", "bpmf_destroy", "bpmf_store_sample",
+    "bpmf_last_time_ms", "bpmf_row_kernel_ms", "bpmf_last_error", "bpmf_destroy", "bpmf_store_sample",
     "bpmf_foldin_submit", "bpmf_foldin_poll", "bpmf_foldin_drain", "bpmf_foldin_samples",
     "bpmf_foldin_capacity",
 ]
@@ -95,6 +95,7 @@ def lib() -> ctypes.CDLL:
         L.bpmf_mean_rating.restype = dbl
         L.bpmf_synchronize.argtypes = [P]
         L.bpmf_last_time_ms.argtypes = [P, P]
+        L.bpmf_row_kernel_ms.argtypes = [P, P]
         L.bpmf_last_error.argtypes = [P]
         L.bpmf_last_error.restype = ctypes.c_char_p
         L.bpmf_destroy.argtypes = [P]
@@ -308,3 +309,10 @@ class Sampler:
         ms = ctypes.c_double()
         self._check(lib().bpmf_last_time_ms(self._ctx, ctypes.byref(ms)))
         return ms.value
+
+    def row_kernel_ms(self):
+        """Mean per-launch device time (ms) of the row kernel of each side over
+        the replays of the last run_sweeps call: (V side, U side)."""
+        ms = (ctypes.c_double * 2)()
+        self._check(lib().bpmf_row_kernel_ms(self._ctx, ms))
+        return float(ms[0]), float(ms[1])

@@ -102,7 +102,16 @@ struct bpmf_ctx {
     int64_t q_cap = 0;
     // graph of one sweep
     hipGraphExec_t graph = nullptr;
+    hipGraph_t graph_src = nullptr;          // kept: owns the event-record nodes below
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // row-kernel timing inside the graph: external event-record nodes before
+    // and after the row kernel of each side (V start, V end, U start, U end),
+    // re-pointed at a fresh set of events before every replay
+    hipEvent_t tev[4] = {};
+    hipGraphNode_t tnode[4] = {};
+    bool timing_nodes = false;
+    std::vector<hipEvent_t> tpool;           // 4 per sweep of the last run
+    double row_ms[2] = {-1.0, -1.0};         // mean per launch, V and U
     double last_ms = 0;
     std::string err;
     bool sticky = false;

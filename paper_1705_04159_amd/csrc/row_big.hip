@@ -1,11 +1,12 @@
-// row_big.hip -- matrix-core row update for FP32 factors with 64 < K <= 128.
+// row_big.hip -- matrix-core row update with a blocked factorisation: FP32
+// factors with 32 < K <= 128, and every K <= 128 in the BF16-Gram mode.
 //
 // Per row (Algorithm 1's item body with BPMF's conditional):
 //   P = Lambda + alpha sum_j y_j y_j^T,  b = Lambda mu + alpha sum_j r'_j y_j,
 //   P = L L^T,  y = L^-1 b,  x = L^-T (y + z).
 // One wavefront per work item.
 //
-// Gram: FP32 rows on v_mfma_f32_16x16x4_f32 (as for K <= 64), or -- in the
+// Gram: FP32 rows on v_mfma_f32_16x16x4_f32 (as for K <= 32), or -- in the
 // BF16-Gram mode -- BF16 copies of the neighbour rows on
 // v_mfma_f32_16x16x32_bf16, where lane l supplies component 16*bi + (l % 16)
 // of the 8 ratings 8*(l / 16) .. +7 of a 32-rating chunk; both accumulate in
@@ -479,12 +480,12 @@ hipError_t launch_big(bpmf_ctx *c, Side &sd, Side &ot, hipStream_t s, int stage)
 
 }  // namespace
 
-// FP32 or BF16-Gram factors, 64 < K <= 128 (BF16-Gram also below), with
+// FP32 factors with 32 < K <= 128 or BF16-Gram factors with K <= 128, and
 // 32-bit buffer offsets.
 bool big_path_available(const bpmf_ctx *c)
 {
     if (c->prec == 0 || c->K > 128) return false;
-    if (c->prec == 1 && c->K <= 64) return false;  // the K <= 64 kernels take it
+    if (c->prec == 1 && c->K <= 32) return false;  // the column-per-lane kernel takes it
     for (int s = 0; s < 2; ++s)
         if ((uint64_t)c->side[s].rows * c->ld * sizeof(float) >= kOOB) return false;
     return (uint64_t)c->split_threshold * 4u < kOOB;

@@ -1,4 +1,5 @@
-// row_fast.hip -- matrix-core row update for FP32 factors, K <= 64.
+// row_fast.hip -- matrix-core row update for FP32 factors, K <= 64 (sweeps
+// take it up to K = 32, fold-in draws up to 64).
 //
 // Per row (Algorithm 1's item body with BPMF's conditional):
 //   P = Lambda + alpha sum_j y_j y_j^T,  b = Lambda mu + alpha sum_j r'_j y_j,
@@ -436,7 +437,9 @@ bool fast_path_available(const bpmf_ctx *c)
 hipError_t launch_row_fast(bpmf_ctx *c, int side_id, hipStream_t s, int stage, bool *handled)
 {
     *handled = false;
-    if (!fast_path_available(c)) return hipSuccess;
+    // Sweeps use this kernel up to K = 32; above that the blocked
+    // factorisation of the K <= 128 kernel is faster (fold-in keeps it to 64).
+    if (!fast_path_available(c) || c->K > 32) return hipSuccess;
     *handled = true;
     Side &sd = c->side[side_id];
     Side &ot = c->side[1 - side_id];

@@ -27,6 +27,8 @@ namespace {
 
 thread_local std::string g_create_err;
 
+constexpr uint32_t kTimedSweeps = 1024;  // replays with their own timing events
+
 int fail(bpmf_ctx *c, int code, const char *fmt, ...)
 {
     char buf[512];
@@ -189,6 +191,17 @@ hipError_t enqueue_sweep_profiled(bpmf_ctx *c, hipStream_t s, hipEvent_t *ev)
 // overlaps on a second stream: the U draw of sweep t needs only U of sweep
 // t-1, so it runs beside the V update; the V draw of sweep t+1 needs only V
 // of sweep t, so it runs beside the U update.  The sweep ends by advancing t.
+// Row update of one side inside the captured sweep, with external event
+// records around the row kernel (stage 0) for timing.
+hipError_t enqueue_update_timed(bpmf_ctx *c, int side_id, hipStream_t s, hipEvent_t a, hipEvent_t b)
+{
+    hipError_t e;
+    if ((e = hipEventRecordWithFlags(a, s, hipEventRecordExternal)) != hipSuccess) return e;
+    if ((e = enqueue_update_stage(c, side_id, s, 0)) != hipSuccess) return e;
+    if ((e = hipEventRecordWithFlags(b, s, hipEventRecordExternal)) != hipSuccess) return e;
+    return enqueue_update_stage(c, side_id, s, 1);
+}
+
 hipError_t enqueue_sweep(bpmf_ctx *c, hipStream_t s)
 {
     hipError_t e;
@@ -197,13 +210,13 @@ hipError_t enqueue_sweep(bpmf_ctx *c, hipStream_t s)
     if ((e = hipStreamWaitEvent(s2, c->fork_ev[0], 0)) != hipSuccess) return e;
     if ((e = launch_hyper(c, BPMF_SIDE_U, s2, 0)) != hipSuccess) return e;
     if ((e = hipEventRecord(c->fork_ev[1], s2)) != hipSuccess) return e;
-    if ((e = enqueue_update(c, BPMF_SIDE_V, s)) != hipSuccess) return e;
+    if ((e = enqueue_update_timed(c, BPMF_SIDE_V, s, c->tev[0], c->tev[1])) != hipSuccess) return e;
     if ((e = hipStreamWaitEvent(s, c->fork_ev[1], 0)) != hipSuccess) return e;
     if ((e = hipEventRecord(c->fork_ev[2], s)) != hipSuccess) return e;
     if ((e = hipStreamWaitEvent(s2, c->fork_ev[2], 0)) != hipSuccess) return e;
     if ((e = launch_hyper(c, BPMF_SIDE_V, s2, 1)) != hipSuccess) return e;
     if ((e = hipEventRecord(c->fork_ev[1], s2)) != hipSuccess) return e;
-    if ((e = enqueue_update(c, BPMF_SIDE_U, s)) != hipSuccess) return e;
+    if ((e = enqueue_update_timed(c, BPMF_SIDE_U, s, c->tev[2], c->tev[3])) != hipSuccess) return e;
     if ((e = launch_predict_test(c, s)) != hipSuccess) return e;
     if ((e = hipStreamWaitEvent(s, c->fork_ev[1], 0)) != hipSuccess) return e;
     return launch_advance_t(c->ctr, s);
@@ -356,6 +369,7 @@ int bpmf_create(int64_t M, int64_t N, const int64_t *csr_ptr, const int32_t *csr
         for (auto &ev : c->fork_ev) CK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
         CK(hipEventCreate(&c->ev0));
         CK(hipEventCreate(&c->ev1));
+        for (auto &ev : c->tev) CK(hipEventCreate(&ev));
         const size_t es = elem_bytes(c);
         std::vector<int64_t> csr_ptr_v(csr_ptr, csr_ptr + M + 1);
         const std::vector<int64_t> *ptrs[2] = {&csr_ptr_v, &tptr};
@@ -468,6 +482,10 @@ void bpmf_destroy(bpmf_ctx *c)
     foldin_destroy(c);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     if (c->graph) (void)hipGraphExecDestroy(c->graph);
+    if (c->graph_src) (void)hipGraphDestroy(c->graph_src);
+    for (auto &ev : c->tev)
+        if (ev) (void)hipEventDestroy(ev);
+    for (auto &ev : c->tpool) (void)hipEventDestroy(ev);
     for (auto &s : c->side) free_side(s);
     void *ps[] = {c->d_mu0, c->d_W0inv, c->test_row, c->test_col, c->test_val, c->pred_sum,
                   c->rmse_part, c->rmse_hist, c->hyp_part[0], c->hyp_stats[0], c->hyp_scratch[0],
@@ -532,6 +550,30 @@ int bpmf_update_side(bpmf_ctx *c, int32_t side, uint32_t t)
     return timed_end(c);
 }
 
+// The external event-record nodes of the captured sweep (V start, V end,
+// U start, U end), so that each replay can be pointed at its own events.
+static int find_timing_nodes(bpmf_ctx *c)
+{
+    size_t nn = 0;
+    HIPCK(c, hipGraphGetNodes(c->graph_src, nullptr, &nn));
+    std::vector<hipGraphNode_t> nodes(nn);
+    HIPCK(c, hipGraphGetNodes(c->graph_src, nodes.data(), &nn));
+    for (auto &t : c->tnode) t = nullptr;
+    for (hipGraphNode_t nd : nodes) {
+        hipGraphNodeType ty;
+        HIPCK(c, hipGraphNodeGetType(nd, &ty));
+        if (ty != hipGraphNodeTypeEventRecord) continue;
+        hipEvent_t ev = nullptr;
+        HIPCK(c, hipGraphEventRecordNodeGetEvent(nd, &ev));
+        for (int k = 0; k < 4; ++k)
+            if (ev == c->tev[k]) c->tnode[k] = nd;
+    }
+    c->timing_nodes = true;
+    for (auto t : c->tnode)
+        if (!t) c->timing_nodes = false;  // sweeps still run, untimed
+    return BPMF_OK;
+}
+
 int bpmf_run_sweeps(bpmf_ctx *c, uint32_t t0, uint32_t n, double *rmse_avg, double *rmse_last)
 {
     STICKY(c);
@@ -548,6 +590,10 @@ int bpmf_run_sweeps(bpmf_ctx *c, uint32_t t0, uint32_t n, double *rmse_avg, doub
             hipGraphExecDestroy(c->graph);
             c->graph = nullptr;
         }
+        if (c->graph_src) {
+            hipGraphDestroy(c->graph_src);
+            c->graph_src = nullptr;
+        }
     }
     if (!c->graph) {
         hipGraph_t g = nullptr;
@@ -560,19 +606,50 @@ int bpmf_run_sweeps(bpmf_ctx *c, uint32_t t0, uint32_t n, double *rmse_avg, doub
                         hipGetErrorString(e2));
         }
         e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
-        hipGraphDestroy(g);
         if (e != hipSuccess) {
+            hipGraphDestroy(g);
             c->graph = nullptr;
             return fail(c, BPMF_E_DEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
         }
+        c->graph_src = g;
+        if (int r = find_timing_nodes(c)) return r;
     }
+    // one set of four timing events per replay (replays past kTimedSweeps
+    // share the last set, so the mean covers the first kTimedSweeps - 1 and
+    // the final one)
+    const uint32_t n_sets = c->timing_nodes ? std::min<uint32_t>(n, kTimedSweeps) : 0;
+    while (c->tpool.size() < 4 * (size_t)n_sets) {
+        hipEvent_t ev = nullptr;
+        HIPCK(c, hipEventCreate(&ev));
+        c->tpool.push_back(ev);
+    }
+    c->row_ms[0] = c->row_ms[1] = -1.0;
     HIPCK(c, hipEventRecord(c->ev0, c->stream));
     HIPCK(c, launch_set_counter(c->ctr, 0, t0, c->stream));
     HIPCK(c, launch_set_counter(c->ctr, 1, t0, c->stream));
     HIPCK(c, launch_hyper(c, BPMF_SIDE_V, c->stream, 0));
-    for (uint32_t i = 0; i < n; ++i) HIPCK(c, hipGraphLaunch(c->graph, c->stream));
+    for (uint32_t i = 0; i < n; ++i) {
+        if (n_sets) {
+            const size_t set = std::min<uint32_t>(i, n_sets - 1);
+            for (int k = 0; k < 4; ++k)
+                HIPCK(c, hipGraphExecEventRecordNodeSetEvent(c->graph, c->tnode[k],
+                                                             c->tpool[4 * set + k]));
+        }
+        HIPCK(c, hipGraphLaunch(c->graph, c->stream));
+    }
     if (int r = timed_end(c)) return r;
     if (int r = check_hyper_status(c)) return r;
+    double acc[2] = {0.0, 0.0};
+    for (uint32_t q = 0; q < n_sets; ++q)
+        for (int sd = 0; sd < 2; ++sd) {
+            float ms = 0.f;
+            HIPCK(c, hipEventElapsedTime(&ms, c->tpool[4 * q + 2 * sd], c->tpool[4 * q + 2 * sd + 1]));
+            acc[sd] += ms;
+        }
+    if (n_sets) {
+        c->row_ms[0] = acc[0] / n_sets;
+        c->row_ms[1] = acc[1] / n_sets;
+    }
     std::vector<double> h(2 * (size_t)n);
     HIPCK(c, hipMemcpy(h.data(), c->rmse_hist, sizeof(double) * 2 * n, hipMemcpyDeviceToHost));
     for (uint32_t i = 0; i < n; ++i) {
@@ -775,6 +852,15 @@ int bpmf_last_time_ms(bpmf_ctx *c, double *ms)
 {
     if (!c || !ms) return BPMF_E_INVAL;
     *ms = c->last_ms;
+    return BPMF_OK;
+}
+
+int bpmf_row_kernel_ms(bpmf_ctx *c, double *ms)
+{
+    if (!c || !ms) return BPMF_E_INVAL;
+    if (c->row_ms[0] < 0.0) return fail(c, BPMF_E_INVAL, "no timed sweeps (none run, or the graph has no timing nodes)");
+    ms[0] = c->row_ms[0];
+    ms[1] = c->row_ms[1];
     return BPMF_OK;
 }
 

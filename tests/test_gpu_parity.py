@@ -176,8 +176,9 @@ def test_init_factor_matches_oracle(bp, orc, prec):
 # single-step row parity
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("prec,K", [("fp64", 10), ("fp64", 1), ("fp64", 33), ("fp32", 10),
-                                    ("fp32", 32), ("fp32", 64), ("fp32", 100), ("fp32", 7),
-                                    ("bf16", 32), ("bf16", 100)])
+                                    ("fp32", 32), ("fp32", 48), ("fp32", 64), ("fp32", 100),
+                                    ("fp32", 128), ("fp32", 7), ("bf16", 10), ("bf16", 32),
+                                    ("bf16", 100)])
 @pytest.mark.parametrize("side", [0, 1])
 def test_row_update_single_step(bp, orc, prec, K, side):
     r = synth.random_small(40 + K, 700, 300, 20000, min(K, 16), empty_rows=5)
@@ -186,7 +187,8 @@ def test_row_update_single_step(bp, orc, prec, K, side):
     assert err.max() <= TOL[prec], (err.max(), np.argmax(err))
 
 
-@pytest.mark.parametrize("prec,K", [("fp64", 10), ("fp32", 32), ("fp32", 100), ("bf16", 64)])
+@pytest.mark.parametrize("prec,K", [("fp64", 10), ("fp32", 32), ("fp32", 64), ("fp32", 100),
+                                    ("bf16", 64)])
 def test_split_rows_single_step(bp, orc, prec, K):
     """Heavy rows split into segments (fixed-order partial reduction)."""
     r = synth.planted(seed=5, M=600, N=250, nnz=30000, K=min(K, 10), zipf=0.9)
@@ -314,3 +316,28 @@ def test_checkpoint_resume_bitexact(bp):
     assert np.array_equal(full.get_factor(bp.SIDE_V), res.get_factor(bp.SIDE_V))
     full.close()
     res.close()
+
+
+def test_row_kernel_timing_inside_graph(bp):
+    """The per-replay timing events of the sweep graph: positive launch
+    times whose sum stays within the device time of the whole run, and no
+    effect on the chain."""
+    r = synth.random_small(13, 900, 400, 30000, 8)
+    a = bp.Sampler(r, 16, prec="fp32", seed=4)
+    with pytest.raises(bp.BPMFError):
+        a.row_kernel_ms()  # nothing timed yet
+    n = 6
+    a.run_sweeps(1, n)
+    kv, ku = a.row_kernel_ms()
+    total = a.last_time_ms()
+    assert kv > 0 and ku > 0
+    assert n * (kv + ku) <= total
+    b = bp.Sampler(r, 16, prec="fp32", seed=4)
+    for t in range(1, n + 1):
+        b.sample_hyper(bp.SIDE_V, t)
+        b.update_side(bp.SIDE_V, t)
+        b.sample_hyper(bp.SIDE_U, t)
+        b.update_side(bp.SIDE_U, t)
+    assert np.array_equal(a.get_factor(bp.SIDE_U), b.get_factor(bp.SIDE_U))
+    a.close()
+    b.close()
