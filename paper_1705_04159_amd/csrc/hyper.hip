@@ -104,7 +104,7 @@ __global__ __launch_bounds__(256) void hyper_reduce(int E, int nblk, const doubl
                                                    double *__restrict__ stats)
 {
     const int lane = threadIdx.x & 63;
-    const int e = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int e = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (e >= E) return;
     double s = 0.0;
     for (int b = lane; b < nblk; b += 64) s += part[(size_t)b * E + e];

@@ -355,7 +355,7 @@ __global__ __launch_bounds__(64 * kBigWPB) void row_big(
     constexpr int NBLK = NB * (NB + 1) / 2;
     extern __shared__ float smem_f[];
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
     const int64_t id = (int64_t)blockIdx.x * kBigWPB + wave;
     if (id >= n_items) return;
     float *lds = smem_f + wave * BigLds<NB>::TOTAL;
@@ -410,7 +410,7 @@ __global__ __launch_bounds__(64 * kBigWPB) void row_finish_big(
     constexpr int NBLK = NB * (NB + 1) / 2;
     extern __shared__ float smem_f[];
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
     const int64_t fid = (int64_t)blockIdx.x * kBigWPB + wave;
     if (fid >= n_fin) return;
     float *lds = smem_f + wave * BigLds<NB>::TOTAL;

@@ -115,7 +115,7 @@ __global__ __launch_bounds__(64 * WPB) void row_fast_f32(
     constexpr int REGION = KP * LDP + KP;
     extern __shared__ float smem_f[];
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
     const int64_t first = ((int64_t)blockIdx.x * WPB + wave) * RPW;
     if (first >= n_items) return;
     float *Ps = smem_f + wave * RPW * REGION;
@@ -228,7 +228,7 @@ __global__ __launch_bounds__(64 * WPB) void foldin_draw_f32(
     constexpr int REGION = KP * LDP + KP;
     extern __shared__ float smem_f[];
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
     const int64_t first = ((int64_t)blockIdx.x * WPB + wave) * RPW;
     if (first >= n_items) return;
     float *Ps = smem_f + wave * RPW * REGION;
@@ -334,7 +334,7 @@ __global__ __launch_bounds__(64 * WPB) void row_finish_fast(
 {
     constexpr int KP = 16 * NB;
     const int c = threadIdx.x & 63;
-    const int64_t fid = (int64_t)blockIdx.x * WPB + (threadIdx.x >> 6);
+    const int64_t fid = (int64_t)blockIdx.x * WPB + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (fid >= n_fin) return;
     const FinishItem f = fin[fid];
     const int KK2 = K * (K + 1) / 2;
