@@ -145,6 +145,14 @@ hipError_t launch_to_bf16(bpmf_ctx *c, int side_id, hipStream_t s);
 size_t row_generic_lds_bytes(int K, int prec);
 // Fold-in kernels (FP32 factors, K <= 64).
 bool fast_path_available(const bpmf_ctx *c);
+// Row kernel for FP32 with 32 < K <= 128 and BF16-Gram with K <= 128.
+bool big_path_available(const bpmf_ctx *c);
+// Elements of one split-row partial slot: K(K+1)/2 + K packed for the
+// column-per-lane and generic kernels, the accumulator image of the blocked
+// kernel otherwise.
+int64_t part_slot_elems(const bpmf_ctx *c);
+// Sum each split row's partial slots (E elements each) into its first slot.
+hipError_t launch_part_reduce(bpmf_ctx *c, Side &sd, hipStream_t s, int64_t E);
 hipError_t launch_foldin_draw(const bpmf_ctx *c, const FoldItem *items, int64_t n_items,
                               const int32_t *nbr, const float *rc, const float *Vring,
                               const float *Lam_ring, const float *Lmu_ring, const uint64_t *req_ids,

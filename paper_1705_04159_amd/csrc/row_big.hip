@@ -15,7 +15,7 @@
 // Factorisation: blocked right-looking Cholesky with 16x16 blocks, the
 // trailing matrix kept in the MFMA accumulators.  For each block column kb:
 // the column goes to LDS; the diagonal block is factored column-per-lane
-// (16 lanes, pivot columns broadcast by v_readlane); every row below it,
+// (16 lanes, pivot columns broadcast within each 16-lane row by DPP); every row below it,
 // and b's segment as one extra row, is solved against L_kk^T (one row per
 // lane; L_kk read by broadcast from LDS), which also yields y_kb = L_kk^-1 b_kb
 // and lets each row update b; the solved panel returns to the accumulators
@@ -32,7 +32,6 @@
 
 namespace bpmf {
 
-hipError_t launch_part_reduce(bpmf_ctx *c, Side &sd, hipStream_t s);
 
 namespace {
 
@@ -40,16 +39,23 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kBigWPB = 2;     // waves per workgroup (independent)
-constexpr int kBigUnroll = 2;  // FP32 Gram: groups of 4 ratings per chunk
 constexpr int kPS = 17;        // panel row stride (floats)
+
+// Waves per SIMD the register allocation must allow (left alone, the
+// compiler trades occupancy for unrolled loads and drops to one wave).
+template <int NB>
+constexpr int big_waves()
+{
+    return NB <= 3 ? 4 : (NB == 4 ? 3 : 2);
+}
 
 template <int NB>
 struct BigLds {
     static constexpr int PAN = NB * 16 * kPS;  // block column kb, rows of all blocks below
     static constexpr int LDG = 256;            // L_kk, row-major 16 x 16
     static constexpr int INVD = 16;            // 1 / L_kk[c][c]
-    static constexpr int VEC = 128;            // b, y, w, x
-    static constexpr int TOTAL = PAN + LDG + INVD + 4 * VEC;
+    static constexpr int VEC = 128;            // b (becomes y), w, x
+    static constexpr int TOTAL = PAN + LDG + INVD + 3 * VEC;
 };
 
 __device__ __forceinline__ void wave_sync()
@@ -120,6 +126,10 @@ __device__ __forceinline__ void gram_item_bf16(const RowItem &it, const int32_t 
 
 // Blocked factorisation and draw for one row held in the accumulators (raw
 // Gram) and b in LDS (b = alpha * rhs + Lambda mu already).  Writes x_c.
+//
+// Register budget: the accumulators (nb(nb+1)/2 x 4) plus a few dozen
+// temporaries; every step works through LDS with a small working set so
+// that two waves fit per SIMD at K = 100.
 template <int NB>
 __device__ __forceinline__ void blocked_chol_sample(floatx4 (&acc)[NB * (NB + 1) / 2], float *lds,
                                                     int K, float alpha,
@@ -132,114 +142,106 @@ __device__ __forceinline__ void blocked_chol_sample(floatx4 (&acc)[NB * (NB + 1)
     float *ldg = pan + L::PAN;
     float *invd = ldg + L::LDG;
     float *bv = invd + L::INVD;
-    float *yv = bv + L::VEC;
-    float *wv = yv + L::VEC;
+    float *wv = bv + L::VEC;
     float *xv = wv + L::VEC;
     const int lane = threadIdx.x & 63;
     const int col = lane & 15;
     const int kq = lane >> 4;
 
-    // P = alpha G + Lambda; identity on the padding
-    static_for<0, NB>([&](auto bic) {
-        constexpr int bi = decltype(bic)::value;
-        static_for<0, bi + 1>([&](auto bjc) {
-            constexpr int bj = decltype(bjc)::value;
-            constexpr int q = bi * (bi + 1) / 2 + bj;
+    // The accumulators hold the negated trailing matrix T = -(alpha G -
+    // sum_k L_ik L_jk^T), so that the trailing updates T_ij += L_ik L_jk^T
+    // take the panel as both MFMA operands.  The prior of block column kb is
+    // added when kb is reached (the updates commute with the addition), one
+    // block column of loads at a time.
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int r = 16 * bi + 4 * kq + v, c = 16 * bj + col;
-                const float prior = (r < K && c < K) ? Lam[r * K + c] : (r == c ? 1.f : 0.f);
-                acc[q][v] = alpha * acc[q][v] + prior;
-            }
-        });
-    });
+    for (int q = 0; q < NB * (NB + 1) / 2; ++q)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[q][v] *= -alpha;
 
     static_for<0, NB>([&](auto kbc) {
         constexpr int kb = decltype(kbc)::value;
         constexpr int R = 16 * (NB - 1 - kb);  // panel rows below the diagonal block
-        // (1) block column kb to LDS
+        // (1) prior of block column kb (identity on the padding), then the
+        // block column to LDS: pan row 16 (i - kb) + r holds row r of block i
+        __builtin_amdgcn_sched_barrier(0);
         static_for<kb, NB>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
             constexpr int q = i * (i + 1) / 2 + kb;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) pan[((i - kb) * 16 + 4 * kq + v) * kPS + col] = acc[q][v];
+            for (int v = 0; v < 4; ++v) {
+                const int r = 16 * i + 4 * kq + v, c = 16 * kb + col;
+                const float prior = (r < K && c < K) ? Lam[r * K + c] : (r == c ? 1.f : 0.f);
+                pan[((i - kb) * 16 + 4 * kq + v) * kPS + col] = prior - acc[q][v];
+            }
         });
         wave_sync();
-        // (2) diagonal block, column-per-lane on 16 lanes (the other lanes
-        // compute copies)
+        // (2) diagonal block column-per-lane (lane col holds column col; the
+        // four lane groups compute copies), with b's segment as an extra
+        // row so that the elimination also yields y_kb = L_kk^-1 b_kb
         {
             float d[16];
 #pragma unroll
             for (int r = 0; r < 16; ++r) d[r] = pan[r * kPS + col];
+            float db = bv[16 * kb + col];
             float mydiag = 1.f;
             static_for<0, 16>([&](auto kc) {
                 constexpr int k = decltype(kc)::value;
-                const float dk = readlane_f(d[k], k);
+                const float dk = bcast16<k>(d[k]);
                 if (col == k) mydiag = dk;
                 const float f = col > k ? d[k] * __builtin_amdgcn_rcpf(dk) : 0.f;
-                float prk[16];
                 static_for<k + 1, 16>([&](auto rc) {
                     constexpr int r = decltype(rc)::value;
-                    prk[r] = readlane_f(d[r], k);
+                    d[r] -= f * bcast16<k>(d[r]);
                 });
-                static_for<k + 1, 16>([&](auto rc) {
-                    constexpr int r = decltype(rc)::value;
-                    d[r] -= f * prk[r];
-                });
+                db -= f * bcast16<k>(db);
             });
             const float inv_s = __builtin_amdgcn_rsqf(mydiag);
-            if (lane < 16) {
+            if (kq == 0) {
 #pragma unroll
                 for (int r = 0; r < 16; ++r) ldg[r * 16 + col] = r >= col ? d[r] * inv_s : 0.f;
                 invd[col] = inv_s;
+                bv[16 * kb + col] = db * inv_s;  // y_kb
             }
         }
         wave_sync();
-        // (3) rows below, and b's segment as row R: solve x L_kk^T = a
-        float xs[2][16];
-        static_for<0, 2>([&](auto hc) {
-            constexpr int h = decltype(hc)::value;
-            const int rr = lane + 64 * h;
-            if (rr <= R) {
-                float a[16];
-                if (rr < R) {
-                    const int off = (16 + rr) * kPS;
+        // (3) rows below: solve x L_kk^T = a (one row per lane), store L_ik,
+        // and fold the row into b: b_r -= L_r,kb . y_kb
+        if constexpr (R > 0) {
+            for (int rr = lane; rr < R; rr += 64) {
+                float x[16];
+                const float *arow = pan + (16 + rr) * kPS;
 #pragma unroll
-                    for (int cc = 0; cc < 16; ++cc) a[cc] = pan[off + cc];
-                } else {
-#pragma unroll
-                    for (int cc = 0; cc < 16; ++cc) a[cc] = bv[16 * kb + cc];
-                }
+                for (int cc = 0; cc < 16; ++cc) x[cc] = arow[cc];
 #pragma unroll
                 for (int cc = 0; cc < 16; ++cc) {
-                    float sacc = a[cc];
+                    const float4 *lrow = reinterpret_cast<const float4 *>(ldg + cc * 16);
+                    float sacc = x[cc];
 #pragma unroll
-                    for (int m = 0; m < cc; ++m) sacc -= xs[h][m] * ldg[cc * 16 + m];
-                    xs[h][cc] = sacc * invd[cc];
+                    for (int m4 = 0; m4 < (cc + 3) / 4; ++m4) {
+                        const float4 l4 = lrow[m4];
+                        if (4 * m4 + 0 < cc) sacc -= x[4 * m4 + 0] * l4.x;
+                        if (4 * m4 + 1 < cc) sacc -= x[4 * m4 + 1] * l4.y;
+                        if (4 * m4 + 2 < cc) sacc -= x[4 * m4 + 2] * l4.z;
+                        if (4 * m4 + 3 < cc) sacc -= x[4 * m4 + 3] * l4.w;
+                    }
+                    x[cc] = sacc * invd[cc];
                 }
-                if (rr < R) {
-                    const int off = (16 + rr) * kPS;
+                float bd = 0.f;
+                const float4 *y4 = reinterpret_cast<const float4 *>(bv + 16 * kb);
 #pragma unroll
-                    for (int cc = 0; cc < 16; ++cc) pan[off + cc] = xs[h][cc];
-                } else {
-#pragma unroll
-                    for (int cc = 0; cc < 16; ++cc) yv[16 * kb + cc] = xs[h][cc];
+                for (int m4 = 0; m4 < 4; ++m4) {
+                    const float4 yy = y4[m4];
+                    bd += x[4 * m4] * yy.x + x[4 * m4 + 1] * yy.y + x[4 * m4 + 2] * yy.z +
+                          x[4 * m4 + 3] * yy.w;
                 }
+                bv[16 * (kb + 1) + rr] -= bd;
+                float *wrow = pan + (16 + rr) * kPS;
+#pragma unroll
+                for (int cc = 0; cc < 16; ++cc) wrow[cc] = x[cc];
             }
-        });
+        }
         wave_sync();
-        // (4) b of the rows below: b_r -= L_r,kb . y_kb
-        static_for<0, 2>([&](auto hc) {
-            constexpr int h = decltype(hc)::value;
-            const int rr = lane + 64 * h;
-            if (rr < R) {
-                float sacc = 0.f;
-#pragma unroll
-                for (int cc = 0; cc < 16; ++cc) sacc += xs[h][cc] * yv[16 * kb + cc];
-                bv[16 * (kb + 1) + rr] -= sacc;
-            }
-        });
-        // (5) L back into the accumulators of block column kb
+        // (4) L of block column kb back into its accumulators
         static_for<kb, NB>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
             constexpr int q = i * (i + 1) / 2 + kb;
@@ -248,22 +250,27 @@ __device__ __forceinline__ void blocked_chol_sample(floatx4 (&acc)[NB * (NB + 1)
                 acc[q][v] = i == kb ? ldg[(4 * kq + v) * 16 + col]
                                     : pan[((i - kb) * 16 + 4 * kq + v) * kPS + col];
         });
-        // (6) trailing update A_ij -= L_i,kb L_j,kb^T on the matrix cores
-        static_for<kb + 1, NB>([&](auto ic) {
-            constexpr int i = decltype(ic)::value;
-            float na[4];
+        // (5) trailing update T_ij += L_i,kb L_j,kb^T on the matrix cores:
+        // lane (c, g) supplies L_i,kb[c][4s + g] for k-step s, which is the
+        // A operand of block row i and the B operand of block column i
+        if constexpr (R > 0) {
+            float op[NB][4];
+            static_for<kb + 1, NB>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
 #pragma unroll
-            for (int s = 0; s < 4; ++s) na[s] = -pan[((i - kb) * 16 + col) * kPS + 4 * s + kq];
-            static_for<kb + 1, i + 1>([&](auto jc) {
-                constexpr int j = decltype(jc)::value;
-                constexpr int q = i * (i + 1) / 2 + j;
-#pragma unroll
-                for (int s = 0; s < 4; ++s) {
-                    const float bo = pan[((j - kb) * 16 + col) * kPS + 4 * s + kq];
-                    acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(na[s], bo, acc[q], 0, 0, 0);
-                }
+                for (int s4 = 0; s4 < 4; ++s4) op[i][s4] = pan[((i - kb) * 16 + col) * kPS + 4 * s4 + kq];
             });
-        });
+            static_for<kb + 1, NB>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                static_for<kb + 1, i + 1>([&](auto jc) {
+                    constexpr int j = decltype(jc)::value;
+                    constexpr int q = i * (i + 1) / 2 + j;
+#pragma unroll
+                    for (int s4 = 0; s4 < 4; ++s4)
+                        acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(op[i][s4], op[j][s4], acc[q], 0, 0, 0);
+                });
+            });
+        }
         wave_sync();
     });
 
@@ -272,7 +279,7 @@ __device__ __forceinline__ void blocked_chol_sample(floatx4 (&acc)[NB * (NB + 1)
     for (int h = 0; h < 2; ++h) {
         const int cc = lane + 64 * h;
         if (cc < 16 * NB) {
-            float w = yv[cc];
+            float w = bv[cc];
             if (cc < K) {
                 const Block4 bl = philox4x32_10(row, t, (stream << 24) | (uint32_t)(cc >> 2), 0u, seed);
                 const int m = cc & 3;
@@ -307,7 +314,7 @@ __device__ __forceinline__ void blocked_chol_sample(floatx4 (&acc)[NB * (NB + 1)
         float accx = 0.f, myx = 0.f;
         static_for<0, 16>([&](auto rc) {
             constexpr int r = 15 - decltype(rc)::value;
-            const float xr = readlane_f((wc - accx) * inv, r);
+            const float xr = bcast16<r>((wc - accx) * inv);
             if (col == r) myx = xr;
             if (col < r) accx += d[r] * xr;
         });
@@ -321,32 +328,37 @@ __device__ __forceinline__ void blocked_chol_sample(floatx4 (&acc)[NB * (NB + 1)
     }
 }
 
+// Partial sums of a segment of a split row: the accumulator image (block q,
+// lane l, value v at (64 q + l) 4 + v; zero on the padding) followed by the
+// rhs (component c at 64 nb(nb+1)/2 ... + c), so stores and loads are whole
+// float4 per lane.
 template <int NB>
-__device__ __forceinline__ void write_partial(const floatx4 (&acc)[NB * (NB + 1) / 2],
-                                              const float (&bacc)[NB], int K, int kq, int col,
-                                              float *__restrict__ dst)
+constexpr int64_t big_slot_elems()
 {
-    const int KK2 = K * (K + 1) / 2;
-    int q = 0;
-#pragma unroll
-    for (int bi = 0; bi < NB; ++bi) {
-#pragma unroll
-        for (int bj = 0; bj <= bi; ++bj) {
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int r = 16 * bi + 4 * kq + v, c = 16 * bj + col;
-                if (r < K && c <= r) dst[pk(r, c)] = acc[q][v];
-            }
-            ++q;
-        }
-        const int c = 16 * bi + col;
-        if (kq == 0 && c < K) dst[KK2 + c] = bacc[bi];
-    }
+    return (int64_t)NB * (NB + 1) / 2 * 256 + 16 * NB;
 }
 
-template <int NB, bool BF16>
-__global__ __launch_bounds__(64 * kBigWPB) void row_big(
-    int K, float alpha, const RowItem *__restrict__ items, int64_t n_items,
+template <int NB>
+__device__ __forceinline__ void write_partial(const floatx4 (&acc)[NB * (NB + 1) / 2],
+                                              const float (&bacc)[NB], int kq, int col,
+                                              float *__restrict__ dst)
+{
+    constexpr int NBLK = NB * (NB + 1) / 2;
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int q = 0; q < NBLK; ++q) reinterpret_cast<floatx4 *>(dst)[q * 64 + lane] = acc[q];
+    if (kq == 0)
+#pragma unroll
+        for (int bi = 0; bi < NB; ++bi) dst[NBLK * 256 + 16 * bi + col] = bacc[bi];
+}
+
+// SEG: the work items are segments of split rows and only their partial
+// sums are written; otherwise they are whole rows, factored and sampled.
+// (Two instantiations keep the partial path's registers out of the
+// factorisation's budget.)
+template <int NB, bool BF16, bool SEG>
+__global__ __launch_bounds__(64 * kBigWPB, big_waves<NB>()) void row_big(
+    int K, float alpha, const RowItem *__restrict__ items, int64_t item0, int64_t n_items,
     const int32_t *__restrict__ nbr, const float *__restrict__ rc, const void *__restrict__ Y,
     int ldy, uint32_t y_bytes, const float *__restrict__ Lam, const float *__restrict__ Lmu,
     float *__restrict__ X, int ldx, float *__restrict__ part, uint64_t seed, uint32_t stream,
@@ -356,9 +368,8 @@ __global__ __launch_bounds__(64 * kBigWPB) void row_big(
     extern __shared__ float smem_f[];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
-    const int64_t id = (int64_t)blockIdx.x * kBigWPB + wave;
+    const int64_t id = item0 + (int64_t)blockIdx.x * kBigWPB + wave;
     if (id >= n_items) return;
-    float *lds = smem_f + wave * BigLds<NB>::TOTAL;
     const int col = lane & 15;
     const int kq = lane >> 4;
     const RowItem it = items[id];
@@ -376,32 +387,33 @@ __global__ __launch_bounds__(64 * kBigWPB) void row_big(
     if constexpr (BF16)
         gram_item_bf16<NB>(it, nbr, rc, ysrc, (uint32_t)ldy * 2u, lane_off, kq, acc, bacc);
     else
-        gram_item<NB, kBigUnroll>(it, nbr, rc, ysrc, (uint32_t)ldy * 4u, lane_off, kq, acc, bacc);
+        gram_item<NB>(it, nbr, rc, ysrc, (uint32_t)ldy * 4u, lane_off, kq, acc, bacc);
 #pragma unroll
     for (int bi = 0; bi < NB; ++bi) {
         bacc[bi] += __shfl_xor(bacc[bi], 16);
         bacc[bi] += __shfl_xor(bacc[bi], 32);
     }
-    if (it.slot >= 0) {
-        write_partial<NB>(acc, bacc, K, kq, col, part + (size_t)it.slot * (K * (K + 1) / 2 + K));
-        return;
-    }
-    float *bv = lds + BigLds<NB>::PAN + BigLds<NB>::LDG + BigLds<NB>::INVD;
-    if (kq == 0)
+    if constexpr (SEG) {
+        write_partial<NB>(acc, bacc, kq, col, part + (size_t)it.slot * big_slot_elems<NB>());
+    } else {
+        float *lds = smem_f + wave * BigLds<NB>::TOTAL;
+        float *bv = lds + BigLds<NB>::PAN + BigLds<NB>::LDG + BigLds<NB>::INVD;
+        if (kq == 0)
 #pragma unroll
-        for (int bi = 0; bi < NB; ++bi) {
-            const int c = 16 * bi + col;
-            bv[c] = c < K ? alpha * bacc[bi] + Lmu[c] : 0.f;
-        }
-    wave_sync();
-    blocked_chol_sample<NB>(acc, lds, K, alpha, Lam, (uint32_t)it.row, ctr[0], seed, stream,
-                            X + (size_t)it.row * ldx);
+            for (int bi = 0; bi < NB; ++bi) {
+                const int c = 16 * bi + col;
+                bv[c] = c < K ? alpha * bacc[bi] + Lmu[c] : 0.f;
+            }
+        wave_sync();
+        blocked_chol_sample<NB>(acc, lds, K, alpha, Lam, (uint32_t)it.row, ctr[0], seed, stream,
+                                X + (size_t)it.row * ldx);
+    }
 }
 
 // Split rows: the summed partial Gram (first slot) into the accumulators,
 // then the same factorisation.
 template <int NB>
-__global__ __launch_bounds__(64 * kBigWPB) void row_finish_big(
+__global__ __launch_bounds__(64 * kBigWPB, big_waves<NB>()) void row_finish_big(
     int K, float alpha, const FinishItem *__restrict__ fin, int64_t n_fin,
     const float *__restrict__ part, const float *__restrict__ Lam, const float *__restrict__ Lmu,
     float *__restrict__ X, int ldx, uint64_t seed, uint32_t stream,
@@ -417,26 +429,15 @@ __global__ __launch_bounds__(64 * kBigWPB) void row_finish_big(
     const int col = lane & 15;
     const int kq = lane >> 4;
     const FinishItem f = fin[fid];
-    const int KK2 = K * (K + 1) / 2;
-    const float *src = part + (size_t)f.first * (KK2 + K);
+    const float *src = part + (size_t)f.first * big_slot_elems<NB>();
     floatx4 acc[NBLK];
-    static_for<0, NB>([&](auto bic) {
-        constexpr int bi = decltype(bic)::value;
-        static_for<0, bi + 1>([&](auto bjc) {
-            constexpr int bj = decltype(bjc)::value;
-            constexpr int q = bi * (bi + 1) / 2 + bj;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int r = 16 * bi + 4 * kq + v, c = 16 * bj + col;
-                acc[q][v] = (r < K && c < K) ? src[r >= c ? pk(r, c) : pk(c, r)] : 0.f;
-            }
-        });
-    });
+    for (int q = 0; q < NBLK; ++q) acc[q] = reinterpret_cast<const floatx4 *>(src)[q * 64 + lane];
     float *bv = lds + BigLds<NB>::PAN + BigLds<NB>::LDG + BigLds<NB>::INVD;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const int c = lane + 64 * h;
-        if (c < 16 * NB) bv[c] = c < K ? alpha * src[KK2 + c] + Lmu[c] : 0.f;
+        if (c < 16 * NB) bv[c] = c < K ? alpha * src[NBLK * 256 + c] + Lmu[c] : 0.f;
     }
     wave_sync();
     blocked_chol_sample<NB>(acc, lds, K, alpha, Lam, (uint32_t)f.row, ctr[0], seed, stream,
@@ -449,7 +450,7 @@ hipError_t launch_big(bpmf_ctx *c, Side &sd, Side &ot, hipStream_t s, int stage)
     const size_t lds = sizeof(float) * kBigWPB * BigLds<NB>::TOTAL;
     if (stage == 1) {
         if (sd.n_fin == 0) return hipSuccess;
-        hipError_t e = launch_part_reduce(c, sd, s);
+        hipError_t e = launch_part_reduce(c, sd, s, big_slot_elems<NB>());
         if (e != hipSuccess) return e;
         const unsigned grid = (unsigned)((sd.n_fin + kBigWPB - 1) / kBigWPB);
         hipLaunchKernelGGL((row_finish_big<NB>), dim3(grid), dim3(64 * kBigWPB), lds, s, c->K,
@@ -458,22 +459,26 @@ hipError_t launch_big(bpmf_ctx *c, Side &sd, Side &ot, hipStream_t s, int stage)
                            c->seed, sd.stream_row, c->ctr);
         return hipGetLastError();
     }
-    if (sd.n_items == 0) return hipSuccess;
-    const unsigned grid = (unsigned)((sd.n_items + kBigWPB - 1) / kBigWPB);
-    if (c->prec == 2) {
-        const uint32_t y_bytes = (uint32_t)(ot.rows * c->ld * 2);
-        hipLaunchKernelGGL((row_big<NB, true>), dim3(grid), dim3(64 * kBigWPB), lds, s, c->K,
-                           (float)c->alpha, sd.items, sd.n_items, sd.nbr, (const float *)sd.rc,
-                           (const void *)ot.Xbf, c->ld, y_bytes, (const float *)sd.Lam_w,
+    // segments of split rows (items [0, n_slots)), then whole rows
+    const int64_t n_seg = sd.n_slots, n_rows = sd.n_items - sd.n_slots;
+    const bool bf = c->prec == 2;
+    const void *ysrc = bf ? (const void *)ot.Xbf : (const void *)ot.X;
+    const uint32_t y_bytes = (uint32_t)(ot.rows * c->ld * (bf ? 2 : 4));
+    auto go = [&](auto kern, int64_t item0, int64_t count, size_t lds_bytes) {
+        if (count <= 0) return;
+        const unsigned grid = (unsigned)((count + kBigWPB - 1) / kBigWPB);
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * kBigWPB), lds_bytes, s, c->K,
+                           (float)c->alpha, sd.items, item0, item0 + count, sd.nbr,
+                           (const float *)sd.rc, ysrc, c->ld, y_bytes, (const float *)sd.Lam_w,
                            (const float *)sd.Lmu_w, (float *)sd.X, c->ld, (float *)c->part,
                            c->seed, sd.stream_row, c->ctr);
+    };
+    if (bf) {
+        go(row_big<NB, true, true>, 0, n_seg, 0);
+        go(row_big<NB, true, false>, n_seg, n_rows, lds);
     } else {
-        const uint32_t y_bytes = (uint32_t)(ot.rows * c->ld * 4);
-        hipLaunchKernelGGL((row_big<NB, false>), dim3(grid), dim3(64 * kBigWPB), lds, s, c->K,
-                           (float)c->alpha, sd.items, sd.n_items, sd.nbr, (const float *)sd.rc,
-                           (const void *)ot.X, c->ld, y_bytes, (const float *)sd.Lam_w,
-                           (const float *)sd.Lmu_w, (float *)sd.X, c->ld, (float *)c->part,
-                           c->seed, sd.stream_row, c->ctr);
+        go(row_big<NB, false, true>, 0, n_seg, 0);
+        go(row_big<NB, false, false>, n_seg, n_rows, lds);
     }
     return hipGetLastError();
 }
@@ -489,6 +494,15 @@ bool big_path_available(const bpmf_ctx *c)
     for (int s = 0; s < 2; ++s)
         if ((uint64_t)c->side[s].rows * c->ld * sizeof(float) >= kOOB) return false;
     return (uint64_t)c->split_threshold * 4u < kOOB;
+}
+
+int64_t part_slot_elems(const bpmf_ctx *c)
+{
+    if (big_path_available(c)) {
+        const int64_t nb = (c->K + 15) / 16;
+        return nb * (nb + 1) / 2 * 256 + 16 * nb;
+    }
+    return (int64_t)c->K * (c->K + 1) / 2 + c->K;
 }
 
 hipError_t launch_row_big(bpmf_ctx *c, int side_id, hipStream_t s, int stage, bool *handled)

@@ -17,8 +17,9 @@
 // ceil(K/16)), four ratings per instruction; the rhs accumulates on the VALU
 // from the same registers.  Loads are buffer loads with 32-bit offsets:
 // out-of-range offsets return 0, which masks the ragged tail and the padded
-// components without branches.  The gather is software-pipelined: ids of
-// chunk c+2 and rows of chunk c+1 are in flight while chunk c is multiplied.
+// components without branches.  Ids and ratings arrive 64 at a time in one
+// coalesced load and reach the lanes that need them by ds_bpermute; all
+// neighbour-row loads of a block of ratings are in flight together.
 //
 // Cholesky: the accumulators go through LDS into a column-per-lane layout
 // (lane c of a row's lane group holds column c of P, plus b as an extra row).
@@ -42,12 +43,9 @@
 namespace bpmf {
 
 hipError_t prepare_hyper(bpmf_ctx *c);
-hipError_t launch_part_reduce(bpmf_ctx *c, Side &sd, hipStream_t s);
 
 namespace {
 
-constexpr int kUnroll = 4;           // groups of 4 ratings per chunk
-constexpr int kChunk = 4 * kUnroll;  // ratings per pipeline chunk
 
 // Factor and sample one row held column-per-lane: lane c of the group has
 // v[r] = P[r][c] for r < KP (identity outside the leading K x K block) and
@@ -141,7 +139,7 @@ __global__ __launch_bounds__(64 * WPB) void row_fast_f32(
         float bacc[NB];
 #pragma unroll
         for (int bi = 0; bi < NB; ++bi) bacc[bi] = 0.f;
-        gram_item<NB, kUnroll>(it, nbr, rc, ysrc, ldy4, lane_off, kq, acc, bacc);
+        gram_item<NB>(it, nbr, rc, ysrc, ldy4, lane_off, kq, acc, bacc);
         // sum the rhs over the four rating slots of each 16-lane column
 #pragma unroll
         for (int bi = 0; bi < NB; ++bi) {
@@ -254,7 +252,7 @@ __global__ __launch_bounds__(64 * WPB) void foldin_draw_f32(
         float bacc[NB];
 #pragma unroll
         for (int bi = 0; bi < NB; ++bi) bacc[bi] = 0.f;
-        gram_item<NB, kUnroll>(it, nbr, rc, ysrc, ldy4, lane_off, kq, acc, bacc);
+        gram_item<NB>(it, nbr, rc, ysrc, ldy4, lane_off, kq, acc, bacc);
 #pragma unroll
         for (int bi = 0; bi < NB; ++bi) {
             bacc[bi] += __shfl_xor(bacc[bi], 16);
@@ -354,7 +352,7 @@ template <int NB, int WPB>
 hipError_t launch_finish_f32(bpmf_ctx *c, Side &sd, hipStream_t s)
 {
     if (sd.n_fin == 0) return hipSuccess;
-    hipError_t e = launch_part_reduce(c, sd, s);
+    hipError_t e = launch_part_reduce(c, sd, s, (int64_t)c->K * (c->K + 1) / 2 + c->K);
     if (e != hipSuccess) return e;
     const unsigned grid = (unsigned)((sd.n_fin + WPB - 1) / WPB);
     hipLaunchKernelGGL((row_finish_fast<NB, WPB>), dim3(grid), dim3(64 * WPB), 0, s, c->K,
@@ -383,12 +381,11 @@ hipError_t launch_f32(bpmf_ctx *c, Side &sd, Side &ot, hipStream_t s)
 }  // namespace
 
 // Sum each split row's FP32 partial slots into its first slot.
-hipError_t launch_part_reduce(bpmf_ctx *c, Side &sd, hipStream_t s)
+hipError_t launch_part_reduce(bpmf_ctx *c, Side &sd, hipStream_t s, int64_t E)
 {
     if (sd.n_fin == 0) return hipSuccess;
-    const int E = c->K * (c->K + 1) / 2 + c->K;
     hipLaunchKernelGGL(part_reduce, dim3((unsigned)sd.n_fin, (unsigned)((E + 255) / 256)), dim3(256),
-                       0, s, sd.fin, E, (float *)c->part);
+                       0, s, sd.fin, (int)E, (float *)c->part);
     return hipGetLastError();
 }
 

@@ -427,7 +427,8 @@ int bpmf_create(int64_t M, int64_t N, const int64_t *csr_ptr, const int32_t *csr
         }
         const int KK2 = K * (K + 1) / 2;
         c->part_slots = std::max(c->side[0].n_slots, c->side[1].n_slots);
-        CK(hipMalloc(&c->part, std::max<size_t>(1, (size_t)c->part_slots * (KK2 + K)) * es));
+        CK(hipMalloc(&c->part, std::max<size_t>(1, (size_t)c->part_slots *
+                                                      std::max<int64_t>(KK2 + K, part_slot_elems(c))) * es));
         CK(dalloc(&c->d_mu0, K));
         CK(dalloc(&c->d_W0inv, (size_t)K * K));
         CK(hipMemcpy(c->d_mu0, mu0.data(), sizeof(double) * K, hipMemcpyHostToDevice));
