@@ -21,7 +21,8 @@
 // coalesced load and reach the lanes that need them by ds_bpermute; all
 // neighbour-row loads of a block of ratings are in flight together.
 //
-// Cholesky: the accumulators go through LDS into a column-per-lane layout
+// Cholesky: the accumulators go through LDS (packed lower triangle) into a
+// column-per-lane layout
 // (lane c of a row's lane group holds column c of P, plus b as an extra row).
 // Right-looking elimination without square roots: at step k every column
 // c > k subtracts its multiple of pivot column k, broadcast from lane k
@@ -107,10 +108,9 @@ __global__ __launch_bounds__(64 * WPB) void row_fast_f32(
     const uint32_t *__restrict__ ctr)
 {
     constexpr int KP = 16 * NB;
-    constexpr int LDP = KP + 1;
     constexpr int NBLK = NB * (NB + 1) / 2;
     constexpr int LPR = 64 / RPW;  // lanes per row in the factorisation
-    constexpr int REGION = KP * LDP + KP;
+    constexpr int REGION = KP * (KP + 1) / 2 + KP;  // packed lower triangle, then b
     extern __shared__ float smem_f[];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
@@ -174,12 +174,11 @@ __global__ __launch_bounds__(64 * WPB) void row_fast_f32(
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int r = 16 * bi + 4 * kq + v, c = 16 * bj + col;
-                    P[r * LDP + c] = acc[q][v];
-                    if (bi != bj) P[c * LDP + r] = acc[q][v];
+                    if (c <= r) P[pk(r, c)] = acc[q][v];
                 }
                 ++q;
             }
-            if (kq == 0) P[KP * LDP + 16 * bi + col] = bacc[bi];
+            if (kq == 0) P[KP * (KP + 1) / 2 + 16 * bi + col] = bacc[bi];
         }
         row_of[h] = it.row;
     });
@@ -201,8 +200,9 @@ __global__ __launch_bounds__(64 * WPB) void row_fast_f32(
     float v[KP + 1];
 #pragma unroll
     for (int r = 0; r < KP; ++r)
-        v[r] = (live && r < K) ? alpha * P[r * LDP + cc] + Lam[r * K + c] : (r == c ? 1.f : 0.f);
-    v[KP] = live ? alpha * P[KP * LDP + cc] + Lmu[c] : 0.f;
+        v[r] = (live && r < K) ? alpha * P[r >= cc ? pk(r, cc) : pk(cc, r)] + Lam[r * K + c]
+                               : (r == c ? 1.f : 0.f);
+    v[KP] = live ? alpha * P[KP * (KP + 1) / 2 + cc] + Lmu[c] : 0.f;
     const float x = chol_sample_column<KP, RPW>(v, K, c, (uint32_t)my_row, ctr[0], 0u, seed, stream);
     if (live) X[(size_t)my_row * ldx + c] = x;
 }
@@ -267,12 +267,11 @@ __global__ __launch_bounds__(64 * WPB) void foldin_draw_f32(
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int r = 16 * bi + 4 * kq + v, c = 16 * bj + col;
-                    P[r * LDP + c] = acc[q][v];
-                    if (bi != bj) P[c * LDP + r] = acc[q][v];
+                    if (c <= r) P[pk(r, c)] = acc[q][v];
                 }
                 ++q;
             }
-            if (kq == 0) P[KP * LDP + 16 * bi + col] = bacc[bi];
+            if (kq == 0) P[KP * (KP + 1) / 2 + 16 * bi + col] = bacc[bi];
         }
         req_of[h] = f.req;
         s_of[h] = f.s;
@@ -297,8 +296,9 @@ __global__ __launch_bounds__(64 * WPB) void foldin_draw_f32(
     float v[KP + 1];
 #pragma unroll
     for (int r = 0; r < KP; ++r)
-        v[r] = (live && r < K) ? alpha * P[r * LDP + cc] + Lam[r * K + c] : (r == c ? 1.f : 0.f);
-    v[KP] = live ? alpha * P[KP * LDP + cc] + Lmu[c] : 0.f;
+        v[r] = (live && r < K) ? alpha * P[r >= cc ? pk(r, cc) : pk(cc, r)] + Lam[r * K + c]
+                               : (r == c ? 1.f : 0.f);
+    v[KP] = live ? alpha * P[KP * (KP + 1) / 2 + cc] + Lmu[c] : 0.f;
     const uint64_t key = my_req >= 0 ? req_ids[my_req] : 0ull;
     const float x = chol_sample_column<KP, RPW>(v, K, c, (uint32_t)key, (uint32_t)my_s,
                                                 (uint32_t)(key >> 32), seed, stream);
@@ -366,7 +366,7 @@ template <int NB, int RPW, int WPB>
 hipError_t launch_f32(bpmf_ctx *c, Side &sd, Side &ot, hipStream_t s)
 {
     constexpr int KP = 16 * NB;
-    const size_t lds = sizeof(float) * WPB * RPW * (KP * (KP + 1) + KP);
+    const size_t lds = sizeof(float) * WPB * RPW * (KP * (KP + 1) / 2 + KP);
     const int64_t per_block = (int64_t)WPB * RPW;
     const unsigned grid = (unsigned)((sd.n_items + per_block - 1) / per_block);
     const uint32_t y_bytes = (uint32_t)(ot.rows * c->ld * sizeof(float));
