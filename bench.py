@@ -181,6 +181,37 @@ def foldin_bench(s, r, rate, seconds, seed, top_n=100):
     }
 
 
+def k100_compare(steps, seed):
+    """The 100M-rating shape at K = 100: the same chain (same seed, same
+    Philox draws) in FP32 and in the BF16-Gram form, `steps` timed sweeps
+    each after two warm-up sweeps; reports throughput and the held-out RMSE
+    of both, and their ratio."""
+    import paper_1705_04159_amd as bp
+
+    t = time.perf_counter()
+    r = synth.netflix_like()
+    log("generated %s: M=%d N=%d nnz=%d in %.1fs" % (r.name, r.M, r.N, r.nnz, time.perf_counter() - t))
+    out = {"workload": r.name, "M": r.M, "N": r.N, "nnz_train": r.nnz, "K": 100, "steps": steps}
+    for prec in ("fp32", "bf16"):
+        s = bp.Sampler(r, 100, prec=prec, seed=seed)
+        s.run_sweeps(1, 2)
+        s.synchronize()
+        t0 = time.perf_counter()
+        avg, last = s.run_sweeps(3, steps)
+        s.synchronize()
+        ms = 1000.0 * (time.perf_counter() - t0) / steps
+        kv, ku = s.row_kernel_ms()
+        s.close()
+        out[prec] = {"ms_per_step": round(ms, 3), "row_updates_per_s": round((r.M + r.N) / ms * 1e3, 1),
+                     "ratings_per_s": round(2 * r.nnz / ms * 1e3, 1),
+                     "rmse_avg": round(float(avg[-1]), 5), "rmse_last": round(float(last[-1]), 5),
+                     "row_kernel_ms": {"rows_V": round(kv, 3), "rows_U": round(ku, 3)}}
+        log("K=100 %s: %s" % (prec, out[prec]))
+    out["bf16_speedup"] = round(out["fp32"]["ms_per_step"] / out["bf16"]["ms_per_step"], 3)
+    out["rmse_avg_rel_diff"] = round(out["bf16"]["rmse_avg"] / out["fp32"]["rmse_avg"] - 1.0, 6)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -195,6 +226,9 @@ def main():
     ap.add_argument("--foldin-rate", type=float, default=5000.0)
     ap.add_argument("--foldin-seconds", type=float, default=3.0)
     ap.add_argument("--no-foldin", action="store_true")
+    ap.add_argument("--k100-steps", type=int, default=50,
+                    help="sweeps of the K = 100 comparison (100M-rating shape, FP32 vs BF16-Gram)")
+    ap.add_argument("--no-k100", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (torch), the "
                          "reference kernel for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE")
@@ -314,6 +348,8 @@ def main():
         out["foldin"] = foldin_bench(s, r, args.foldin_rate, args.foldin_seconds, args.seed)
         log("fold-in: %s" % out["foldin"])
     s.close()
+    if not args.no_k100 and args.workload == "movielens":
+        out["k100"] = k100_compare(args.k100_steps, args.seed)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(r, K, args.cpu_seconds, args.seed)
         log("cpu baseline: %s" % out["cpu_baseline"])
