@@ -3,7 +3,6 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include <type_traits>
 
 #include "internal.h"
 
@@ -151,18 +150,9 @@ __device__ __forceinline__ void gram_item_pipe(const RowItem &it, const int32_t 
     }
 }
 
-// Gram and rhs of one work item into the accumulators (whole wave), FP32
-// rows on v_mfma_f32_16x16x4_f32.  The item's ratings are taken in blocks of
-// 64: lane l loads the id and rating of rating l of the block (one coalesced
-// load each, the next block's in flight during this one), and group g of the
-// block multiplies ratings 4g .. 4g+3, lane l holding component
-// 16*bi + (l % 16) of the neighbour row of rating 4g + l / 16 -- its offset
-// fetched from the lane that loaded it (ds_bpermute) -- which is both the A
-// operand of block row bi and the B operand of block column bj, so only the
-// nb(nb+1)/2 lower 16x16 blocks of P are accumulated.  All neighbour-row
-// loads of NG groups are issued before their products; ratings past the end
-// read as 0 (buffer range check) and whole groups past the end are skipped.
-// (For nb > 2 the per-group pipelined form above is used.)
+// Gram and rhs of one work item into the accumulators (whole wave): the
+// pipelined per-group form, four groups (16 ratings) per stage for rows of
+// up to 32 components and two for wider rows (register budget).
 template <int NB>
 __device__ __forceinline__ void gram_item(const RowItem &it, const int32_t *__restrict__ nbr,
                                           const float *__restrict__ rc,
@@ -170,69 +160,7 @@ __device__ __forceinline__ void gram_item(const RowItem &it, const int32_t *__re
                                           const uint32_t (&lane_off)[NB], int kq,
                                           floatx4 (&acc)[NB * (NB + 1) / 2], float (&bacc)[NB])
 {
-    if constexpr (NB > 2) {
-        // wider rows: per-group loads, software-pipelined (measured faster)
-        gram_item_pipe<NB, 2>(it, nbr, rc, ysrc, ldy4, lane_off, kq, acc, bacc);
-        return;
-    }
-    constexpr int NG = 16;  // groups per batch of loads
-    const int lane = threadIdx.x & 63;
-    const uint32_t cnt = (uint32_t)(it.end - it.beg);
-    const __amdgpu_buffer_rsrc_t jsrc = make_rsrc(nbr + it.beg, cnt * 4u);
-    const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(rc + it.beg, cnt * 4u);
-    const uint32_t nblk = (cnt + 63) / 64;
-    uint32_t jn = buf_u32(jsrc, (uint32_t)lane * 4u);
-    float rn = buf_f32(rsrc, (uint32_t)lane * 4u);
-    int bl = 0;
-    float rl = 0.f;
-    // groups g0 .. g0 + n - 1 of the current block: loads first, then products
-    auto batch = [&](auto g0c, auto nc) {
-        constexpr int g0 = decltype(g0c)::value, n = decltype(nc)::value;
-        float y[n][NB];
-        float r[n];
-#pragma unroll
-        for (int gg = 0; gg < n; ++gg) {
-            const int src = 4 * (g0 + gg) + kq;
-            const uint32_t base = (uint32_t)__shfl(bl, src);
-            r[gg] = __shfl(rl, src);
-#pragma unroll
-            for (int bi = 0; bi < NB; ++bi) y[gg][bi] = buf_f32(ysrc, base + lane_off[bi]);
-        }
-#pragma unroll
-        for (int gg = 0; gg < n; ++gg) {
-            int q = 0;
-#pragma unroll
-            for (int bi = 0; bi < NB; ++bi) {
-#pragma unroll
-                for (int bj = 0; bj <= bi; ++bj) {
-                    acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(y[gg][bi], y[gg][bj], acc[q], 0, 0, 0);
-                    ++q;
-                }
-                bacc[bi] += r[gg] * y[gg][bi];
-            }
-        }
-    };
-    for (uint32_t b = 0; b < nblk; ++b) {
-        const uint32_t t = b * 64 + (uint32_t)lane;
-        bl = (int)(t < cnt ? jn * ldy4 : kOOB);
-        rl = rn;
-        jn = buf_u32(jsrc, (t + 64) * 4u);  // next block (0 past the end)
-        rn = buf_f32(rsrc, (t + 64) * 4u);
-        const uint32_t rem = cnt - b * 64;
-        if (rem >= 64) {
-            static_for<0, 16 / NG>([&](auto sc) {
-                batch(std::integral_constant<int, decltype(sc)::value * NG>{},
-                      std::integral_constant<int, NG>{});
-            });
-        } else {
-            // last block: batches of four groups while they hold ratings
-            const uint32_t G = (rem + 3) / 4;
-            static_for<0, 4>([&](auto sc) {
-                constexpr int g0 = decltype(sc)::value * 4;
-                if (g0 < (int)G) batch(std::integral_constant<int, g0>{}, std::integral_constant<int, 4>{});
-            });
-        }
-    }
+    gram_item_pipe<NB, (NB <= 2 ? 4 : 2)>(it, nbr, rc, ysrc, ldy4, lane_off, kq, acc, bacc);
 }
 
 }  // namespace

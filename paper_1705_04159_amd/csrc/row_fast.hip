@@ -17,9 +17,8 @@
 // ceil(K/16)), four ratings per instruction; the rhs accumulates on the VALU
 // from the same registers.  Loads are buffer loads with 32-bit offsets:
 // out-of-range offsets return 0, which masks the ragged tail and the padded
-// components without branches.  Ids and ratings arrive 64 at a time in one
-// coalesced load and reach the lanes that need them by ds_bpermute; all
-// neighbour-row loads of a block of ratings are in flight together.
+// components without branches.  The gather is software-pipelined: ids of
+// chunk c+2 and rows of chunk c+1 are in flight while chunk c is multiplied.
 //
 // Cholesky: the accumulators go through LDS (packed lower triangle) into a
 // column-per-lane layout
