@@ -88,7 +88,8 @@ typedef struct bpmf_params {
     int32_t center;       /* 1: subtract the mean training rating (default 1) */
     int32_t burn_in;      /* sweeps t <= burn_in are left out of the running prediction mean */
     int32_t foldin_S;     /* fold-in sample ring size (default 16) */
-    int32_t split_threshold; /* rows with more ratings are split across wavefronts (0: library default) */
+    int32_t split_threshold; /* rows with more ratings are split across wavefronts (0: library
+                                default, 2048 for K <= 64 and 8192 above) */
     uint64_t foldin_pool_bytes; /* fold-in device memory budget (0: 256 MiB) */
 } bpmf_params;
 

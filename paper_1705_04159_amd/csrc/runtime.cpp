@@ -342,7 +342,10 @@ int bpmf_create(int64_t M, int64_t N, const int64_t *csr_ptr, const int32_t *csr
     c->nu0 = p->nu0;
     c->seed = p->seed;
     c->burn_in = p->burn_in;
-    c->split_threshold = p->split_threshold > 0 ? p->split_threshold : 2048;
+    // default: rows above 2048 ratings are split (above 8192 for K > 64, where
+    // a segment's partial sums are large and its Gram long enough to keep
+    // the waves busy)
+    c->split_threshold = p->split_threshold > 0 ? p->split_threshold : (K > 64 ? 8192 : 2048);
     c->foldin_S = p->foldin_S > 0 ? p->foldin_S : 16;
     c->foldin_pool = p->foldin_pool_bytes;
     double rbar = 0.0;
