@@ -181,7 +181,7 @@ def foldin_bench(s, r, rate, seconds, seed, top_n=100):
     }
 
 
-def k100_compare(steps, seed):
+def k100_compare(steps, seed, autotune=True):
     """The 100M-rating shape at K = 100: the same chain (same seed, same
     Philox draws) in FP32 and in the BF16-Gram form, `steps` timed sweeps
     each after two warm-up sweeps; reports throughput and the held-out RMSE
@@ -195,6 +195,9 @@ def k100_compare(steps, seed):
     for prec in ("fp32", "bf16"):
         s = bp.Sampler(r, 100, prec=prec, seed=seed)
         s.run_sweeps(1, 2)
+        split = None
+        if autotune:
+            split, _, _ = s.autotune(3)
         s.synchronize()
         t0 = time.perf_counter()
         avg, last = s.run_sweeps(3, steps)
@@ -205,7 +208,8 @@ def k100_compare(steps, seed):
         out[prec] = {"ms_per_step": round(ms, 3), "row_updates_per_s": round((r.M + r.N) / ms * 1e3, 1),
                      "ratings_per_s": round(2 * r.nnz / ms * 1e3, 1),
                      "rmse_avg": round(float(avg[-1]), 5), "rmse_last": round(float(last[-1]), 5),
-                     "row_kernel_ms": {"rows_V": round(kv, 3), "rows_U": round(ku, 3)}}
+                     "row_kernel_ms": {"rows_V": round(kv, 3), "rows_U": round(ku, 3)},
+                     "split_threshold": split}
         log("K=100 %s: %s" % (prec, out[prec]))
     out["bf16_speedup"] = round(out["fp32"]["ms_per_step"] / out["bf16"]["ms_per_step"], 3)
     out["rmse_avg_rel_diff"] = round(out["bf16"]["rmse_avg"] / out["fp32"]["rmse_avg"] - 1.0, 6)
@@ -229,6 +233,8 @@ def main():
     ap.add_argument("--k100-steps", type=int, default=50,
                     help="sweeps of the K = 100 comparison (100M-rating shape, FP32 vs BF16-Gram)")
     ap.add_argument("--no-k100", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the library's default split threshold and kernel family")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (torch), the "
                          "reference kernel for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE")
@@ -264,6 +270,14 @@ def main():
     if warm > 0:
         s.run_sweeps(1, warm)
         log("warmup %d sweeps done" % warm)
+    tuned = None
+    if not args.no_autotune:
+        t = time.perf_counter()
+        split, kmax, tried = s.autotune(5)
+        tuned = {"split_threshold": split, "fast_kmax": kmax,
+                 "tried": [[a, b, round(m, 4)] for a, b, m in tried]}
+        log("autotune (%.1fs): split %d, kmax %d; tried %s" % (time.perf_counter() - t, split, kmax,
+                                                              tuned["tried"]))
     s.synchronize()
     t0 = time.perf_counter()
     avg, last = s.run_sweeps(warm + 1, steps)  # returns after the stream is drained
@@ -336,6 +350,7 @@ def main():
         "rmse_last": round(float(last[-1]), 5),
         "phase_ms": phase,
         "row_kernel_ms": {k: round(v, 4) for k, v in k_ms.items()},
+        "autotune": tuned,
         "roofline": roof,
     }
     if not args.no_foldin and prec == "fp32" and K <= 64:
@@ -349,7 +364,7 @@ def main():
         log("fold-in: %s" % out["foldin"])
     s.close()
     if not args.no_k100 and args.workload == "movielens":
-        out["k100"] = k100_compare(args.k100_steps, args.seed)
+        out["k100"] = k100_compare(args.k100_steps, args.seed, not args.no_autotune)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(r, K, args.cpu_seconds, args.seed)
         log("cpu baseline: %s" % out["cpu_baseline"])

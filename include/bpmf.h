@@ -175,6 +175,23 @@ int bpmf_synchronize(bpmf_ctx *c);
  * bpmf_update_side / bpmf_sample_hyper / bpmf_run_sweeps call. */
 int bpmf_last_time_ms(bpmf_ctx *c, double *ms);
 
+/* Autotuning of the degree-bucket cut-off and kernel family on the
+ * context's own data.  The paper balances per-item work by degree with a
+ * fixed cost plus a cost per rating (Sec. III and IV-B); here the cut-off
+ * above which a row is split into segments across wavefronts (and, for
+ * FP32 with 32 < K <= 64, whether rows take the column-per-lane or the
+ * blocked kernel) is chosen by timing n_sweeps (1..64) graph sweeps per
+ * candidate: split thresholds 512, 1024, ... up to the first power of two
+ * at or above the largest degree, and the current one; a candidate replaces
+ * the current plan only if it is at least 2% faster.  The chain state (factors, hyperparameters,
+ * running predictions, sweep counter) is restored afterwards, so the chain
+ * continues exactly as if no trial had run; only the plan changes.  Outputs
+ * (each may be NULL): the chosen threshold and kernel cut-off K (32 or 64),
+ * the number of candidates tried (at most 64) and, per candidate, its
+ * threshold, kernel cut-off and mean ms per sweep (caller arrays of 64). */
+int bpmf_autotune(bpmf_ctx *c, uint32_t n_sweeps, int32_t *chosen_split, int32_t *chosen_kmax,
+                  int32_t *n_tried, int32_t *tried_split, int32_t *tried_kmax, double *tried_ms);
+
 /* Mean device time (ms) of one launch of the row-update kernel (the work
  * items of the row loops of Algorithm 1, split-row finishing excluded) over
  * the sweeps of the most recent bpmf_run_sweeps call: ms[0] for the V side,

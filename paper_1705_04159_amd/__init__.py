@@ -33,7 +33,7 @@ EXPORTS = [
     "bpmf_run_sweeps", "bpmf_profile_sweeps", "bpmf_predict", "bpmf_get_factor", "bpmf_set_factor",
     "bpmf_get_factor_f64", "bpmf_set_factor_f64", "bpmf_get_hyper", "bpmf_set_hyper",
     "bpmf_get_csc", "bpmf_get_plan", "bpmf_mean_rating", "bpmf_synchronize",
-    "bpmf_last_time_ms", "bpmf_row_kernel_ms", "bpmf_last_error", "bpmf_destroy", "bpmf_store_sample",
+    "bpmf_last_time_ms", "bpmf_row_kernel_ms", "bpmf_autotune", "bpmf_last_error", "bpmf_destroy", "bpmf_store_sample",
     "bpmf_foldin_submit", "bpmf_foldin_poll", "bpmf_foldin_drain", "bpmf_foldin_samples",
     "bpmf_foldin_capacity",
 ]
@@ -96,6 +96,7 @@ def lib() -> ctypes.CDLL:
         L.bpmf_synchronize.argtypes = [P]
         L.bpmf_last_time_ms.argtypes = [P, P]
         L.bpmf_row_kernel_ms.argtypes = [P, P]
+        L.bpmf_autotune.argtypes = [P, ctypes.c_uint32, P, P, P, P, P, P]
         L.bpmf_last_error.argtypes = [P]
         L.bpmf_last_error.restype = ctypes.c_char_p
         L.bpmf_destroy.argtypes = [P]
@@ -309,6 +310,18 @@ class Sampler:
         ms = ctypes.c_double()
         self._check(lib().bpmf_last_time_ms(self._ctx, ctypes.byref(ms)))
         return ms.value
+
+    def autotune(self, n_sweeps=3):
+        """Time candidate split thresholds (and kernel families) on this
+        context's data and keep the fastest; the chain state is unchanged.
+        Returns (split, kmax, [(split, kmax, ms_per_sweep), ...])."""
+        sp, km, nt = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        ts = (ctypes.c_int32 * 64)()
+        tk = (ctypes.c_int32 * 64)()
+        tm = (ctypes.c_double * 64)()
+        self._check(lib().bpmf_autotune(self._ctx, n_sweeps, ctypes.byref(sp), ctypes.byref(km),
+                                        ctypes.byref(nt), ts, tk, tm))
+        return sp.value, km.value, [(ts[i], tk[i], tm[i]) for i in range(nt.value)]
 
     def row_kernel_ms(self):
         """Mean per-launch device time (ms) of the row kernel of each side over

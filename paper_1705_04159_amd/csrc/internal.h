@@ -57,6 +57,7 @@ struct Side {
     int64_t n_fin = 0;
     int64_t n_slots = 0;
     std::vector<int32_t> perm;  // host copy of the processing order
+    std::vector<int64_t> hptr;  // host copy of the neighbour offsets (re-planning)
     int64_t n_split = 0;
     uint32_t stream_row = 0, stream_hyp = 0, stream_init = 0;
 };
@@ -74,6 +75,7 @@ struct bpmf_ctx {
     uint64_t seed = 0;
     int burn_in = 0;
     int split_threshold = 0;
+    int fast_kmax = 32;  // FP32 rows up to this K take the column-per-lane kernel
     double *d_mu0 = nullptr, *d_W0inv = nullptr;
     bpmf::Side side[2];
     // test set

@@ -490,7 +490,7 @@ hipError_t launch_big(bpmf_ctx *c, Side &sd, Side &ot, hipStream_t s, int stage)
 bool big_path_available(const bpmf_ctx *c)
 {
     if (c->prec == 0 || c->K > 128) return false;
-    if (c->prec == 1 && c->K <= 32) return false;  // the column-per-lane kernel takes it
+    if (c->prec == 1 && c->K <= c->fast_kmax && c->K <= 64) return false;  // column-per-lane kernel
     for (int s = 0; s < 2; ++s)
         if ((uint64_t)c->side[s].rows * c->ld * sizeof(float) >= kOOB) return false;
     return (uint64_t)c->split_threshold * 4u < kOOB;

@@ -433,9 +433,10 @@ bool fast_path_available(const bpmf_ctx *c)
 hipError_t launch_row_fast(bpmf_ctx *c, int side_id, hipStream_t s, int stage, bool *handled)
 {
     *handled = false;
-    // Sweeps use this kernel up to K = 32; above that the blocked
-    // factorisation of the K <= 128 kernel is faster (fold-in keeps it to 64).
-    if (!fast_path_available(c) || c->K > 32) return hipSuccess;
+    // Sweeps use this kernel up to K = fast_kmax (32 by default: above it the
+    // blocked factorisation of the K <= 128 kernel is faster; the autotuner
+    // may raise it to 64).  Fold-in keeps it to K = 64.
+    if (!fast_path_available(c) || c->K > c->fast_kmax) return hipSuccess;
     *handled = true;
     Side &sd = c->side[side_id];
     Side &ot = c->side[1 - side_id];

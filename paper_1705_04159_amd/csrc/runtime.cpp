@@ -407,6 +407,7 @@ int bpmf_create(int64_t M, int64_t N, const int64_t *csr_ptr, const int32_t *csr
                     CK(hipMemcpy(sd.rc, r.data(), sizeof(float) * nnz, hipMemcpyHostToDevice));
                 }
             }
+            sd.hptr = *ptrs[sid];
             std::vector<RowItem> items;
             std::vector<FinishItem> fin;
             plan_side(*ptrs[sid], sd.rows, c->split_threshold,
@@ -575,6 +576,160 @@ static int find_timing_nodes(bpmf_ctx *c)
     c->timing_nodes = true;
     for (auto t : c->tnode)
         if (!t) c->timing_nodes = false;  // sweeps still run, untimed
+    return BPMF_OK;
+}
+
+// Re-plan both sides for a new split threshold / kernel family: work items,
+// finishing items and the partial-sum workspace; the sweep graph is rebuilt
+// on the next bpmf_run_sweeps.
+static int replan(bpmf_ctx *c, int split, int fast_kmax)
+{
+    HIPCK(c, hipStreamSynchronize(c->stream));
+    c->split_threshold = split;
+    c->fast_kmax = fast_kmax;
+    for (int sid = 0; sid < 2; ++sid) {
+        Side &sd = c->side[sid];
+        std::vector<RowItem> items;
+        std::vector<FinishItem> fin;
+        plan_side(sd.hptr, sd.rows, split, std::max<int64_t>(128, split / 2), sd.perm, sd.n_split,
+                  items, fin, sd.n_slots);
+        (void)hipFree(sd.items);
+        (void)hipFree(sd.fin);
+        sd.items = nullptr;
+        sd.fin = nullptr;
+        sd.n_items = (int64_t)items.size();
+        sd.n_fin = (int64_t)fin.size();
+        HIPCK(c, dalloc(&sd.items, items.size()));
+        HIPCK(c, dalloc(&sd.fin, fin.size()));
+        if (!items.empty())
+            HIPCK(c, hipMemcpy(sd.items, items.data(), sizeof(RowItem) * items.size(), hipMemcpyHostToDevice));
+        if (!fin.empty())
+            HIPCK(c, hipMemcpy(sd.fin, fin.data(), sizeof(FinishItem) * fin.size(), hipMemcpyHostToDevice));
+    }
+    const int64_t KK2 = (int64_t)c->K * (c->K + 1) / 2;
+    c->part_slots = std::max(c->side[0].n_slots, c->side[1].n_slots);
+    (void)hipFree(c->part);
+    c->part = nullptr;
+    HIPCK(c, hipMalloc(&c->part, std::max<size_t>(1, (size_t)c->part_slots *
+                                                        std::max<int64_t>(KK2 + c->K, part_slot_elems(c))) *
+                                    elem_bytes(c)));
+    if (c->graph) (void)hipGraphExecDestroy(c->graph);
+    if (c->graph_src) (void)hipGraphDestroy(c->graph_src);
+    c->graph = nullptr;
+    c->graph_src = nullptr;
+    return BPMF_OK;
+}
+
+// Device copies of everything a sweep changes (factors, BF16 shadows,
+// hyperparameters, running prediction sums, counters).
+struct ChainSnapshot {
+    std::vector<std::pair<void *, size_t>> regions;  // (live buffer, bytes)
+    std::vector<void *> copies;
+};
+
+static int snapshot_take(bpmf_ctx *c, ChainSnapshot &sn)
+{
+    const size_t es = elem_bytes(c);
+    const size_t K = (size_t)c->K;
+    for (auto &sd : c->side) {
+        sn.regions.push_back({sd.X, (size_t)sd.rows * c->ld * es});
+        if (sd.Xbf) sn.regions.push_back({sd.Xbf, (size_t)sd.rows * c->ld * sizeof(uint16_t)});
+        sn.regions.push_back({sd.mu, K * sizeof(double)});
+        sn.regions.push_back({sd.Lam, K * K * sizeof(double)});
+        sn.regions.push_back({sd.Lam_w, K * K * es});
+        sn.regions.push_back({sd.Lmu_w, K * es});
+    }
+    sn.regions.push_back({c->pred_sum, (size_t)c->n_test * sizeof(double)});
+    sn.regions.push_back({c->ctr, 4 * sizeof(uint32_t)});
+    for (auto &rg : sn.regions) {
+        void *p = nullptr;
+        if (rg.second) HIPCK(c, hipMalloc(&p, rg.second));
+        sn.copies.push_back(p);
+        if (rg.second)
+            HIPCK(c, hipMemcpyAsync(p, rg.first, rg.second, hipMemcpyDeviceToDevice, c->stream));
+    }
+    HIPCK(c, hipStreamSynchronize(c->stream));
+    return BPMF_OK;
+}
+
+static int snapshot_restore(bpmf_ctx *c, const ChainSnapshot &sn)
+{
+    for (size_t q = 0; q < sn.regions.size(); ++q)
+        if (sn.regions[q].second)
+            HIPCK(c, hipMemcpyAsync(sn.regions[q].first, sn.copies[q], sn.regions[q].second,
+                                    hipMemcpyDeviceToDevice, c->stream));
+    HIPCK(c, hipStreamSynchronize(c->stream));
+    return BPMF_OK;
+}
+
+static void snapshot_free(ChainSnapshot &sn)
+{
+    for (void *p : sn.copies) (void)hipFree(p);
+    sn.copies.clear();
+}
+
+int bpmf_run_sweeps(bpmf_ctx *c, uint32_t t0, uint32_t n, double *rmse_avg, double *rmse_last);
+
+int bpmf_autotune(bpmf_ctx *c, uint32_t n_sweeps, int32_t *chosen_split, int32_t *chosen_kmax,
+                  int32_t *n_tried, int32_t *tried_split, int32_t *tried_kmax, double *tried_ms)
+{
+    STICKY(c);
+    if (n_sweeps == 0 || n_sweeps > 64) return fail(c, BPMF_E_INVAL, "n_sweeps must be 1..64");
+    // candidate cut-offs: powers of two from 512 up to the first at or above
+    // the largest degree (no split), and the kernel families for FP32 K in (32, 64]
+    int64_t max_deg = 0;
+    for (auto &sd : c->side)
+        for (int64_t r = 0; r < sd.rows; ++r) max_deg = std::max(max_deg, sd.hptr[r + 1] - sd.hptr[r]);
+    std::vector<int> splits;
+    for (int64_t s = 512; s <= (1 << 24); s *= 2) {
+        splits.push_back((int)s);
+        if (s >= max_deg) break;
+    }
+    if (std::find(splits.begin(), splits.end(), c->split_threshold) == splits.end())
+        splits.push_back(c->split_threshold);
+    std::vector<int> kmaxes = {c->fast_kmax};
+    if (c->prec == BPMF_FP32 && c->K > 32 && c->K <= 64) kmaxes = {32, 64};
+    const int old_split = c->split_threshold, old_kmax = c->fast_kmax;
+    ChainSnapshot sn;
+    if (int r = snapshot_take(c, sn)) {
+        snapshot_free(sn);
+        return r;
+    }
+    int best_split = old_split, best_kmax = old_kmax, q = 0, rc = BPMF_OK;
+    double best = 1e300, incumbent = 1e300;
+    for (int km : kmaxes)
+        for (int sp : splits) {
+            if ((rc = replan(c, sp, km)) != BPMF_OK) break;
+            if ((rc = snapshot_restore(c, sn)) != BPMF_OK) break;
+            // one untimed sweep builds the graph, then n_sweeps timed
+            if ((rc = bpmf_run_sweeps(c, 1, 1, nullptr, nullptr)) != BPMF_OK) break;
+            if ((rc = bpmf_run_sweeps(c, 2, n_sweeps, nullptr, nullptr)) != BPMF_OK) break;
+            const double ms = c->last_ms / n_sweeps;
+            if (q < 64) {
+                if (tried_split) tried_split[q] = sp;
+                if (tried_kmax) tried_kmax[q] = km;
+                if (tried_ms) tried_ms[q] = ms;
+            }
+            ++q;
+            if (sp == old_split && km == old_kmax) incumbent = ms;
+            if (ms < best) {
+                best = ms;
+                best_split = sp;
+                best_kmax = km;
+            }
+        }
+    // keep the current plan unless a candidate is clearly faster (timing noise)
+    if (best > 0.98 * incumbent) {
+        best_split = old_split;
+        best_kmax = old_kmax;
+    }
+    if (rc == BPMF_OK) rc = replan(c, best_split, best_kmax);
+    if (rc == BPMF_OK) rc = snapshot_restore(c, sn);
+    snapshot_free(sn);
+    if (rc != BPMF_OK) return rc;
+    if (chosen_split) *chosen_split = best_split;
+    if (chosen_kmax) *chosen_kmax = best_kmax;
+    if (n_tried) *n_tried = std::min(q, 64);
     return BPMF_OK;
 }
 

@@ -341,3 +341,29 @@ def test_row_kernel_timing_inside_graph(bp):
     assert np.array_equal(a.get_factor(bp.SIDE_U), b.get_factor(bp.SIDE_U))
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("K", [16, 48])
+def test_autotune_keeps_the_chain(bp, K):
+    """The autotuner tries split thresholds (and, for FP32 K = 48, both kernel
+    families), restores the chain state bit-for-bit and leaves a plan with
+    which the chain continues to the same RMSE as an untuned run."""
+    r = synth.planted(seed=5, M=600, N=250, nnz=30000, K=10, zipf=0.9)
+    a = bp.Sampler(r, K, prec="fp32", seed=3)
+    b = bp.Sampler(r, K, prec="fp32", seed=3)
+    a.run_sweeps(1, 2)
+    b.run_sweeps(1, 2)
+    split, kmax, tried = a.autotune(2)
+    assert len(tried) >= 2 and all(ms > 0 for _, _, ms in tried)
+    assert (split, kmax) in [(s, k) for s, k, _ in tried]
+    assert {k for _, k, _ in tried} == ({32, 64} if K == 48 else {32})
+    for side in (bp.SIDE_U, bp.SIDE_V):
+        assert np.array_equal(a.get_factor(side), b.get_factor(side))
+        ma, la = a.get_hyper(side)
+        mb, lb = b.get_hyper(side)
+        assert np.array_equal(ma, mb) and np.array_equal(la, lb)
+    avg_a, last_a = a.run_sweeps(3, 4)
+    avg_b, last_b = b.run_sweeps(3, 4)
+    assert abs(avg_a[-1] / avg_b[-1] - 1) <= 5e-3
+    a.close()
+    b.close()
