@@ -374,3 +374,71 @@ def test_foldin_mean_variance_by_direct_formula(orc):
         z = orc.normals(42, 77, s, orc.FOLDIN, 5, K)
         x = orc.row_draw_z(2.0, movie, rc, Vs[s], mus[s], Lams[s], z)
         assert np.allclose(U[s], x, rtol=1e-14, atol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# Whole sampler: Geweke's joint-distribution test
+# ---------------------------------------------------------------------------
+def test_geweke_joint_distribution(orc):
+    """Geweke (2004): alternating one Gibbs sweep (hyper V, rows V, hyper U,
+    rows U, in Algorithm 1's order) with a fresh draw of the ratings from the
+    likelihood leaves the prior invariant, so test functions of the
+    parameters must have the same means as under independent draws from the
+    prior.  The prior side uses scipy's Wishart and numpy normals; the sweep
+    side is the oracle.  Planted mistakes in the Normal-Wishart posterior move
+    these means by many standard errors (checked on the CPU: nu* off by one
+    |z| = 23, W0 scaled by 1.2 |z| = 19, mu0 dropped |z| = 13, beta0 halved
+    |z| = 5.3); the likelihood precision is weakly identified by five ratings
+    and is pinned by the row-conditional tests above instead.
+    Tiny problem: M = N = 3, K = 2, five observed pairs, non-trivial prior."""
+    K, M, N, alpha = 2, 3, 3, 2.0
+    mu0 = np.array([0.3, -0.2])
+    W0 = np.array([[0.8, 0.3], [0.3, 0.5]])
+    beta0, nu0 = 2.0, 5.0
+    pairs = [(0, 0), (0, 2), (1, 1), (2, 0), (2, 1)]
+    ptr = np.array([0, 2, 3, 5], np.int64)
+    col = np.array([j for _, j in pairs], np.int32)
+    rows_of = np.array([i for i, _ in pairs])
+    rng = np.random.default_rng(2004)
+
+    def prior_side(n):
+        lam = scipy.stats.wishart(df=nu0, scale=W0).rvs(random_state=rng)
+        mu = rng.multivariate_normal(mu0, np.linalg.inv(beta0 * lam))
+        X = rng.multivariate_normal(mu, np.linalg.inv(lam), size=n)
+        return mu, lam, X
+
+    def ratings(U, V):
+        return (np.sum(U[rows_of] * V[col], axis=1) + rng.normal(0, alpha ** -0.5, len(pairs)))
+
+    def g(muU, lamU, U, muV, lamV, V):
+        return np.array([muU[0], muV[1], lamU[0, 0], lamU[0, 1], lamV[1, 1], U[0, 1], V[2, 0],
+                         U[0, 0] ** 2, U[1, 0] * V[1, 0], U[2] @ V[1], muU[0] ** 2, muV[1] ** 2,
+                         (U[0] @ V[0]) ** 2, (U[2] @ V[0]) ** 2, U[1] @ V[1]])
+
+    n_draw = 20000
+    mc = np.empty((n_draw, 15))
+    for q in range(n_draw):
+        muU, lamU, U = prior_side(M)
+        muV, lamV, V = prior_side(N)
+        mc[q] = g(muU, lamU, U, muV, lamV, V)
+
+    muU, lamU, U = prior_side(M)
+    muV, lamV, V = prior_side(N)
+    sc = np.empty((n_draw, 15))
+    seed = 77
+    for q in range(n_draw):
+        r = ratings(U, V)
+        cptr, crow, cval = orc.transpose_csr(M, N, ptr, col, r)
+        t = q + 1
+        muV, lamV = orc.hyper_draw(V, mu0, beta0, nu0, W0, seed, orc.HYP_V, t)
+        orc.update_rows(cptr, crow, cval, U, V, muV, lamV, alpha, seed, orc.ROW_V, t)
+        muU, lamU = orc.hyper_draw(U, mu0, beta0, nu0, W0, seed, orc.HYP_U, t)
+        orc.update_rows(ptr, col, r, V, U, muU, lamU, alpha, seed, orc.ROW_U, t)
+        sc[q] = g(muU, lamU, U, muV, lamV, V)
+
+    # standard errors: independent draws; batch means for the chain
+    se_mc = mc.std(axis=0) / np.sqrt(n_draw)
+    batches = sc[: (n_draw // 50) * 50].reshape(50, -1, 15).mean(axis=1)
+    se_sc = batches.std(axis=0, ddof=1) / np.sqrt(50)
+    z = (mc.mean(axis=0) - sc.mean(axis=0)) / np.sqrt(se_mc ** 2 + se_sc ** 2)
+    assert np.all(np.abs(z) < 4.5), z
