@@ -197,7 +197,7 @@ def k100_compare(steps, seed, autotune=True):
         s.run_sweeps(1, 2)
         split = None
         if autotune:
-            split, _, _ = s.autotune(3)
+            split, _, _, _ = s.autotune(3)
         s.synchronize()
         t0 = time.perf_counter()
         avg, last = s.run_sweeps(3, steps)
@@ -273,11 +273,11 @@ def main():
     tuned = None
     if not args.no_autotune:
         t = time.perf_counter()
-        split, kmax, tried = s.autotune(5)
-        tuned = {"split_threshold": split, "fast_kmax": kmax,
-                 "tried": [[a, b, round(m, 4)] for a, b, m in tried]}
-        log("autotune (%.1fs): split %d, kmax %d; tried %s" % (time.perf_counter() - t, split, kmax,
-                                                              tuned["tried"]))
+        split, kmax, low, tried = s.autotune(5)
+        tuned = {"split_threshold": split, "fast_kmax": kmax, "lowrank_dmax": low,
+                 "tried": [[a, b, c_, round(m, 4)] for a, b, c_, m in tried]}
+        log("autotune (%.1fs): split %d, kmax %d, low %d; tried %s" % (
+            time.perf_counter() - t, split, kmax, low, tuned["tried"]))
     s.synchronize()
     t0 = time.perf_counter()
     avg, last = s.run_sweeps(warm + 1, steps)  # returns after the stream is drained
@@ -362,6 +362,14 @@ def main():
             s.store_sample()
         out["foldin"] = foldin_bench(s, r, args.foldin_rate, args.foldin_seconds, args.seed)
         log("fold-in: %s" % out["foldin"])
+        # offered-load sweep (1 s each) to locate the knee
+        knee = []
+        for rate in (1000.0, 2500.0, 10000.0, 20000.0):
+            f = foldin_bench(s, r, rate, 1.0, args.seed + int(rate))
+            knee.append({k: f[k] for k in ("offered_req_per_s", "completed_req_per_s", "p50_ms",
+                                           "p99_ms")})
+        out["foldin"]["load_sweep"] = knee
+        log("fold-in load sweep: %s" % knee)
     s.close()
     if not args.no_k100 and args.workload == "movielens":
         out["k100"] = k100_compare(args.k100_steps, args.seed, not args.no_autotune)

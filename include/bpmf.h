@@ -162,8 +162,9 @@ int bpmf_get_csc(bpmf_ctx *c, int64_t *ptr, int32_t *row, void *rc);
 
 /* The degree plan of a side: perm[rows] = row ids in processing order
  * (degree descending, ties by row id), n_split = number of rows split
- * across wavefronts (they come first in perm).  Either pointer may be NULL. */
-int bpmf_get_plan(bpmf_ctx *c, int32_t side, int32_t *perm, int64_t *n_split);
+ * across wavefronts (they come first in perm), n_low = number of rows on the
+ * rank-one-update path (the last ones in perm).  Any pointer may be NULL. */
+int bpmf_get_plan(bpmf_ctx *c, int32_t side, int32_t *perm, int64_t *n_split, int64_t *n_low);
 
 /* Mean training rating subtracted from the ratings (0 when center = 0). */
 double bpmf_mean_rating(const bpmf_ctx *c);
@@ -175,22 +176,28 @@ int bpmf_synchronize(bpmf_ctx *c);
  * bpmf_update_side / bpmf_sample_hyper / bpmf_run_sweeps call. */
 int bpmf_last_time_ms(bpmf_ctx *c, double *ms);
 
-/* Autotuning of the degree-bucket cut-off and kernel family on the
+/* Autotuning of the degree-bucket cut-offs and kernel family on the
  * context's own data.  The paper balances per-item work by degree with a
- * fixed cost plus a cost per rating (Sec. III and IV-B); here the cut-off
- * above which a row is split into segments across wavefronts (and, for
- * FP32 with 32 < K <= 64, whether rows take the column-per-lane or the
- * blocked kernel) is chosen by timing n_sweeps (1..64) graph sweeps per
- * candidate: split thresholds 512, 1024, ... up to the first power of two
- * at or above the largest degree, and the current one; a candidate replaces
- * the current plan only if it is at least 2% faster.  The chain state (factors, hyperparameters,
- * running predictions, sweep counter) is restored afterwards, so the chain
- * continues exactly as if no trial had run; only the plan changes.  Outputs
- * (each may be NULL): the chosen threshold and kernel cut-off K (32 or 64),
- * the number of candidates tried (at most 64) and, per candidate, its
- * threshold, kernel cut-off and mean ms per sweep (caller arrays of 64). */
+ * fixed cost plus a cost per rating and switches small items to a cheaper
+ * serial method (Sec. III, Fig. 2, Sec. IV-B); here three cut-offs are chosen
+ * by timing n_sweeps (1..64) graph sweeps per candidate:
+ *   - the degree above which a row is split into segments across
+ *     wavefronts: 512, 1024, ... up to the first power of two at or above the
+ *     largest degree, and the current one;
+ *   - for FP32 with 32 < K <= 64, whether rows take the column-per-lane
+ *     (kmax 64) or the blocked (kmax 32) kernel;
+ *   - for FP32 with K <= 64, the degree up to which rows take the rank-one
+ *     update path (0 = off, 4, 8; a side uses it only where the saved
+ *     factorisations outweigh transforming the gathered factor).
+ * A candidate replaces the current plan only if it is at least 2% faster.
+ * The chain state (factors, hyperparameters, running predictions, sweep
+ * counter) is restored afterwards, so the chain continues as if no trial had
+ * run; only the plan changes.  Outputs (each may be NULL): the chosen values,
+ * the number of candidates tried (at most 64) and, per candidate, its values
+ * and mean ms per sweep (caller arrays of 64). */
 int bpmf_autotune(bpmf_ctx *c, uint32_t n_sweeps, int32_t *chosen_split, int32_t *chosen_kmax,
-                  int32_t *n_tried, int32_t *tried_split, int32_t *tried_kmax, double *tried_ms);
+                  int32_t *chosen_low, int32_t *n_tried, int32_t *tried_split, int32_t *tried_kmax,
+                  int32_t *tried_low, double *tried_ms);
 
 /* Mean device time (ms) of one launch of the row-update kernel (the work
  * items of the row loops of Algorithm 1, split-row finishing excluded) over

@@ -96,7 +96,7 @@ def lib() -> ctypes.CDLL:
         L.bpmf_synchronize.argtypes = [P]
         L.bpmf_last_time_ms.argtypes = [P, P]
         L.bpmf_row_kernel_ms.argtypes = [P, P]
-        L.bpmf_autotune.argtypes = [P, ctypes.c_uint32, P, P, P, P, P, P]
+        L.bpmf_autotune.argtypes = [P, ctypes.c_uint32, P, P, P, P, P, P, P, P]
         L.bpmf_last_error.argtypes = [P]
         L.bpmf_last_error.restype = ctypes.c_char_p
         L.bpmf_destroy.argtypes = [P]
@@ -262,8 +262,14 @@ class Sampler:
     def get_plan(self, side):
         perm = np.zeros(self.rows(side), np.int32)
         ns = ctypes.c_int64()
-        self._check(lib().bpmf_get_plan(self._ctx, side, _ptr(perm), ctypes.byref(ns)))
+        self._check(lib().bpmf_get_plan(self._ctx, side, _ptr(perm), ctypes.byref(ns), None))
         return perm, ns.value
+
+    def lowrank_rows(self, side):
+        """Number of rows of `side` on the rank-one-update path."""
+        nl = ctypes.c_int64()
+        self._check(lib().bpmf_get_plan(self._ctx, side, None, None, ctypes.byref(nl)))
+        return nl.value
 
     @property
     def mean_rating(self):
@@ -312,16 +318,17 @@ class Sampler:
         return ms.value
 
     def autotune(self, n_sweeps=3):
-        """Time candidate split thresholds (and kernel families) on this
-        context's data and keep the fastest; the chain state is unchanged.
-        Returns (split, kmax, [(split, kmax, ms_per_sweep), ...])."""
-        sp, km, nt = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        """Time candidate plans (split threshold, kernel family, rank-one
+        cut-off) on this context's data and keep the fastest; the chain state
+        is unchanged.  Returns (split, kmax, low, [(split, kmax, low, ms), ...])."""
+        sp, km, lo, nt = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         ts = (ctypes.c_int32 * 64)()
         tk = (ctypes.c_int32 * 64)()
+        tl = (ctypes.c_int32 * 64)()
         tm = (ctypes.c_double * 64)()
         self._check(lib().bpmf_autotune(self._ctx, n_sweeps, ctypes.byref(sp), ctypes.byref(km),
-                                        ctypes.byref(nt), ts, tk, tm))
-        return sp.value, km.value, [(ts[i], tk[i], tm[i]) for i in range(nt.value)]
+                                        ctypes.byref(lo), ctypes.byref(nt), ts, tk, tl, tm))
+        return sp.value, km.value, lo.value, [(ts[i], tk[i], tl[i], tm[i]) for i in range(nt.value)]
 
     def row_kernel_ms(self):
         """Mean per-launch device time (ms) of the row kernel of each side over

@@ -175,7 +175,7 @@ __global__ __launch_bounds__(kThreads) void hyper_draw(
     const double *__restrict__ W0inv, double beta0, double nu0, uint64_t seed, uint32_t stream,
     const uint32_t *__restrict__ ctr, uint32_t t_off, double *__restrict__ gbuf, int n_lds_bufs,
     double *__restrict__ mu_out, double *__restrict__ Lam_out, T *__restrict__ Lam_w,
-    T *__restrict__ Lmu_w, int *__restrict__ status)
+    T *__restrict__ Lmu_w, T *__restrict__ Linv_w, T *__restrict__ Ltmu_w, int *__restrict__ status)
 {
     extern __shared__ __align__(16) char smem_raw[];
     const int KK2 = K * (K + 1) / 2;
@@ -279,6 +279,51 @@ __global__ __launch_bounds__(kThreads) void hyper_draw(
         for (int j = 0; j <= i; ++j) s += Bm[pk(i, j)] * zv[j];
         Lmu_w[i] = (T)s;
     }
+    if (Linv_w) {
+        // for the rank-one row path: chol(Lambda)^-1 = B^-1 and B^T mu
+        for (int i = tid; i < K; i += kThreads) Ltmu_w[i] = (T)zv[i];
+        __syncthreads();
+        tri_inverse_packed(K, Bm, Ci);
+        for (int e = tid; e < K * K; e += kThreads) {
+            const int r = e / K, cc = e - (e / K) * K;
+            Linv_w[e] = cc <= r ? (T)Ci[pk(r, cc)] : (T)0;
+        }
+    }
+    if (tid == 0 && !ok) *status = 0;
+}
+
+// For the rank-one row path after (mu, Lambda) were set by the host:
+// chol(Lambda)^-1 and chol(Lambda)^T mu, FP64 in one workgroup.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void prior_factor(int K, const double *__restrict__ mu,
+                                                         const double *__restrict__ Lam,
+                                                         T *__restrict__ Linv_w, T *__restrict__ Ltmu_w,
+                                                         int *__restrict__ status)
+{
+    extern __shared__ __align__(16) char smem_raw[];
+    const int KK2 = K * (K + 1) / 2;
+    double *P = (double *)smem_raw;
+    double *Ci = P + KK2;
+    __shared__ int ok;
+    const int tid = threadIdx.x;
+    if (tid == 0) ok = 1;
+    for (int e = tid; e < KK2; e += kThreads) {
+        int r, c;
+        tri_index(e, r, c);
+        P[e] = Lam[r * K + c];
+    }
+    __syncthreads();
+    chol_packed(K, P, &ok);
+    tri_inverse_packed(K, P, Ci);
+    for (int e = tid; e < K * K; e += kThreads) {
+        const int r = e / K, cc = e - (e / K) * K;
+        Linv_w[e] = cc <= r ? (T)Ci[pk(r, cc)] : (T)0;
+    }
+    for (int i = tid; i < K; i += kThreads) {
+        double s = 0.0;
+        for (int j = i; j < K; ++j) s += P[pk(j, i)] * mu[j];
+        Ltmu_w[i] = (T)s;
+    }
     if (tid == 0 && !ok) *status = 0;
 }
 
@@ -347,12 +392,15 @@ hipError_t launch_hyper(bpmf_ctx *c, int side_id, hipStream_t s, uint32_t t_off)
         hipLaunchKernelGGL((hyper_draw<double>), dim3(1), dim3(kThreads), lds2, s, K, rows,
                            stats, c->d_mu0, c->d_W0inv, c->beta0, c->nu0, c->seed,
                            sd.stream_hyp, c->ctr, t_off, scratch, nb, sd.mu, sd.Lam,
-                           (double *)sd.Lam_w, (double *)sd.Lmu_w, c->hyp_status);
+                           (double *)sd.Lam_w, (double *)sd.Lmu_w, (double *)nullptr,
+                           (double *)nullptr, c->hyp_status);
     else
         hipLaunchKernelGGL((hyper_draw<float>), dim3(1), dim3(kThreads), lds2, s, K, rows,
                            stats, c->d_mu0, c->d_W0inv, c->beta0, c->nu0, c->seed,
                            sd.stream_hyp, c->ctr, t_off, scratch, nb, sd.mu, sd.Lam,
-                           (float *)sd.Lam_w, (float *)sd.Lmu_w, c->hyp_status);
+                           (float *)sd.Lam_w, (float *)sd.Lmu_w,
+                           sd.n_low ? (float *)sd.Linv_w : (float *)nullptr,
+                           sd.n_low ? (float *)sd.Ltmu_w : (float *)nullptr, c->hyp_status);
     return hipGetLastError();
 }
 
@@ -380,6 +428,13 @@ hipError_t prepare_hyper(bpmf_ctx *c)
 hipError_t launch_prior_to_working(bpmf_ctx *c, int side_id, hipStream_t s)
 {
     Side &sd = c->side[side_id];
+    if (sd.n_low && c->prec == 1) {
+        const size_t lds = sizeof(double) * (size_t)c->K * (c->K + 1);
+        hipLaunchKernelGGL((prior_factor<float>), dim3(1), dim3(kThreads), lds, s, c->K, sd.mu, sd.Lam,
+                           (float *)sd.Linv_w, (float *)sd.Ltmu_w, c->hyp_status);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     if (c->prec == 0)
         hipLaunchKernelGGL((prior_to_working<double>), dim3(1), dim3(256), 0, s, c->K, sd.mu,
                            sd.Lam, (double *)sd.Lam_w, (double *)sd.Lmu_w);

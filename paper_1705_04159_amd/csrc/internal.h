@@ -58,6 +58,13 @@ struct Side {
     int64_t n_slots = 0;
     std::vector<int32_t> perm;  // host copy of the processing order
     std::vector<int64_t> hptr;  // host copy of the neighbour offsets (re-planning)
+    // rows with few ratings on the rank-one-update path: the last n_low
+    // work items; L_Lam^-1 and L_Lam^T mu from the hyper draw, and the
+    // gathered factor premultiplied by L_Lam^-1
+    int64_t n_low = 0;
+    void *Linv_w = nullptr;   // device [K * K] FP32
+    void *Ltmu_w = nullptr;   // device [K] FP32
+    float *Yt = nullptr;      // device [other rows * ld]
     int64_t n_split = 0;
     uint32_t stream_row = 0, stream_hyp = 0, stream_init = 0;
 };
@@ -76,6 +83,7 @@ struct bpmf_ctx {
     int burn_in = 0;
     int split_threshold = 0;
     int fast_kmax = 32;  // FP32 rows up to this K take the column-per-lane kernel
+    int low_dmax = 0;    // rows with at most this many ratings take the rank-one path (0: off)
     double *d_mu0 = nullptr, *d_W0inv = nullptr;
     bpmf::Side side[2];
     // test set
@@ -149,6 +157,9 @@ size_t row_generic_lds_bytes(int K, int prec);
 bool fast_path_available(const bpmf_ctx *c);
 // Row kernel for FP32 with 32 < K <= 128 and BF16-Gram with K <= 128.
 bool big_path_available(const bpmf_ctx *c);
+// Rank-one-update path for rows with few ratings (FP32, K <= 64).
+bool lowrank_available(const bpmf_ctx *c);
+hipError_t launch_row_lowrank(bpmf_ctx *c, int side_id, hipStream_t s);
 // Elements of one split-row partial slot: K(K+1)/2 + K packed for the
 // column-per-lane and generic kernels, the accumulator image of the blocked
 // kernel otherwise.

@@ -460,7 +460,7 @@ hipError_t launch_big(bpmf_ctx *c, Side &sd, Side &ot, hipStream_t s, int stage)
         return hipGetLastError();
     }
     // segments of split rows (items [0, n_slots)), then whole rows
-    const int64_t n_seg = sd.n_slots, n_rows = sd.n_items - sd.n_slots;
+    const int64_t n_seg = sd.n_slots, n_rows = sd.n_items - sd.n_slots - sd.n_low;
     const bool bf = c->prec == 2;
     const void *ysrc = bf ? (const void *)ot.Xbf : (const void *)ot.X;
     const uint32_t y_bytes = (uint32_t)(ot.rows * c->ld * (bf ? 2 : 4));

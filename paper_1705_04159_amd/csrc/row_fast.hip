@@ -366,11 +366,13 @@ hipError_t launch_f32(bpmf_ctx *c, Side &sd, Side &ot, hipStream_t s)
 {
     constexpr int KP = 16 * NB;
     const size_t lds = sizeof(float) * WPB * RPW * (KP * (KP + 1) / 2 + KP);
+    const int64_t n_items = sd.n_items - sd.n_low;  // the rank-one path takes the tail
     const int64_t per_block = (int64_t)WPB * RPW;
-    const unsigned grid = (unsigned)((sd.n_items + per_block - 1) / per_block);
+    const unsigned grid = (unsigned)((n_items + per_block - 1) / per_block);
     const uint32_t y_bytes = (uint32_t)(ot.rows * c->ld * sizeof(float));
+    if (n_items == 0) return hipSuccess;
     hipLaunchKernelGGL((row_fast_f32<NB, RPW, WPB>), dim3(grid), dim3(64 * WPB), lds, s, c->K,
-                       (float)c->alpha, sd.items, sd.n_items, sd.nbr, (const float *)sd.rc,
+                       (float)c->alpha, sd.items, n_items, sd.nbr, (const float *)sd.rc,
                        (const float *)ot.X, c->ld, y_bytes, (const float *)sd.Lam_w,
                        (const float *)sd.Lmu_w, (float *)sd.X, c->ld, (float *)c->part, c->seed,
                        sd.stream_row, c->ctr);

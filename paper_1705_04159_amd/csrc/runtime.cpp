@@ -112,7 +112,7 @@ bool spd_inverse_host(int K, const std::vector<double> &A, std::vector<double> &
 // `seg` ratings whose partial sums land in consecutive slots.
 void plan_side(const std::vector<int64_t> &ptr, int64_t rows, int64_t split, int64_t seg,
                std::vector<int32_t> &perm, int64_t &n_split, std::vector<RowItem> &items,
-               std::vector<FinishItem> &fin, int64_t &n_slots)
+               std::vector<FinishItem> &fin, int64_t &n_slots, int64_t low_dmax, int64_t &n_low)
 {
     perm.resize(rows);
     std::iota(perm.begin(), perm.end(), 0);
@@ -135,10 +135,32 @@ void plan_side(const std::vector<int64_t> &ptr, int64_t rows, int64_t split, int
         }
         fin.push_back(f);
     }
+    n_low = 0;
     for (int64_t q = n_split; q < rows; ++q) {
         int32_t r = perm[q];
         items.push_back(RowItem{r, -1, ptr[r], ptr[r + 1]});
+        if (ptr[r + 1] - ptr[r] <= low_dmax) ++n_low;  // a suffix: degrees descend
     }
+}
+
+// Whether a side's rows with at most low_dmax ratings take the rank-one path:
+// worth it when the factorisations saved (K^3/3 each) outweigh transforming
+// the gathered factor (K^2 per row of the other side) several times over.
+int64_t low_rows_used(const bpmf_ctx *c, int64_t n_low, int64_t other_rows)
+{
+    if (c->low_dmax <= 0 || !lowrank_available(c)) return 0;
+    const double K = (double)c->K;
+    return (double)n_low * K * K * K / 3.0 > 4.0 * (double)other_rows * K * K ? n_low : 0;
+}
+
+// Device buffers of the rank-one path for a side that uses it.
+hipError_t alloc_lowrank(bpmf_ctx *c, Side &sd, int64_t other_rows)
+{
+    hipError_t e = hipSuccess;
+    if (!sd.Linv_w && (e = hipMalloc(&sd.Linv_w, sizeof(float) * c->K * c->K)) != hipSuccess) return e;
+    if (!sd.Ltmu_w && (e = hipMalloc(&sd.Ltmu_w, sizeof(float) * c->K)) != hipSuccess) return e;
+    if (!sd.Yt) e = hipMalloc(&sd.Yt, sizeof(float) * std::max<int64_t>(1, other_rows * c->ld));
+    return e;
 }
 
 size_t elem_bytes(const bpmf_ctx *c) { return c->prec == 0 ? sizeof(double) : sizeof(float); }
@@ -153,6 +175,8 @@ hipError_t enqueue_update_stage(bpmf_ctx *c, int side_id, hipStream_t s, int sta
     if (!handled) e = launch_row_big(c, side_id, s, stage, &handled);
     if (e != hipSuccess) return e;
     if (!handled) e = launch_row_generic(c, side_id, s, stage);
+    if (e != hipSuccess) return e;
+    if (stage == 0 && c->side[side_id].n_low) e = launch_row_lowrank(c, side_id, s);
     if (e != hipSuccess) return e;
     if (stage == 1 && c->prec == 2) e = launch_to_bf16(c, side_id, s);
     return e;
@@ -224,7 +248,8 @@ hipError_t enqueue_sweep(bpmf_ctx *c, hipStream_t s)
 
 void free_side(Side &s)
 {
-    void *ps[] = {s.ptr, s.nbr, s.rc, s.X, s.Xbf, s.mu, s.Lam, s.Lam_w, s.Lmu_w, s.items, s.fin};
+    void *ps[] = {s.ptr, s.nbr, s.rc, s.X, s.Xbf, s.mu, s.Lam, s.Lam_w, s.Lmu_w, s.items, s.fin,
+                  s.Linv_w, s.Ltmu_w, s.Yt};
     for (void *p : ps) (void)hipFree(p);
 }
 
@@ -346,6 +371,8 @@ int bpmf_create(int64_t M, int64_t N, const int64_t *csr_ptr, const int32_t *csr
     // a segment's partial sums are large and its Gram long enough to keep
     // the waves busy)
     c->split_threshold = p->split_threshold > 0 ? p->split_threshold : (K > 64 ? 8192 : 2048);
+    // rank-one path for rows with at most 8 ratings where it pays (FP32, K <= 64)
+    c->low_dmax = lowrank_available(c) ? 8 : 0;
     c->foldin_S = p->foldin_S > 0 ? p->foldin_S : 16;
     c->foldin_pool = p->foldin_pool_bytes;
     double rbar = 0.0;
@@ -410,9 +437,12 @@ int bpmf_create(int64_t M, int64_t N, const int64_t *csr_ptr, const int32_t *csr
             sd.hptr = *ptrs[sid];
             std::vector<RowItem> items;
             std::vector<FinishItem> fin;
+            int64_t n_low = 0;
             plan_side(*ptrs[sid], sd.rows, c->split_threshold,
                       std::max<int64_t>(128, c->split_threshold / 2), sd.perm, sd.n_split, items,
-                      fin, sd.n_slots);
+                      fin, sd.n_slots, c->low_dmax, n_low);
+            sd.n_low = low_rows_used(c, n_low, sid == 0 ? N : M);
+            if (sd.n_low) CK(alloc_lowrank(c, sd, sid == 0 ? N : M));
             sd.n_items = (int64_t)items.size();
             sd.n_fin = (int64_t)fin.size();
             CK(dalloc(&sd.items, items.size()));
@@ -582,17 +612,22 @@ static int find_timing_nodes(bpmf_ctx *c)
 // Re-plan both sides for a new split threshold / kernel family: work items,
 // finishing items and the partial-sum workspace; the sweep graph is rebuilt
 // on the next bpmf_run_sweeps.
-static int replan(bpmf_ctx *c, int split, int fast_kmax)
+static int replan(bpmf_ctx *c, int split, int fast_kmax, int low_dmax)
 {
     HIPCK(c, hipStreamSynchronize(c->stream));
     c->split_threshold = split;
     c->fast_kmax = fast_kmax;
+    c->low_dmax = low_dmax;
     for (int sid = 0; sid < 2; ++sid) {
         Side &sd = c->side[sid];
         std::vector<RowItem> items;
         std::vector<FinishItem> fin;
+        int64_t n_low = 0;
         plan_side(sd.hptr, sd.rows, split, std::max<int64_t>(128, split / 2), sd.perm, sd.n_split,
-                  items, fin, sd.n_slots);
+                  items, fin, sd.n_slots, low_dmax, n_low);
+        const int64_t other = c->side[1 - sid].rows;
+        sd.n_low = low_rows_used(c, n_low, other);
+        if (sd.n_low) HIPCK(c, alloc_lowrank(c, sd, other));
         (void)hipFree(sd.items);
         (void)hipFree(sd.fin);
         sd.items = nullptr;
@@ -670,8 +705,18 @@ static void snapshot_free(ChainSnapshot &sn)
 
 int bpmf_run_sweeps(bpmf_ctx *c, uint32_t t0, uint32_t n, double *rmse_avg, double *rmse_last);
 
+// Rank-one path inputs from the current (mu, Lambda) of each side using it.
+static int refresh_lowrank(bpmf_ctx *c)
+{
+    for (int sid = 0; sid < 2; ++sid)
+        if (c->side[sid].n_low) HIPCK(c, launch_prior_to_working(c, sid, c->stream));
+    HIPCK(c, hipStreamSynchronize(c->stream));
+    return BPMF_OK;
+}
+
 int bpmf_autotune(bpmf_ctx *c, uint32_t n_sweeps, int32_t *chosen_split, int32_t *chosen_kmax,
-                  int32_t *n_tried, int32_t *tried_split, int32_t *tried_kmax, double *tried_ms)
+                  int32_t *chosen_low, int32_t *n_tried, int32_t *tried_split, int32_t *tried_kmax,
+                  int32_t *tried_low, double *tried_ms)
 {
     STICKY(c);
     if (n_sweeps == 0 || n_sweeps > 64) return fail(c, BPMF_E_INVAL, "n_sweeps must be 1..64");
@@ -689,18 +734,22 @@ int bpmf_autotune(bpmf_ctx *c, uint32_t n_sweeps, int32_t *chosen_split, int32_t
         splits.push_back(c->split_threshold);
     std::vector<int> kmaxes = {c->fast_kmax};
     if (c->prec == BPMF_FP32 && c->K > 32 && c->K <= 64) kmaxes = {32, 64};
-    const int old_split = c->split_threshold, old_kmax = c->fast_kmax;
+    std::vector<int> lows = {c->low_dmax};
+    if (lowrank_available(c)) lows = {0, 4, 8};
+    const int old_split = c->split_threshold, old_kmax = c->fast_kmax, old_low = c->low_dmax;
     ChainSnapshot sn;
     if (int r = snapshot_take(c, sn)) {
         snapshot_free(sn);
         return r;
     }
-    int best_split = old_split, best_kmax = old_kmax, q = 0, rc = BPMF_OK;
+    int best_split = old_split, best_kmax = old_kmax, best_low = old_low, q = 0, rc = BPMF_OK;
     double best = 1e300, incumbent = 1e300;
+    for (int ld : lows)
     for (int km : kmaxes)
         for (int sp : splits) {
-            if ((rc = replan(c, sp, km)) != BPMF_OK) break;
+            if ((rc = replan(c, sp, km, ld)) != BPMF_OK) break;
             if ((rc = snapshot_restore(c, sn)) != BPMF_OK) break;
+            if ((rc = refresh_lowrank(c)) != BPMF_OK) break;
             // one untimed sweep builds the graph, then n_sweeps timed
             if ((rc = bpmf_run_sweeps(c, 1, 1, nullptr, nullptr)) != BPMF_OK) break;
             if ((rc = bpmf_run_sweeps(c, 2, n_sweeps, nullptr, nullptr)) != BPMF_OK) break;
@@ -708,27 +757,32 @@ int bpmf_autotune(bpmf_ctx *c, uint32_t n_sweeps, int32_t *chosen_split, int32_t
             if (q < 64) {
                 if (tried_split) tried_split[q] = sp;
                 if (tried_kmax) tried_kmax[q] = km;
+                if (tried_low) tried_low[q] = ld;
                 if (tried_ms) tried_ms[q] = ms;
             }
             ++q;
-            if (sp == old_split && km == old_kmax) incumbent = ms;
+            if (sp == old_split && km == old_kmax && ld == old_low) incumbent = ms;
             if (ms < best) {
                 best = ms;
                 best_split = sp;
                 best_kmax = km;
+                best_low = ld;
             }
         }
     // keep the current plan unless a candidate is clearly faster (timing noise)
     if (best > 0.98 * incumbent) {
         best_split = old_split;
         best_kmax = old_kmax;
+        best_low = old_low;
     }
-    if (rc == BPMF_OK) rc = replan(c, best_split, best_kmax);
+    if (rc == BPMF_OK) rc = replan(c, best_split, best_kmax, best_low);
     if (rc == BPMF_OK) rc = snapshot_restore(c, sn);
+    if (rc == BPMF_OK) rc = refresh_lowrank(c);
     snapshot_free(sn);
     if (rc != BPMF_OK) return rc;
     if (chosen_split) *chosen_split = best_split;
     if (chosen_kmax) *chosen_kmax = best_kmax;
+    if (chosen_low) *chosen_low = best_low;
     if (n_tried) *n_tried = std::min(q, 64);
     return BPMF_OK;
 }
@@ -988,13 +1042,14 @@ int bpmf_get_csc(bpmf_ctx *c, int64_t *ptr, int32_t *row, void *rc)
     return BPMF_OK;
 }
 
-int bpmf_get_plan(bpmf_ctx *c, int32_t side, int32_t *perm, int64_t *n_split)
+int bpmf_get_plan(bpmf_ctx *c, int32_t side, int32_t *perm, int64_t *n_split, int64_t *n_low)
 {
     STICKY(c);
     if (int r = check_side(c, side)) return r;
     Side &sd = c->side[side];
     if (perm) memcpy(perm, sd.perm.data(), sizeof(int32_t) * sd.rows);
     if (n_split) *n_split = sd.n_split;
+    if (n_low) *n_low = sd.n_low;
     return BPMF_OK;
 }
 

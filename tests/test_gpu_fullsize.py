@@ -85,6 +85,26 @@ def test_full_size_sampled_rows(bp, orc, name, K, prec):
                                                                  np.median(err)), flush=True)
         assert np.isfinite(got[rows]).all()
         assert err.max() <= TOL[prec], (side, err.max(), rows[np.argmax(err)])
+        if prec == "bf16":
+            # the BF16-Gram error itself: against the oracle on the unrounded
+            # FP32 neighbour rows, with each sampled row's condition number
+            X2 = X0.copy()
+            if side == bp.SIDE_V:
+                orc.update_rows(cptr, crow, csc_rc, Y, X2, mu, Lam, 2.0, seed, orc.ROW_V, t, rows=rows)
+                ptr, idx = cptr, crow
+            else:
+                orc.update_rows(r.csr_ptr, r.csr_col, csr_rc, Y, X2, mu, Lam, 2.0, seed, orc.ROW_U, t,
+                                rows=rows)
+                ptr, idx = r.csr_ptr, r.csr_col
+            e2 = np.linalg.norm(got[rows] - X2[rows], axis=1) / np.maximum(
+                np.linalg.norm(X2[rows], axis=1), 1e-3 * np.sqrt(K))
+            kappa = np.array([np.linalg.cond(Lam + 2.0 * Y[idx[ptr[q]:ptr[q + 1]]].T @ Y[idx[ptr[q]:ptr[q + 1]]])
+                              for q in rows])
+            print("  side %d BF16-Gram vs FP64 on unrounded rows: max %.3e, p99 %.3e, median %.3e; "
+                  "kappa(P) median %.1f max %.1f; corr(log err, log kappa) %.2f" % (
+                      side, e2.max(), np.percentile(e2, 99), np.median(e2), np.median(kappa),
+                      kappa.max(), np.corrcoef(np.log(e2 + 1e-30), np.log(kappa))[0, 1]), flush=True)
+            assert e2.max() <= TOL["bf16"], (side, e2.max())
     s.close()
 
 

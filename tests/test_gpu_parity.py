@@ -353,10 +353,11 @@ def test_autotune_keeps_the_chain(bp, K):
     b = bp.Sampler(r, K, prec="fp32", seed=3)
     a.run_sweeps(1, 2)
     b.run_sweeps(1, 2)
-    split, kmax, tried = a.autotune(2)
-    assert len(tried) >= 2 and all(ms > 0 for _, _, ms in tried)
-    assert (split, kmax) in [(s, k) for s, k, _ in tried]
-    assert {k for _, k, _ in tried} == ({32, 64} if K == 48 else {32})
+    split, kmax, low, tried = a.autotune(2)
+    assert len(tried) >= 2 and all(ms > 0 for _, _, _, ms in tried)
+    assert (split, kmax, low) in [(s, k, l) for s, k, l, _ in tried]
+    assert {k for _, k, _, _ in tried} == ({32, 64} if K == 48 else {32})
+    assert {l for _, _, l, _ in tried} == {0, 4, 8}
     for side in (bp.SIDE_U, bp.SIDE_V):
         assert np.array_equal(a.get_factor(side), b.get_factor(side))
         ma, la = a.get_hyper(side)
@@ -367,3 +368,22 @@ def test_autotune_keeps_the_chain(bp, K):
     assert abs(avg_a[-1] / avg_b[-1] - 1) <= 5e-3
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("K", [10, 32, 48, 64])
+def test_lowrank_rows_single_step(bp, orc, K):
+    """Rows with few ratings (Poisson(3) users against 200 movies) take the
+    rank-one-update path; the draws match the oracle's full factorisation."""
+    r = synth.random_small(60 + K, 3000, 200, 9000, min(K, 12), empty_rows=40)
+    s = bp.Sampler(r, K, prec="fp32", seed=1)
+    n_low = s.lowrank_rows(bp.SIDE_U)
+    deg = np.diff(r.csr_ptr)
+    assert n_low == int((deg <= 8).sum()) and n_low > 2000
+    assert s.lowrank_rows(bp.SIDE_V) == 0
+    s.close()
+    err, got, ref = single_step(bp, orc, r, K, "fp32", bp.SIDE_U)
+    assert np.isfinite(got).all()
+    assert err.max() <= TOL["fp32"], (err.max(), np.argmax(err))
+    # a second state and sweep index
+    err2, _, _ = single_step(bp, orc, r, K, "fp32", bp.SIDE_U, t=9, seed=5)
+    assert err2.max() <= TOL["fp32"]
