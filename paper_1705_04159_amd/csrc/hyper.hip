@@ -13,7 +13,7 @@
 // row-major order), then mu = mu* + chol(beta* Lambda)^-T z.
 //
 // Three launches: per-block FP64 moment sums over row chunks (S is formed as
-// sum x x^T - n xbar xbar^T), a fixed-order reduction of the block sums (one
+// sum x x^T - n xbar xbar^T; on the FP64 matrix cores for K <= 112), a fixed-order reduction of the block sums (one
 // wavefront per entry), and one workgroup for the K x K algebra.  The
 // algebra avoids forming W* and two of the three factorisations:
 //   * L_W is obtained from one Cholesky of the index-reversed W*^-1:
@@ -25,6 +25,7 @@
 //     mu = mu* + B^-T z / sqrt(beta*).
 // All K x K matrices are packed lower triangles in LDS when they fit.
 #include <algorithm>
+#include <type_traits>
 
 #include "internal.h"
 #include "rng_device.h"
@@ -96,6 +97,76 @@ __global__ __launch_bounds__(kThreads) void hyper_moments(int K, const XT *__res
         const int e = tid + m * kThreads;
         if (e < E) part[(size_t)blockIdx.x * E + e] = acc[m];
     }
+}
+
+// The same block sums on the FP64 matrix cores (nb = ceil(K/16) <= 7): one
+// wavefront per block of rows, four rows per v_mfma_f64_16x16x4f64 step --
+// lane l holds component 16*bi + (l % 16) of row 4g + l / 16 as an FP64
+// value (FP32 factors convert exactly), which is both the A operand of block
+// row bi and the B operand of block column bj, so only the nb(nb+1)/2 lower
+// 16x16 blocks of X^T X are accumulated; sum x on the VALU from the same
+// registers.  (The FP64 instruction returns D[4 v + l / 16][l % 16] in value v
+// of lane l, unlike the FP32 one.)  Products of FP32 values are exact in
+// FP64, and every sum is in FP64 in a fixed order.
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+template <int NB, typename XT>
+__global__ __launch_bounds__(64) void hyper_moments_mfma(int K, const XT *__restrict__ X, int ld,
+                                                         int64_t rows, int64_t chunk,
+                                                         double *__restrict__ part)
+{
+    constexpr int NBLK = NB * (NB + 1) / 2;
+    const int lane = threadIdx.x;
+    const int col = lane & 15, kq = lane >> 4;
+    const int64_t r0 = (int64_t)blockIdx.x * chunk;
+    const int64_t r1 = min<int64_t>(rows, r0 + chunk);
+    const int E = K + K * (K + 1) / 2;
+    doublex4 acc[NBLK];
+#pragma unroll
+    for (int q = 0; q < NBLK; ++q) acc[q] = doublex4{0.0, 0.0, 0.0, 0.0};
+    double sx[NB];
+#pragma unroll
+    for (int bi = 0; bi < NB; ++bi) sx[bi] = 0.0;
+    for (int64_t base = r0; base < r1; base += 4) {
+        const int64_t r = base + kq;
+        double y[NB];
+#pragma unroll
+        for (int bi = 0; bi < NB; ++bi) {
+            const int c = 16 * bi + col;
+            y[bi] = (r < r1 && c < K) ? as_f64(X[(size_t)r * ld + c]) : 0.0;
+            sx[bi] += y[bi];
+        }
+        int q = 0;
+#pragma unroll
+        for (int bi = 0; bi < NB; ++bi)
+#pragma unroll
+            for (int bj = 0; bj <= bi; ++bj) {
+                acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(y[bi], y[bj], acc[q], 0, 0, 0);
+                ++q;
+            }
+    }
+    double *dst = part + (size_t)blockIdx.x * E;
+#pragma unroll
+    for (int bi = 0; bi < NB; ++bi) {
+        double t = sx[bi];
+        t += __shfl_xor(t, 16);
+        t += __shfl_xor(t, 32);
+        const int c = 16 * bi + col;
+        if (kq == 0 && c < K) dst[c] = t;
+    }
+    int q = 0;
+#pragma unroll
+    for (int bi = 0; bi < NB; ++bi)
+#pragma unroll
+        for (int bj = 0; bj <= bi; ++bj) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                // FP64 result layout: lane l, value v holds D[4 v + l / 16][l % 16]
+                const int i = 16 * bi + 4 * v + kq, j = 16 * bj + col;
+                if (i < K && j <= i) dst[K + pk(i, j)] = acc[q][v];
+            }
+            ++q;
+        }
 }
 
 // stats[e] = sum over blocks of part[b][e]: one wavefront per entry, lane l
@@ -380,11 +451,33 @@ hipError_t launch_hyper(bpmf_ctx *c, int side_id, hipStream_t s, uint32_t t_off)
     if (chunk < 1) chunk = 1;
     int used = (int)((rows + chunk - 1) / chunk);
     if (used < 1) used = 1;
-    const int ne = (E + kThreads - 1) / kThreads;
-    if (ne <= 3) launch_moments<3>(c, sd, part, used, chunk, s);
-    else if (ne <= 9) launch_moments<9>(c, sd, part, used, chunk, s);
-    else if (ne <= 21) launch_moments<21>(c, sd, part, used, chunk, s);
-    else launch_moments<33>(c, sd, part, used, chunk, s);
+    const int nbk = (K + 15) / 16;
+    if (nbk <= 7) {
+        auto go = [&](auto nbc) {
+            constexpr int NB = decltype(nbc)::value;
+            if (c->prec == 0)
+                hipLaunchKernelGGL((hyper_moments_mfma<NB, double>), dim3(used), dim3(64), 0, s, K,
+                                   (const double *)sd.X, c->ld, rows, chunk, part);
+            else
+                hipLaunchKernelGGL((hyper_moments_mfma<NB, float>), dim3(used), dim3(64), 0, s, K,
+                                   (const float *)sd.X, c->ld, rows, chunk, part);
+        };
+        switch (nbk) {
+        case 1: go(std::integral_constant<int, 1>{}); break;
+        case 2: go(std::integral_constant<int, 2>{}); break;
+        case 3: go(std::integral_constant<int, 3>{}); break;
+        case 4: go(std::integral_constant<int, 4>{}); break;
+        case 5: go(std::integral_constant<int, 5>{}); break;
+        case 6: go(std::integral_constant<int, 6>{}); break;
+        default: go(std::integral_constant<int, 7>{}); break;
+        }
+    } else {
+        const int ne = (E + kThreads - 1) / kThreads;
+        if (ne <= 3) launch_moments<3>(c, sd, part, used, chunk, s);
+        else if (ne <= 9) launch_moments<9>(c, sd, part, used, chunk, s);
+        else if (ne <= 21) launch_moments<21>(c, sd, part, used, chunk, s);
+        else launch_moments<33>(c, sd, part, used, chunk, s);
+    }
     hipLaunchKernelGGL(hyper_reduce, dim3((E + 3) / 4), dim3(256), 0, s, E, used, part, stats);
     const int nb = lds_buffers(K, c->hyp_lds_max);
     const size_t lds2 = draw_lds(K, nb);

@@ -467,7 +467,7 @@ int bpmf_create(int64_t M, int64_t N, const int64_t *csr_ptr, const int32_t *csr
         CK(dalloc(&c->d_W0inv, (size_t)K * K));
         CK(hipMemcpy(c->d_mu0, mu0.data(), sizeof(double) * K, hipMemcpyHostToDevice));
         CK(hipMemcpy(c->d_W0inv, W0inv.data(), sizeof(double) * K * K, hipMemcpyHostToDevice));
-        c->hyp_blocks = 512;
+        c->hyp_blocks = K <= 64 ? 2048 : 1024;  // row blocks of the moment sums (one wave each on the matrix-core path)
         for (int sid = 0; sid < 2; ++sid) {
             CK(dalloc(&c->hyp_part[sid], (size_t)c->hyp_blocks * (K + KK2)));
             CK(dalloc(&c->hyp_stats[sid], (size_t)(K + KK2)));
