@@ -57,6 +57,87 @@ def algorithmic(K, nnz, rows_finished, rows_written, gather_row_bytes, src_bytes
     return gram, fact, byts
 
 
+PEAK_FP64_TFLOPS = 78.6  # MI355X dense FP64 (matrix cores), TFLOP/s
+GATHER_SOURCES_MB = (3.4, 18.0, 96.0, 192.0)  # one L2, Infinity Cache, HBM-sized sources
+
+
+def measure_peaks(row_bytes, src_bytes):
+    """Peaks measured on this GPU by the library's micro-benchmarks: a stream
+    triad (HBM), the FP32 vector and the FP32 / BF16 / FP64 matrix-core
+    rates, and random whole-row gathers of `row_bytes` (the gathered factor's
+    row, rounded up to 16 B) from sources of the standard sizes and of this
+    workload's two factors (`src_bytes`)."""
+    import paper_1705_04159_amd as bp
+
+    rb = (row_bytes + 15) // 16 * 16
+    out = {
+        "hbm_triad_gbs": round(bp.peak_triad(1 << 30, 10), 1),
+        "fp32_valu_tflops": round(bp.peak_compute(bp.PEAK_FP32_VALU), 2),
+        "fp32_mfma_tflops": round(bp.peak_compute(bp.PEAK_FP32_MFMA), 2),
+        "bf16_mfma_tflops": round(bp.peak_compute(bp.PEAK_BF16_MFMA), 1),
+        "fp64_mfma_tflops": round(bp.peak_compute(bp.PEAK_FP64_MFMA), 2),
+        "gather_row_bytes": rb,
+        "gather_gbs": {},
+    }
+    sizes = sorted(set([int(mb * 1e6) for mb in GATHER_SOURCES_MB] + [int(b) for b in src_bytes]))
+    for b in sizes:
+        out["gather_gbs"][str(b)] = round(bp.peak_gather(max(b, rb), rb, 1 << 23, 5), 1)
+    return out
+
+
+def sweep_roofline(K, prec, r, ms_per_step, peaks):
+    """T_roof of one sweep: the sum over the two sides of
+    max(matrix-core time, vector time, memory time) of that side's row
+    updates, with the algorithmic work of `algorithmic` for every row and
+    rating.  Against the spec sheet (FP32 work at 157.3 TFLOP/s; in the
+    BF16-Gram form the Gram at 2.5 PFLOP/s and the factorisation at
+    157.3; bytes at 8 TB/s, the gather counted only when its source exceeds
+    one L2) and against the measured peaks (the same split of the work;
+    compulsory bytes at the triad rate plus every gathered row at the
+    measured gather rate for a source of that factor's size).  The fraction
+    is T_roof over the measured sweep time."""
+    esize = 8 if prec == "fp64" else (2 if prec == "bf16" else 4)
+    ld = K if prec == "fp64" else (K + 3) // 4 * 4
+    sides = {"V": (r.N, r.M * ld * esize), "U": (r.M, r.N * ld * esize)}
+    res = {"sides": {}}
+    tot_spec = tot_meas = 0.0
+    for name, (rows, src) in sides.items():
+        gram, fact, byts = algorithmic(K, r.nnz, rows, rows, ld * esize, src)
+        gathered = ld * esize * r.nnz
+        compulsory = byts - (gathered if src > L2_BYTES else 0)
+        if prec == "fp64":
+            spec = {"mfma": (gram + fact) / (PEAK_FP64_TFLOPS * 1e12), "valu": 0.0}
+        elif prec == "bf16":
+            spec = {"mfma": gram / (PEAK_BF16_TFLOPS * 1e12), "valu": fact / (PEAK_FP32_TFLOPS * 1e12)}
+        else:
+            spec = {"mfma": (gram + fact) / (PEAK_FP32_TFLOPS * 1e12), "valu": 0.0}
+        spec["hbm"] = byts / (PEAK_HBM_GBS * 1e9)
+        b_spec = max(spec, key=spec.get)
+        side = {"bound_spec": b_spec, "t_spec_ms": round(1e3 * spec[b_spec], 4)}
+        tot_spec += spec[b_spec]
+        if peaks:
+            p32 = max(peaks["fp32_mfma_tflops"], peaks["fp32_valu_tflops"]) * 1e12
+            if prec == "fp64":
+                meas = {"mfma": (gram + fact) / (peaks["fp64_mfma_tflops"] * 1e12), "valu": 0.0}
+            elif prec == "bf16":
+                meas = {"mfma": gram / (peaks["bf16_mfma_tflops"] * 1e12), "valu": fact / p32}
+            else:
+                meas = {"mfma": (gram + fact) / (peaks["fp32_mfma_tflops"] * 1e12), "valu": 0.0}
+            g = peaks["gather_gbs"][str(int(src))]
+            meas["memory"] = compulsory / (peaks["hbm_triad_gbs"] * 1e9) + gathered / (g * 1e9)
+            b_meas = max(meas, key=meas.get)
+            side.update({"bound_measured": b_meas, "t_measured_ms": round(1e3 * meas[b_meas], 4),
+                         "gather_gbs": g})
+            tot_meas += meas[b_meas]
+        res["sides"][name] = side
+    res["t_roof_ms_spec"] = round(1e3 * tot_spec, 4)
+    res["frac_spec"] = round(1e3 * tot_spec / ms_per_step, 4)
+    if peaks:
+        res["t_roof_ms_measured"] = round(1e3 * tot_meas, 4)
+        res["frac_measured"] = round(1e3 * tot_meas / ms_per_step, 4)
+    return res
+
+
 def profiled_traffic(workload, K, prec, side):
     """HBM bytes per launch of the row kernel from the committed rocprofv3
     counter summaries (FETCH_SIZE and WRITE_SIZE, each scaled by the same
@@ -81,10 +162,21 @@ def profiled_traffic(workload, K, prec, side):
     return None
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(r, K, seconds, seed):
     """The FP64 oracle timed on this host on a bounded sample of the same
     workload: random rows of both sides (in proportion M : N), updated with
-    the oracle's row routine and all host cores, until `seconds` elapse."""
+    the oracle's row routine, first on one thread for a quarter of `seconds`,
+    then on all host cores for the rest."""
     import oracle
 
     oracle.build()
@@ -93,26 +185,36 @@ def cpu_baseline(r, K, seconds, seed):
                       r.test_col[:1], r.test_val[:1], seed=seed)
     mu, lam = np.zeros(K), np.eye(K) * K
     order = rng.permutation(r.M + r.N)
-    done, t0 = 0, time.perf_counter()
-    batch = 512
-    while time.perf_counter() - t0 < seconds:
-        q = done % len(order)
-        sweep = 1 + done // len(order)
-        sel = order[q:q + batch]
-        u = sel[sel < r.M]
-        v = sel[sel >= r.M] - r.M
-        if len(v):
-            oracle.update_rows(ch.csc_ptr, ch.csc_row, ch.csc_rc, ch.U, ch.V, mu, lam, 2.0, seed,
-                               oracle.ROW_V, sweep, rows=v)
-        if len(u):
-            oracle.update_rows(ch.csr_ptr, ch.csr_col, ch.csr_rc, ch.V, ch.U, mu, lam, 2.0, seed,
-                               oracle.ROW_U, sweep, rows=u)
-        done += len(sel)
-    el = time.perf_counter() - t0
-    return {"value": done / el, "unit": "row-updates/s", "cores": oracle.max_threads(),
+    cores = oracle.max_threads()
+
+    def run(budget, start, batch):
+        done, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < budget:
+            q = (start + done) % len(order)
+            sweep = 1 + (start + done) // len(order)
+            sel = order[q:q + batch]
+            u = sel[sel < r.M]
+            v = sel[sel >= r.M] - r.M
+            if len(v):
+                oracle.update_rows(ch.csc_ptr, ch.csc_row, ch.csc_rc, ch.U, ch.V, mu, lam, 2.0, seed,
+                                   oracle.ROW_V, sweep, rows=v)
+            if len(u):
+                oracle.update_rows(ch.csr_ptr, ch.csr_col, ch.csr_rc, ch.V, ch.U, mu, lam, 2.0, seed,
+                                   oracle.ROW_U, sweep, rows=u)
+            done += len(sel)
+        return done, time.perf_counter() - t0
+
+    oracle.set_threads(1)
+    d1, e1 = run(0.25 * seconds, 0, 32)
+    oracle.set_threads(cores)
+    done, el = run(0.75 * seconds, d1, 512)
+    return {"value": done / el, "unit": "row-updates/s", "cores": cores,
             "kind": "oracle",
-            "sample": "%d row draws (FP64) over random rows of both sides of the same "
-                      "workload (%d rows per sweep), %.1f s" % (done, r.M + r.N, el)}
+            "one_thread_value": round(d1 / e1, 1),
+            "cpu_model": cpu_model(),
+            "sample": "%d row draws (FP64) over random rows of both sides of the same workload "
+                      "(%d rows per sweep) on %d threads in %.1f s, after %d on one thread in %.1f s" % (
+                          done, r.M + r.N, cores, el, d1, e1)}
 
 
 def foldin_requests(r, n_req, seed, max_n=5000):
@@ -139,13 +241,18 @@ def foldin_requests(r, n_req, seed, max_n=5000):
     return reqs, sizes
 
 
-def foldin_bench(s, r, rate, seconds, seed, top_n=100):
-    """Open-loop Poisson arrivals at `rate` req/s for `seconds`; latency is
-    completion (seen by the scheduler) minus the scheduled arrival time."""
+def foldin_bench(s, r, rate, seconds, seed, top_n=100, warm_seconds=0.0):
+    """Open-loop Poisson arrivals at `rate` req/s for `warm_seconds` +
+    `seconds`; latency is completion (seen by the scheduler) minus the
+    scheduled arrival time, reported over the requests that arrive after the
+    first `warm_seconds`."""
     rng = np.random.default_rng(seed + 1)
-    n_req = int(rate * seconds)
+    n_req = int(rate * (seconds + warm_seconds))
     arrivals = np.cumsum(rng.exponential(1.0 / rate, n_req))
-    reqs, sizes = foldin_requests(r, n_req, seed)
+    # at most 50,000 distinct requests, submitted cyclically on longer runs
+    uniq, usizes = foldin_requests(r, min(n_req, 50000), seed)
+    reqs = [uniq[i % len(uniq)] for i in range(n_req)]
+    sizes = usizes[np.arange(n_req) % len(uniq)]
     # warm the path (first batch allocations, kernel loads)
     for movie, rating in reqs[:8]:
         s.foldin_submit(movie, rating, top_n)
@@ -168,10 +275,13 @@ def foldin_bench(s, r, rate, seconds, seed, top_n=100):
     for i in range(n_req):
         res = s.foldin_poll(int(ids[i]), top_n)
         lat[i] = res[3] + lag[i]
+    keep = arrivals >= warm_seconds
+    lat, sizes = lat[keep], sizes[keep]
     return {
         "offered_req_per_s": rate,
         "completed_req_per_s": round(n_req / t_end, 1),
-        "n_requests": n_req,
+        "n_requests": int(keep.sum()),
+        "warmup_s": warm_seconds,
         "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 3),
         "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 3),
         "p999_ms": round(1e3 * float(np.percentile(lat, 99.9)), 3),
@@ -181,7 +291,7 @@ def foldin_bench(s, r, rate, seconds, seed, top_n=100):
     }
 
 
-def k100_compare(steps, seed, autotune=True):
+def k100_compare(steps, seed, autotune=True, with_peaks=True):
     """The 100M-rating shape at K = 100: the same chain (same seed, same
     Philox draws) in FP32 and in the BF16-Gram form, `steps` timed sweeps
     each after two warm-up sweeps; reports throughput and the held-out RMSE
@@ -193,6 +303,10 @@ def k100_compare(steps, seed, autotune=True):
     log("generated %s: M=%d N=%d nnz=%d in %.1fs" % (r.name, r.M, r.N, r.nnz, time.perf_counter() - t))
     out = {"workload": r.name, "M": r.M, "N": r.N, "nnz_train": r.nnz, "K": 100, "steps": steps}
     for prec in ("fp32", "bf16"):
+        peaks = None
+        if with_peaks:
+            rb = (100 + 3) // 4 * 4 * (2 if prec == "bf16" else 4)  # row stride of the gathered factor
+            peaks = measure_peaks(rb, (r.M * rb, r.N * rb))
         s = bp.Sampler(r, 100, prec=prec, seed=seed)
         s.run_sweeps(1, 2)
         split = None
@@ -209,7 +323,8 @@ def k100_compare(steps, seed, autotune=True):
                      "ratings_per_s": round(2 * r.nnz / ms * 1e3, 1),
                      "rmse_avg": round(float(avg[-1]), 5), "rmse_last": round(float(last[-1]), 5),
                      "row_kernel_ms": {"rows_V": round(kv, 3), "rows_U": round(ku, 3)},
-                     "split_threshold": split}
+                     "split_threshold": split,
+                     "sweep_roofline": sweep_roofline(100, prec, r, ms, peaks)}
         log("K=100 %s: %s" % (prec, out[prec]))
     out["bf16_speedup"] = round(out["fp32"]["ms_per_step"] / out["bf16"]["ms_per_step"], 3)
     out["rmse_avg_rel_diff"] = round(out["bf16"]["rmse_avg"] / out["fp32"]["rmse_avg"] - 1.0, 6)
@@ -229,10 +344,15 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=5)
     ap.add_argument("--foldin-rate", type=float, default=5000.0)
     ap.add_argument("--foldin-seconds", type=float, default=3.0)
+    ap.add_argument("--foldin-warmup-seconds", type=float, default=0.0)
+    ap.add_argument("--foldin-sweep", default="1000,2500,10000,20000,40000,80000",
+                    help="offered loads (req/s) of the 1-s load sweep, comma separated; empty: none")
     ap.add_argument("--no-foldin", action="store_true")
     ap.add_argument("--k100-steps", type=int, default=50,
                     help="sweeps of the K = 100 comparison (100M-rating shape, FP32 vs BF16-Gram)")
     ap.add_argument("--no-k100", action="store_true")
+    ap.add_argument("--no-peaks", action="store_true",
+                    help="skip the micro-benchmarks of the measured peaks")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the library's default split threshold and kernel family")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -263,6 +383,13 @@ def main():
     r = gen()
     log("generated %s: M=%d N=%d nnz=%d test=%d in %.1fs" % (r.name, r.M, r.N, r.nnz,
                                                              len(r.test_row), time.perf_counter() - t))
+    esize = 8 if prec == "fp64" else (2 if prec == "bf16" else 4)
+    ld = K if prec == "fp64" else (K + 3) // 4 * 4
+    peaks = None
+    if not args.no_peaks:
+        t = time.perf_counter()
+        peaks = measure_peaks(ld * esize, (r.M * ld * esize, r.N * ld * esize))
+        log("measured peaks (%.1fs): %s" % (time.perf_counter() - t, peaks))
     t = time.perf_counter()
     s = bp.Sampler(r, K, prec=prec, seed=args.seed)
     log("created context in %.1fs" % (time.perf_counter() - t))
@@ -300,7 +427,6 @@ def main():
     # the kernel's stream, one pair per replay)
     k_ms = dict(zip(["rows_V", "rows_U"], s.row_kernel_ms()))
     log("row kernel per launch (ms, timed sweeps): %s" % {k: round(v, 4) for k, v in k_ms.items()})
-    esize = 8 if prec == "fp64" else (2 if prec == "bf16" else 4)
     _, ns_u = s.get_plan(bp.SIDE_U)
     _, ns_v = s.get_plan(bp.SIDE_V)
     cand = {
@@ -325,6 +451,24 @@ def main():
         roof = {"bound": "mfma", "achieved": round(flops / sec / 1e12, 3), "peak": round(peak, 1),
                 "unit": "TFLOP/s"}
     roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
+    if peaks:
+        # the same bound against the rates measured on this GPU
+        if roof["bound"] == "hbm":
+            src = (r.M if dom == "rows_V" else r.N) * ld * esize
+            gathered = ld * esize * r.nnz
+            t_meas = ((byts - gathered) / (peaks["hbm_triad_gbs"] * 1e9)
+                      + gathered / (peaks["gather_gbs"][str(int(src))] * 1e9))
+            roof["peak_measured"] = round(byts / t_meas / 1e9, 1)
+        else:
+            p32 = peaks["fp32_mfma_tflops"]
+            pm = p32
+            if prec == "bf16":
+                pm = flops / (gram / peaks["bf16_mfma_tflops"]
+                              + fact / max(p32, peaks["fp32_valu_tflops"]))
+            elif prec == "fp64":
+                pm = peaks["fp64_mfma_tflops"]
+            roof["peak_measured"] = round(pm, 2)
+        roof["frac_measured"] = round(roof["achieved"] / roof["peak_measured"], 4)
     roof["traffic"] = profiled_traffic(r.name, K, prec, dom[-1])
     roof["kernel"] = "row update, side %s (mean of %d launches in the timed sweeps, %.4f ms)" % (
         dom[-1], steps, k_ms[dom])
@@ -352,6 +496,8 @@ def main():
         "row_kernel_ms": {k: round(v, 4) for k, v in k_ms.items()},
         "autotune": tuned,
         "roofline": roof,
+        "sweep_roofline": sweep_roofline(K, prec, r, ms_per_step, peaks),
+        "peaks_measured": peaks,
     }
     if not args.no_foldin and prec == "fp32" and K <= 64:
         # 16 posterior samples from the running chain, then open-loop serving
@@ -360,11 +506,12 @@ def main():
             s.run_sweeps(t, 1)
             t += 1
             s.store_sample()
-        out["foldin"] = foldin_bench(s, r, args.foldin_rate, args.foldin_seconds, args.seed)
+        out["foldin"] = foldin_bench(s, r, args.foldin_rate, args.foldin_seconds, args.seed,
+                                     warm_seconds=args.foldin_warmup_seconds)
         log("fold-in: %s" % out["foldin"])
         # offered-load sweep (1 s each) to locate the knee
         knee = []
-        for rate in (1000.0, 2500.0, 10000.0, 20000.0):
+        for rate in [float(x) for x in args.foldin_sweep.split(",") if x.strip()]:
             f = foldin_bench(s, r, rate, 1.0, args.seed + int(rate))
             knee.append({k: f[k] for k in ("offered_req_per_s", "completed_req_per_s", "p50_ms",
                                            "p99_ms")})
@@ -372,7 +519,7 @@ def main():
         log("fold-in load sweep: %s" % knee)
     s.close()
     if not args.no_k100 and args.workload == "movielens":
-        out["k100"] = k100_compare(args.k100_steps, args.seed, not args.no_autotune)
+        out["k100"] = k100_compare(args.k100_steps, args.seed, not args.no_autotune, not args.no_peaks)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(r, K, args.cpu_seconds, args.seed)
         log("cpu baseline: %s" % out["cpu_baseline"])

@@ -36,7 +36,11 @@ EXPORTS = [
     "bpmf_last_time_ms", "bpmf_row_kernel_ms", "bpmf_autotune", "bpmf_last_error", "bpmf_destroy", "bpmf_store_sample",
     "bpmf_foldin_submit", "bpmf_foldin_poll", "bpmf_foldin_drain", "bpmf_foldin_samples",
     "bpmf_foldin_capacity",
+    # include/bpmf_peaks.h
+    "bpmf_peak_triad", "bpmf_peak_compute", "bpmf_peak_gather",
 ]
+
+PEAK_FP32_VALU, PEAK_FP32_MFMA, PEAK_BF16_MFMA, PEAK_FP64_MFMA = 0, 1, 2, 3
 
 
 class BPMFError(RuntimeError):
@@ -90,7 +94,7 @@ def lib() -> ctypes.CDLL:
         L.bpmf_get_hyper.argtypes = [P, i32, P, P]
         L.bpmf_set_hyper.argtypes = [P, i32, P, P]
         L.bpmf_get_csc.argtypes = [P, P, P, P]
-        L.bpmf_get_plan.argtypes = [P, i32, P, P]
+        L.bpmf_get_plan.argtypes = [P, i32, P, P, P]
         L.bpmf_mean_rating.argtypes = [P]
         L.bpmf_mean_rating.restype = dbl
         L.bpmf_synchronize.argtypes = [P]
@@ -108,8 +112,39 @@ def lib() -> ctypes.CDLL:
         L.bpmf_foldin_samples.argtypes = [P]
         L.bpmf_foldin_capacity.argtypes = [P]
         L.bpmf_foldin_capacity.restype = i64
+        L.bpmf_peak_triad.argtypes = [i64, i32, P]
+        L.bpmf_peak_compute.argtypes = [i32, i32, P]
+        L.bpmf_peak_gather.argtypes = [i64, i32, i64, i32, P]
         _lib = L
     return _lib
+
+
+def _peak_check(rc, what):
+    if rc != OK:
+        raise RuntimeError("%s failed with status %d" % (what, rc))
+
+
+def peak_triad(bytes_per_array=1 << 30, reps=10):
+    """HBM rate of a stream triad over three arrays on the current GPU, GB/s."""
+    v = ctypes.c_double()
+    _peak_check(lib().bpmf_peak_triad(int(bytes_per_array), int(reps), ctypes.byref(v)), "bpmf_peak_triad")
+    return v.value
+
+
+def peak_compute(kind, reps=5):
+    """Dense rate of one instruction kind (PEAK_*) on the current GPU, TFLOP/s."""
+    v = ctypes.c_double()
+    _peak_check(lib().bpmf_peak_compute(int(kind), int(reps), ctypes.byref(v)), "bpmf_peak_compute")
+    return v.value
+
+
+def peak_gather(src_bytes, row_bytes, n_rows=1 << 23, reps=5):
+    """Rate of random whole-row gathers of `row_bytes` from a `src_bytes`
+    source on the current GPU, GB/s."""
+    v = ctypes.c_double()
+    _peak_check(lib().bpmf_peak_gather(int(src_bytes), int(row_bytes), int(n_rows), int(reps),
+                                       ctypes.byref(v)), "bpmf_peak_gather")
+    return v.value
 
 
 def _ptr(a):

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "libbpmf.so")
 SOURCES = ["runtime.cpp", "row_generic.hip", "row_fast.hip", "hyper.hip", "misc.hip", "foldin.hip",
-           "foldin.cpp", "row_big.hip", "row_lowrank.hip"]
+           "foldin.cpp", "row_big.hip", "row_lowrank.hip", "peaks.hip"]
 ARCH = os.environ.get("BPMF_OFFLOAD_ARCH", "gfx950")
 
 COMMON = [

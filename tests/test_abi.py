@@ -1,6 +1,7 @@
 """CPU checks of the C ABI: the library builds for gfx950, loads, and exports
-every function include/bpmf.h declares (no compute calls: no GPU here)."""
+every function the headers under include/ declare (no compute calls: no GPU here)."""
 import ctypes
+import glob
 import os
 import re
 
@@ -10,9 +11,11 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _declared():
-    src = open(os.path.join(ROOT, "include", "bpmf.h")).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(bpmf_[a-z0-9_]+)\s*\(", src)))
+    names = set()
+    for h in sorted(glob.glob(os.path.join(ROOT, "include", "*.h"))):
+        src = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names.update(re.findall(r"\b(bpmf_[a-z0-9_]+)\s*\(", src))
+    return sorted(names)
 
 
 @pytest.fixture(scope="module")
@@ -68,3 +71,21 @@ def test_default_params_and_error_paths(libpath):
     rc = L.bpmf_create(2, 3, ptr.ctypes.data, col.ctypes.data, val.ctypes.data, None, None, None,
                        1, None, None, None, 0, ctypes.byref(p), ctypes.byref(ctx))
     assert rc == bp.E_INVAL
+
+
+def test_peak_argument_checks(libpath):
+    """The measurement calls reject bad sizes on the host, before any GPU work."""
+    import paper_1705_04159_amd as bp
+
+    L = bp.lib()
+    v = ctypes.c_double()
+    assert L.bpmf_peak_triad(1000, 1, ctypes.byref(v)) == bp.E_INVAL  # under 1 MiB
+    assert L.bpmf_peak_triad((1 << 20) + 8, 1, ctypes.byref(v)) == bp.E_INVAL  # not a multiple of 16
+    assert L.bpmf_peak_triad(1 << 20, 0, ctypes.byref(v)) == bp.E_INVAL
+    assert L.bpmf_peak_compute(4, 1, ctypes.byref(v)) == bp.E_INVAL
+    assert L.bpmf_peak_compute(-1, 1, ctypes.byref(v)) == bp.E_INVAL
+    assert L.bpmf_peak_gather(1 << 20, 24, 10, 1, ctypes.byref(v)) == bp.E_INVAL  # row not 16-B multiple
+    assert L.bpmf_peak_gather(1 << 20, 2048, 10, 1, ctypes.byref(v)) == bp.E_INVAL  # row over 1 KiB
+    assert L.bpmf_peak_gather(64, 128, 10, 1, ctypes.byref(v)) == bp.E_INVAL  # source under one row
+    assert L.bpmf_peak_gather(1 << 20, 128, 0, 1, ctypes.byref(v)) == bp.E_INVAL
+    assert L.bpmf_peak_gather(1 << 20, 128, 10, 1, None) == bp.E_INVAL
