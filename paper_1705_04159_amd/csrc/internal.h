@@ -51,6 +51,8 @@ struct Side {
     double *Lam = nullptr;   // device [K * K]
     void *Lam_w = nullptr;   // device [K * K] Lambda in working precision
     void *Lmu_w = nullptr;   // device [K]     Lambda mu in working precision
+    float *Lam_img = nullptr; // device [nb (nb + 1) / 2 * 256], nb = ceil(K / 16): Lambda in
+                              // the blocked kernel's accumulator layout (K <= 128)
     RowItem *items = nullptr;
     int64_t n_items = 0;
     FinishItem *fin = nullptr;

@@ -133,7 +133,7 @@ __device__ __forceinline__ void gram_item_bf16(const RowItem &it, const int32_t 
 template <int NB>
 __device__ __forceinline__ void blocked_chol_sample(floatx4 (&acc)[NB * (NB + 1) / 2], float *lds,
                                                     int K, float alpha,
-                                                    const float *__restrict__ Lam, uint32_t row,
+                                                    const floatx4 *__restrict__ img, uint32_t row,
                                                     uint32_t t, uint64_t seed, uint32_t stream,
                                                     float *__restrict__ xrow)
 {
@@ -148,31 +148,28 @@ __device__ __forceinline__ void blocked_chol_sample(floatx4 (&acc)[NB * (NB + 1)
     const int col = lane & 15;
     const int kq = lane >> 4;
 
-    // The accumulators hold the negated trailing matrix T = -(alpha G -
-    // sum_k L_ik L_jk^T), so that the trailing updates T_ij += L_ik L_jk^T
-    // take the panel as both MFMA operands.  The prior of block column kb is
-    // added when kb is reached (the updates commute with the addition), one
-    // block column of loads at a time.
+    // The accumulators hold the negated trailing matrix T = -(Lambda +
+    // alpha G - sum_k L_ik L_jk^T), so that the trailing updates
+    // T_ij += L_ik L_jk^T take the panel as both MFMA operands.  The prior
+    // comes from its image in the accumulator layout (identity on the
+    // padding), one float4 per block and lane.
 #pragma unroll
-    for (int q = 0; q < NB * (NB + 1) / 2; ++q)
+    for (int q = 0; q < NB * (NB + 1) / 2; ++q) {
+        const floatx4 p = img[q * 64 + lane];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) acc[q][v] *= -alpha;
+        for (int v = 0; v < 4; ++v) acc[q][v] = -alpha * acc[q][v] - p[v];
+    }
 
     static_for<0, NB>([&](auto kbc) {
         constexpr int kb = decltype(kbc)::value;
         constexpr int R = 16 * (NB - 1 - kb);  // panel rows below the diagonal block
-        // (1) prior of block column kb (identity on the padding), then the
-        // block column to LDS: pan row 16 (i - kb) + r holds row r of block i
+        // (1) block column kb to LDS: pan row 16 (i - kb) + r holds row r of block i
         __builtin_amdgcn_sched_barrier(0);
         static_for<kb, NB>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
             constexpr int q = i * (i + 1) / 2 + kb;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int r = 16 * i + 4 * kq + v, c = 16 * kb + col;
-                const float prior = (r < K && c < K) ? Lam[r * K + c] : (r == c ? 1.f : 0.f);
-                pan[((i - kb) * 16 + 4 * kq + v) * kPS + col] = prior - acc[q][v];
-            }
+            for (int v = 0; v < 4; ++v) pan[((i - kb) * 16 + 4 * kq + v) * kPS + col] = -acc[q][v];
         });
         wave_sync();
         // (2) diagonal block column-per-lane (lane col holds column col; the
@@ -188,12 +185,13 @@ __device__ __forceinline__ void blocked_chol_sample(floatx4 (&acc)[NB * (NB + 1)
                 constexpr int k = decltype(kc)::value;
                 const float dk = bcast16<k>(d[k]);
                 if (col == k) mydiag = dk;
-                const float f = col > k ? d[k] * __builtin_amdgcn_rcpf(dk) : 0.f;
+                // negated multiplier: each update is one v_fmac with a DPP operand
+                const float nf = col > k ? -d[k] * __builtin_amdgcn_rcpf(dk) : 0.f;
                 static_for<k + 1, 16>([&](auto rc) {
                     constexpr int r = decltype(rc)::value;
-                    d[r] -= f * bcast16<k>(d[r]);
+                    d[r] = __builtin_fmaf(bcast16<k>(d[r]), nf, d[r]);
                 });
-                db -= f * bcast16<k>(db);
+                db = __builtin_fmaf(bcast16<k>(db), nf, db);
             });
             const float inv_s = __builtin_amdgcn_rsqf(mydiag);
             if (kq == 0) {
@@ -360,7 +358,7 @@ template <int NB, bool BF16, bool SEG>
 __global__ __launch_bounds__(64 * kBigWPB, big_waves<NB>()) void row_big(
     int K, float alpha, const RowItem *__restrict__ items, int64_t item0, int64_t n_items,
     const int32_t *__restrict__ nbr, const float *__restrict__ rc, const void *__restrict__ Y,
-    int ldy, uint32_t y_bytes, const float *__restrict__ Lam, const float *__restrict__ Lmu,
+    int ldy, uint32_t y_bytes, const floatx4 *__restrict__ img, const float *__restrict__ Lmu,
     float *__restrict__ X, int ldx, float *__restrict__ part, uint64_t seed, uint32_t stream,
     const uint32_t *__restrict__ ctr)
 {
@@ -405,7 +403,7 @@ __global__ __launch_bounds__(64 * kBigWPB, big_waves<NB>()) void row_big(
                 bv[c] = c < K ? alpha * bacc[bi] + Lmu[c] : 0.f;
             }
         wave_sync();
-        blocked_chol_sample<NB>(acc, lds, K, alpha, Lam, (uint32_t)it.row, ctr[0], seed, stream,
+        blocked_chol_sample<NB>(acc, lds, K, alpha, img, (uint32_t)it.row, ctr[0], seed, stream,
                                 X + (size_t)it.row * ldx);
     }
 }
@@ -415,7 +413,7 @@ __global__ __launch_bounds__(64 * kBigWPB, big_waves<NB>()) void row_big(
 template <int NB>
 __global__ __launch_bounds__(64 * kBigWPB, big_waves<NB>()) void row_finish_big(
     int K, float alpha, const FinishItem *__restrict__ fin, int64_t n_fin,
-    const float *__restrict__ part, const float *__restrict__ Lam, const float *__restrict__ Lmu,
+    const float *__restrict__ part, const floatx4 *__restrict__ img, const float *__restrict__ Lmu,
     float *__restrict__ X, int ldx, uint64_t seed, uint32_t stream,
     const uint32_t *__restrict__ ctr)
 {
@@ -440,26 +438,46 @@ __global__ __launch_bounds__(64 * kBigWPB, big_waves<NB>()) void row_finish_big(
         if (c < 16 * NB) bv[c] = c < K ? alpha * src[NBLK * 256 + c] + Lmu[c] : 0.f;
     }
     wave_sync();
-    blocked_chol_sample<NB>(acc, lds, K, alpha, Lam, (uint32_t)f.row, ctr[0], seed, stream,
+    blocked_chol_sample<NB>(acc, lds, K, alpha, img, (uint32_t)f.row, ctr[0], seed, stream,
                             X + (size_t)f.row * ldx);
+}
+
+// The prior Lambda (identity on the padding) in the accumulator layout:
+// block q = i (i + 1) / 2 + j (i >= j), lane l, value v holds
+// Lambda[16 i + 4 (l / 16) + v][16 j + l % 16].
+template <int NB>
+__global__ __launch_bounds__(256) void prior_image(int K, const float *__restrict__ Lam, float *__restrict__ img)
+{
+    const int e = blockIdx.x * 256 + threadIdx.x;  // ((q * 64) + l) * 4 + v
+    if (e >= NB * (NB + 1) / 2 * 256) return;
+    const int v = e & 3, l = (e >> 2) & 63, q = e >> 8;
+    int i = 0;
+    while ((i + 1) * (i + 2) / 2 <= q) ++i;
+    const int j = q - i * (i + 1) / 2;
+    const int r = 16 * i + 4 * (l >> 4) + v, cc = 16 * j + (l & 15);
+    img[e] = (r < K && cc < K) ? Lam[r * K + cc] : (r == cc ? 1.f : 0.f);
 }
 
 template <int NB>
 hipError_t launch_big(bpmf_ctx *c, Side &sd, Side &ot, hipStream_t s, int stage)
 {
     const size_t lds = sizeof(float) * kBigWPB * BigLds<NB>::TOTAL;
+    const floatx4 *img = (const floatx4 *)sd.Lam_img;
     if (stage == 1) {
         if (sd.n_fin == 0) return hipSuccess;
         hipError_t e = launch_part_reduce(c, sd, s, big_slot_elems<NB>());
         if (e != hipSuccess) return e;
         const unsigned grid = (unsigned)((sd.n_fin + kBigWPB - 1) / kBigWPB);
         hipLaunchKernelGGL((row_finish_big<NB>), dim3(grid), dim3(64 * kBigWPB), lds, s, c->K,
-                           (float)c->alpha, sd.fin, sd.n_fin, (const float *)c->part,
-                           (const float *)sd.Lam_w, (const float *)sd.Lmu_w, (float *)sd.X, c->ld,
-                           c->seed, sd.stream_row, c->ctr);
+                           (float)c->alpha, sd.fin, sd.n_fin, (const float *)c->part, img,
+                           (const float *)sd.Lmu_w, (float *)sd.X, c->ld, c->seed, sd.stream_row,
+                           c->ctr);
         return hipGetLastError();
     }
-    // segments of split rows (items [0, n_slots)), then whole rows
+    // the prior image of this sweep, segments of split rows (items
+    // [0, n_slots)), then whole rows
+    hipLaunchKernelGGL((prior_image<NB>), dim3((NB * (NB + 1) / 2 * 256 + 255) / 256), dim3(256), 0, s, c->K,
+                       (const float *)sd.Lam_w, sd.Lam_img);
     const int64_t n_seg = sd.n_slots, n_rows = sd.n_items - sd.n_slots - sd.n_low;
     const bool bf = c->prec == 2;
     const void *ysrc = bf ? (const void *)ot.Xbf : (const void *)ot.X;
@@ -469,7 +487,7 @@ hipError_t launch_big(bpmf_ctx *c, Side &sd, Side &ot, hipStream_t s, int stage)
         const unsigned grid = (unsigned)((count + kBigWPB - 1) / kBigWPB);
         hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * kBigWPB), lds_bytes, s, c->K,
                            (float)c->alpha, sd.items, item0, item0 + count, sd.nbr,
-                           (const float *)sd.rc, ysrc, c->ld, y_bytes, (const float *)sd.Lam_w,
+                           (const float *)sd.rc, ysrc, c->ld, y_bytes, img,
                            (const float *)sd.Lmu_w, (float *)sd.X, c->ld, (float *)c->part,
                            c->seed, sd.stream_row, c->ctr);
     };
