@@ -53,6 +53,8 @@ struct Side {
     void *Lmu_w = nullptr;   // device [K]     Lambda mu in working precision
     float *Lam_img = nullptr; // device [nb (nb + 1) / 2 * 256], nb = ceil(K / 16): Lambda in
                               // the blocked kernel's accumulator layout (K <= 128)
+    float *Lam_pk = nullptr;  // device [KP (KP + 1) / 2], KP = 16 ceil(K / 16): Lambda packed
+                              // lower-triangular for the K <= 64 matrix-core kernel
     RowItem *items = nullptr;
     int64_t n_items = 0;
     FinishItem *fin = nullptr;

@@ -98,11 +98,25 @@ __device__ __forceinline__ float chol_sample_column(float (&v)[KP + 1], int K, i
     return myx;
 }
 
+// Lambda packed like the kernel's LDS copy of P: entry r (r + 1) / 2 + c,
+// c <= r < KP, is Lambda[r][c] inside the leading K x K block, else 0.
+__global__ __launch_bounds__(256) void prior_packed(int K, int KP, const float *__restrict__ Lam,
+                                                    float *__restrict__ LamPk)
+{
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= KP * (KP + 1) / 2) return;
+    int r = (int)((sqrtf(8.f * (float)e + 1.f) - 1.f) * 0.5f);
+    while ((r + 1) * (r + 2) / 2 <= e) ++r;
+    while (r * (r + 1) / 2 > e) --r;
+    const int cc = e - r * (r + 1) / 2;
+    LamPk[e] = (r < K && cc < K) ? Lam[r * K + cc] : 0.f;
+}
+
 template <int NB, int RPW, int WPB>
 __global__ __launch_bounds__(64 * WPB) void row_fast_f32(
     int K, float alpha, const RowItem *__restrict__ items, int64_t n_items,
     const int32_t *__restrict__ nbr, const float *__restrict__ rc, const float *__restrict__ Y,
-    int ldy, uint32_t y_bytes, const float *__restrict__ Lam, const float *__restrict__ Lmu,
+    int ldy, uint32_t y_bytes, const float *__restrict__ LamPk, const float *__restrict__ Lmu,
     float *__restrict__ X, int ldx, float *__restrict__ part, uint64_t seed, uint32_t stream,
     const uint32_t *__restrict__ ctr)
 {
@@ -124,6 +138,23 @@ __global__ __launch_bounds__(64 * WPB) void row_fast_f32(
 #pragma unroll
     for (int bi = 0; bi < NB; ++bi) lane_off[bi] = 16 * bi + col < K ? (16 * bi + col) * 4u : kOOB;
     const int KK2 = K * (K + 1) / 2;
+
+    // The prior Lambda, packed like P (LamPk), into each row region of this
+    // wave by direct global-to-LDS loads (no registers; they complete while
+    // the gather runs): the Gram is later added onto it.
+    {
+        constexpr int NE = KP * (KP + 1) / 2;
+        static_for<0, (NE + 63) / 64>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            if (64 * i + lane < NE) {
+#pragma unroll
+                for (int h = 0; h < RPW; ++h)
+                    __builtin_amdgcn_global_load_lds(
+                        (const void __attribute__((address_space(1))) *)(LamPk + 64 * i + lane),
+                        (void __attribute__((address_space(3))) *)(Ps + h * REGION + 64 * i), 4, 0, 0);
+            }
+        });
+    }
 
     int row_of[RPW];
     static_for<0, RPW>([&](auto hc) {
@@ -173,7 +204,7 @@ __global__ __launch_bounds__(64 * WPB) void row_fast_f32(
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int r = 16 * bi + 4 * kq + v, c = 16 * bj + col;
-                    if (c <= r) P[pk(r, c)] = acc[q][v];
+                    if (c <= r) P[pk(r, c)] = alpha * acc[q][v] + P[pk(r, c)];  // Lambda + alpha G
                 }
                 ++q;
             }
@@ -198,9 +229,7 @@ __global__ __launch_bounds__(64 * WPB) void row_fast_f32(
     const int cc = c < KP ? c : 0;
     float v[KP + 1];
 #pragma unroll
-    for (int r = 0; r < KP; ++r)
-        v[r] = (live && r < K) ? alpha * P[r >= cc ? pk(r, cc) : pk(cc, r)] + Lam[r * K + c]
-                               : (r == c ? 1.f : 0.f);
+    for (int r = 0; r < KP; ++r) v[r] = (live && r < K) ? P[r >= cc ? pk(r, cc) : pk(cc, r)] : (r == c ? 1.f : 0.f);
     v[KP] = live ? alpha * P[KP * (KP + 1) / 2 + cc] + Lmu[c] : 0.f;
     const float x = chol_sample_column<KP, RPW>(v, K, c, (uint32_t)my_row, ctr[0], 0u, seed, stream);
     if (live) X[(size_t)my_row * ldx + c] = x;
@@ -371,9 +400,11 @@ hipError_t launch_f32(bpmf_ctx *c, Side &sd, Side &ot, hipStream_t s)
     const unsigned grid = (unsigned)((n_items + per_block - 1) / per_block);
     const uint32_t y_bytes = (uint32_t)(ot.rows * c->ld * sizeof(float));
     if (n_items == 0) return hipSuccess;
+    hipLaunchKernelGGL(prior_packed, dim3((KP * (KP + 1) / 2 + 255) / 256), dim3(256), 0, s, c->K, KP,
+                       (const float *)sd.Lam_w, sd.Lam_pk);
     hipLaunchKernelGGL((row_fast_f32<NB, RPW, WPB>), dim3(grid), dim3(64 * WPB), lds, s, c->K,
                        (float)c->alpha, sd.items, n_items, sd.nbr, (const float *)sd.rc,
-                       (const float *)ot.X, c->ld, y_bytes, (const float *)sd.Lam_w,
+                       (const float *)ot.X, c->ld, y_bytes, (const float *)sd.Lam_pk,
                        (const float *)sd.Lmu_w, (float *)sd.X, c->ld, (float *)c->part, c->seed,
                        sd.stream_row, c->ctr);
     return hipGetLastError();

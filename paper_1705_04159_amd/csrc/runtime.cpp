@@ -248,8 +248,8 @@ hipError_t enqueue_sweep(bpmf_ctx *c, hipStream_t s)
 
 void free_side(Side &s)
 {
-    void *ps[] = {s.ptr, s.nbr, s.rc, s.X, s.Xbf, s.mu, s.Lam, s.Lam_w, s.Lmu_w, s.Lam_img, s.items,
-                  s.fin, s.Linv_w, s.Ltmu_w, s.Yt};
+    void *ps[] = {s.ptr, s.nbr, s.rc, s.X, s.Xbf, s.mu, s.Lam, s.Lam_w, s.Lmu_w, s.Lam_img, s.Lam_pk,
+                  s.items, s.fin, s.Linv_w, s.Ltmu_w, s.Yt};
     for (void *p : ps) (void)hipFree(p);
 }
 
@@ -423,6 +423,8 @@ int bpmf_create(int64_t M, int64_t N, const int64_t *csr_ptr, const int32_t *csr
             if (K <= 128) {
                 const size_t nb = (K + 15) / 16;
                 CK(hipMalloc(&sd.Lam_img, sizeof(float) * nb * (nb + 1) / 2 * 256));
+                const size_t kp = 16 * nb;
+                if (K <= 64) CK(hipMalloc(&sd.Lam_pk, sizeof(float) * kp * (kp + 1) / 2));
             }
             CK(hipMemcpy(sd.ptr, ptrs[sid]->data(), sizeof(int64_t) * (sd.rows + 1),
                          hipMemcpyHostToDevice));
