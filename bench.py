@@ -138,6 +138,80 @@ def sweep_roofline(K, prec, r, ms_per_step, peaks):
     return res
 
 
+FIG2_DEGREES = (1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096, 8192)
+# kernel family: (split threshold, fast_kmax, rank-one cut-off, applies to degree d)
+FIG2_VARIANTS = {
+    "rank-one (VALU)": (1 << 24, 32, 8, lambda d: d <= 8),
+    "MFMA, column-per-lane factorisation": (1 << 24, 32, 0, lambda d: True),
+    "MFMA, blocked factorisation": (1 << 24, 0, 0, lambda d: True),
+    "split into segments of 128": (128, 32, 0, lambda d: d > 128),
+}
+
+
+def uniform_degree(d, N, n_rows, seed):
+    """n_rows users with exactly d distinct ratings each over N movies
+    (start + 7919 j mod N: distinct for d <= N, as 7919 is prime to N)."""
+    import types
+
+    rng = np.random.default_rng(seed)
+    start = rng.integers(0, N, n_rows)
+    cols = (start[:, None] + 7919 * np.arange(d, dtype=np.int64)[None, :]) % N
+    cols.sort(axis=1)
+    n_test = 1000
+    return types.SimpleNamespace(
+        name="uniform-degree-%d" % d, M=n_rows, N=N, nnz=n_rows * d,
+        csr_ptr=np.arange(n_rows + 1, dtype=np.int64) * d, csr_col=cols.ravel().astype(np.int32),
+        csr_val=(3.5 + rng.standard_normal(n_rows * d)).astype(np.float32),
+        test_row=rng.integers(0, n_rows, n_test).astype(np.int32),
+        test_col=rng.integers(0, N, n_test).astype(np.int32),
+        test_val=np.full(n_test, 3.5, np.float32))
+
+
+def fit_fixed_plus_per_rating(d, t):
+    """Least-squares fit of t = a + b d in relative error (each point weighted
+    by 1 / t), the paper's per-item cost model (a fixed cost plus a cost per
+    rating).  Returns (a, b)."""
+    d, t = np.asarray(d, np.float64), np.asarray(t, np.float64)
+    A = np.stack([1.0 / t, d / t], axis=1)
+    (a, b), *_ = np.linalg.lstsq(A, np.ones_like(t), rcond=None)
+    return float(a), float(b)
+
+
+def fig2_per_degree(K, N, seed, max_ratings=16_000_000):
+    """Per-row cost of each kernel family against the row's degree (users of
+    one degree each, the gathered factor V of the 20M shape's size), from the
+    eager U-side phases (row kernel + split finishing) of three sweeps; then
+    the fixed + per-rating fit of each family."""
+    import paper_1705_04159_amd as bp
+
+    res = {"K": K, "N": N, "degrees": list(FIG2_DEGREES), "rows": [], "ns_per_row": {}, "fit": {}}
+    for v in FIG2_VARIANTS:
+        res["ns_per_row"][v] = []
+    for d in FIG2_DEGREES:
+        n_rows = max(8192, min(262144, max_ratings // d))
+        r = uniform_degree(d, N, n_rows, seed + d)
+        s = bp.Sampler(r, K, prec="fp32", seed=seed)
+        t = 1
+        res["rows"].append(n_rows)
+        for v, (split, kmax, low, applies) in FIG2_VARIANTS.items():
+            if not applies(d):
+                res["ns_per_row"][v].append(None)
+                continue
+            s.set_plan(split, kmax, low)
+            s.run_sweeps(t, 2)
+            ph = s.profile_sweeps(t + 2, 3)
+            t += 5
+            ms = float(ph[4] + ph[5])  # rows_U + split_U
+            res["ns_per_row"][v].append(round(1e6 * ms / n_rows, 2))
+        s.close()
+        log("fig2 d=%d rows=%d: %s" % (d, n_rows, {v: res["ns_per_row"][v][-1] for v in FIG2_VARIANTS}))
+    for v in FIG2_VARIANTS:
+        pts = [(d, x) for d, x in zip(FIG2_DEGREES, res["ns_per_row"][v]) if x is not None]
+        a, b = fit_fixed_plus_per_rating([p[0] for p in pts], [p[1] for p in pts])
+        res["fit"][v] = {"fixed_ns": round(a, 2), "per_rating_ns": round(b, 4)}
+    return res
+
+
 def profiled_traffic(workload, K, prec, side):
     """HBM bytes per launch of the row kernel from the committed rocprofv3
     counter summaries (FETCH_SIZE and WRITE_SIZE, each scaled by the same
@@ -351,6 +425,9 @@ def main():
     ap.add_argument("--k100-steps", type=int, default=50,
                     help="sweeps of the K = 100 comparison (100M-rating shape, FP32 vs BF16-Gram)")
     ap.add_argument("--no-k100", action="store_true")
+    ap.add_argument("--fig2", action="store_true",
+                    help="only time each kernel family per row against the row's degree (K = 32, "
+                         "N = 26,744) and fit the fixed + per-rating cost model; one JSON line")
     ap.add_argument("--no-peaks", action="store_true",
                     help="skip the micro-benchmarks of the measured peaks")
     ap.add_argument("--no-autotune", action="store_true",
@@ -374,6 +451,9 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if args.fig2:
+        print(json.dumps({"fig2": fig2_per_degree(32, 26744, args.seed)}), flush=True)
+        return
 
     import paper_1705_04159_amd as bp
 

@@ -199,6 +199,21 @@ int bpmf_autotune(bpmf_ctx *c, uint32_t n_sweeps, int32_t *chosen_split, int32_t
                   int32_t *chosen_low, int32_t *n_tried, int32_t *tried_split, int32_t *tried_kmax,
                   int32_t *tried_low, double *tried_ms);
 
+/* Sets the plan the autotuner would choose, by hand: split_threshold
+ * (1..2^24; rows with more ratings are cut into segments of
+ * max(128, split_threshold / 2)), fast_kmax (0..64; FP32 factors with
+ * K <= fast_kmax take the column-per-lane kernel, larger K the blocked one)
+ * and lowrank_dmax (0, 4 or 8; with FP32 factors and K <= 64 every row with
+ * at most that many ratings takes the rank-one update path -- unlike the
+ * autotuner, without weighing the transform of the gathered factor).  The
+ * work items, finishing items and partial-sum workspace are rebuilt and the
+ * sweep graph is re-captured on the next bpmf_run_sweeps; the chain state is
+ * untouched and the samples do not depend on the plan beyond rounding.  Used
+ * to time each kernel family per degree (the per-item cost against degree
+ * of Sec. III, Fig. 2).  BPMF_E_INVAL for a value out of range or the
+ * rank-one path where it does not apply. */
+int bpmf_set_plan(bpmf_ctx *c, int32_t split_threshold, int32_t fast_kmax, int32_t lowrank_dmax);
+
 /* Mean device time (ms) of one launch of the row-update kernel (the work
  * items of the row loops of Algorithm 1, split-row finishing excluded) over
  * the sweeps of the most recent bpmf_run_sweeps call: ms[0] for the V side,

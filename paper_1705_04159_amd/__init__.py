@@ -33,7 +33,7 @@ EXPORTS = [
     "bpmf_run_sweeps", "bpmf_profile_sweeps", "bpmf_predict", "bpmf_get_factor", "bpmf_set_factor",
     "bpmf_get_factor_f64", "bpmf_set_factor_f64", "bpmf_get_hyper", "bpmf_set_hyper",
     "bpmf_get_csc", "bpmf_get_plan", "bpmf_mean_rating", "bpmf_synchronize",
-    "bpmf_last_time_ms", "bpmf_row_kernel_ms", "bpmf_autotune", "bpmf_last_error", "bpmf_destroy", "bpmf_store_sample",
+    "bpmf_last_time_ms", "bpmf_row_kernel_ms", "bpmf_autotune", "bpmf_set_plan", "bpmf_last_error", "bpmf_destroy", "bpmf_store_sample",
     "bpmf_foldin_submit", "bpmf_foldin_poll", "bpmf_foldin_drain", "bpmf_foldin_samples",
     "bpmf_foldin_capacity",
     # include/bpmf_peaks.h
@@ -101,6 +101,7 @@ def lib() -> ctypes.CDLL:
         L.bpmf_last_time_ms.argtypes = [P, P]
         L.bpmf_row_kernel_ms.argtypes = [P, P]
         L.bpmf_autotune.argtypes = [P, ctypes.c_uint32, P, P, P, P, P, P, P, P]
+        L.bpmf_set_plan.argtypes = [P, i32, i32, i32]
         L.bpmf_last_error.argtypes = [P]
         L.bpmf_last_error.restype = ctypes.c_char_p
         L.bpmf_destroy.argtypes = [P]
@@ -299,6 +300,12 @@ class Sampler:
         ns = ctypes.c_int64()
         self._check(lib().bpmf_get_plan(self._ctx, side, _ptr(perm), ctypes.byref(ns), None))
         return perm, ns.value
+
+    def set_plan(self, split_threshold, fast_kmax, lowrank_dmax):
+        """Fix the split threshold, kernel family cut-off and rank-one cut-off
+        by hand (what autotune() would choose)."""
+        self._check(lib().bpmf_set_plan(self._ctx, int(split_threshold), int(fast_kmax),
+                                        int(lowrank_dmax)))
 
     def lowrank_rows(self, side):
         """Number of rows of `side` on the rank-one-update path."""

@@ -618,7 +618,7 @@ static int find_timing_nodes(bpmf_ctx *c)
 // Re-plan both sides for a new split threshold / kernel family: work items,
 // finishing items and the partial-sum workspace; the sweep graph is rebuilt
 // on the next bpmf_run_sweeps.
-static int replan(bpmf_ctx *c, int split, int fast_kmax, int low_dmax)
+static int replan(bpmf_ctx *c, int split, int fast_kmax, int low_dmax, bool force_low = false)
 {
     HIPCK(c, hipStreamSynchronize(c->stream));
     c->split_threshold = split;
@@ -632,7 +632,7 @@ static int replan(bpmf_ctx *c, int split, int fast_kmax, int low_dmax)
         plan_side(sd.hptr, sd.rows, split, std::max<int64_t>(128, split / 2), sd.perm, sd.n_split,
                   items, fin, sd.n_slots, low_dmax, n_low);
         const int64_t other = c->side[1 - sid].rows;
-        sd.n_low = low_rows_used(c, n_low, other);
+        sd.n_low = force_low && lowrank_available(c) ? n_low : low_rows_used(c, n_low, other);
         if (sd.n_low) HIPCK(c, alloc_lowrank(c, sd, other));
         (void)hipFree(sd.items);
         (void)hipFree(sd.fin);
@@ -791,6 +791,20 @@ int bpmf_autotune(bpmf_ctx *c, uint32_t n_sweeps, int32_t *chosen_split, int32_t
     if (chosen_low) *chosen_low = best_low;
     if (n_tried) *n_tried = std::min(q, 64);
     return BPMF_OK;
+}
+
+int bpmf_set_plan(bpmf_ctx *c, int32_t split_threshold, int32_t fast_kmax, int32_t lowrank_dmax)
+{
+    STICKY(c);
+    if (split_threshold < 1 || split_threshold > (1 << 24))
+        return fail(c, BPMF_E_INVAL, "split_threshold must be 1..2^24");
+    if (fast_kmax < 0 || fast_kmax > 64) return fail(c, BPMF_E_INVAL, "fast_kmax must be 0..64");
+    if (lowrank_dmax != 0 && lowrank_dmax != 4 && lowrank_dmax != 8)
+        return fail(c, BPMF_E_INVAL, "lowrank_dmax must be 0, 4 or 8");
+    if (lowrank_dmax && !lowrank_available(c))
+        return fail(c, BPMF_E_INVAL, "the rank-one path needs FP32 factors and K <= 64");
+    if (int rc = replan(c, split_threshold, fast_kmax, lowrank_dmax, true)) return rc;
+    return refresh_lowrank(c);
 }
 
 int bpmf_run_sweeps(bpmf_ctx *c, uint32_t t0, uint32_t n, double *rmse_avg, double *rmse_last)

@@ -1,0 +1,54 @@
+"""Host-side pieces of bench.py (no GPU): the algorithmic work per launch,
+the sweep roofline against the spec sheet, the per-degree inputs and the
+fixed + per-rating cost fit."""
+import os
+import sys
+import types
+
+import numpy as np
+
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+import bench  # noqa: E402
+
+
+def test_algorithmic_work_per_launch():
+    # K = 2: per rating K(K+1) + 2K = 10 FLOP, per row K^3/3 + 2K^2 FLOP
+    gram, fact, byts = bench.algorithmic(2, 100, 7, 9, 8, 1 << 30)
+    assert gram == 1000
+    assert abs(fact - 7 * (8 / 3 + 8)) < 1e-12
+    assert byts == 8 * 100 + 8 * 100 + 4 * 2 * 9  # ids+ratings, gathered rows (source > L2), written rows
+    _, _, b_small = bench.algorithmic(2, 100, 7, 9, 8, 1 << 10)  # source fits L2: no gather bytes
+    assert b_small == 8 * 100 + 4 * 2 * 9
+
+
+def test_sweep_roofline_spec_terms():
+    """The 20M shape at K = 32: the V side (gathering a 17.7 MB U) is bound by
+    HBM, the U side by the FP32 matrix cores; the sum is about 0.45 ms."""
+    r = types.SimpleNamespace(M=138493, N=26744, nnz=18000237)
+    res = bench.sweep_roofline(32, "fp32", r, 1.0, None)
+    assert res["sides"]["V"]["bound_spec"] == "hbm" and res["sides"]["U"]["bound_spec"] == "mfma"
+    assert 0.43 < res["t_roof_ms_spec"] < 0.46
+    assert res["frac_spec"] == res["t_roof_ms_spec"]
+    # BF16-Gram at K = 100: V side HBM-bound, U side bound by the FP32 factorisation
+    r = types.SimpleNamespace(M=480189, N=17770, nnz=90432457)
+    res = bench.sweep_roofline(100, "bf16", r, 10.0, None)
+    assert res["sides"]["V"]["bound_spec"] == "hbm" and res["sides"]["U"]["bound_spec"] == "valu"
+
+
+def test_uniform_degree_rows():
+    r = bench.uniform_degree(300, 26744, 50, 3)
+    cols = r.csr_col.reshape(50, 300)
+    assert (np.diff(cols, axis=1) > 0).all()  # sorted, distinct
+    assert cols.min() >= 0 and cols.max() < 26744
+    assert r.nnz == 15000 and r.csr_ptr[-1] == 15000
+
+
+def test_fixed_plus_per_rating_fit():
+    d = np.array([1, 2, 4, 8, 64, 512, 4096], np.float64)
+    a, b = bench.fit_fixed_plus_per_rating(d, 120.0 + 0.35 * d)
+    assert abs(a - 120.0) < 1e-9 and abs(b - 0.35) < 1e-12
+    # noisy data: the relative-error fit keeps the small-degree points
+    rng = np.random.default_rng(0)
+    t = (120.0 + 0.35 * d) * (1 + 0.01 * rng.standard_normal(len(d)))
+    a, b = bench.fit_fixed_plus_per_rating(d, t)
+    assert abs(a / 120.0 - 1) < 0.05 and abs(b / 0.35 - 1) < 0.05

@@ -58,13 +58,15 @@ def _bf16_round(x):
     return u.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
-def single_step(bp, orc, r, K, prec, side, t=7, seed=123, split=0, rows=None):
+def single_step(bp, orc, r, K, prec, side, t=7, seed=123, split=0, rows=None, plan=None):
     """Set identical state on both sides, update one side once, compare."""
-    _say("single_step %s K=%d prec=%s side=%d split=%d M=%d N=%d nnz=%d" % (
-        r.name, K, prec, side, split, r.M, r.N, r.nnz))
+    _say("single_step %s K=%d prec=%s side=%d split=%d plan=%s M=%d N=%d nnz=%d" % (
+        r.name, K, prec, side, split, plan, r.M, r.N, r.nnz))
     rng = np.random.default_rng(seed)
     U, V, mu, Lam = _random_state(rng, r.M, r.N, K)
     s = bp.Sampler(r, K, prec=prec, seed=seed, split_threshold=split)
+    if plan is not None:
+        s.set_plan(*plan)
     s.set_factor(bp.SIDE_U, U)
     s.set_factor(bp.SIDE_V, V)
     s.set_hyper(side, mu, Lam)
@@ -368,6 +370,40 @@ def test_autotune_keeps_the_chain(bp, K):
     assert abs(avg_a[-1] / avg_b[-1] - 1) <= 5e-3
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("K,plan", [(16, (128, 32, 8)), (32, (128, 0, 0)), (32, (1 << 24, 32, 4)),
+                                    (48, (256, 64, 8))])
+def test_set_plan_single_step(bp, orc, K, plan):
+    """A plan fixed by hand (split threshold 128: movies with 129-207
+    ratings in two segments; the blocked kernel at K = 32, the
+    column-per-lane kernel at K = 48, the rank-one path forced for every user
+    with at most 4 or 8 ratings) gives the oracle's draws on both sides."""
+    r = synth.random_small(11, 3000, 150, 24000, 10, empty_rows=20)
+    deg_u, deg_v = np.diff(r.csr_ptr), np.bincount(r.csr_col, minlength=r.N)
+    assert (deg_v > 128).sum() > 50 and (deg_u <= 4).sum() > 100 and (deg_u == 0).any()
+    s = bp.Sampler(r, K, prec="fp32", seed=1)
+    s.set_plan(*plan)
+    if plan[2]:
+        assert s.lowrank_rows(bp.SIDE_U) == int((deg_u <= plan[2]).sum())
+    s.close()
+    for side in (bp.SIDE_U, bp.SIDE_V):
+        err, got, _ = single_step(bp, orc, r, K, "fp32", side, plan=plan)
+        assert np.isfinite(got).all()
+        assert err.max() <= TOL["fp32"], (side, err.max(), np.argmax(err))
+
+
+def test_set_plan_rejects_bad_values(bp):
+    r = synth.planted(seed=5, M=60, N=25, nnz=600, K=10, zipf=0.9)
+    s = bp.Sampler(r, 16, prec="fp32", seed=1)
+    for plan in [(0, 32, 0), (1 << 25, 32, 0), (2048, 65, 0), (2048, 32, 5), (2048, -1, 0)]:
+        with pytest.raises(RuntimeError):
+            s.set_plan(*plan)
+    s.close()
+    s = bp.Sampler(r, 16, prec="fp64", seed=1)
+    with pytest.raises(RuntimeError):
+        s.set_plan(2048, 32, 8)  # the rank-one path is FP32 only
+    s.close()
 
 
 @pytest.mark.parametrize("K", [10, 32, 48, 64])
