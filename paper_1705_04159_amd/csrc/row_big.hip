@@ -510,7 +510,8 @@ bool big_path_available(const bpmf_ctx *c)
     if (c->prec == 0 || c->K > 128) return false;
     if (c->prec == 1 && c->K <= c->fast_kmax && c->K <= 64) return false;  // column-per-lane kernel
     for (int s = 0; s < 2; ++s)
-        if ((uint64_t)c->side[s].rows * c->ld * sizeof(float) >= kOOB) return false;
+        if ((uint64_t)c->side[s].rows * c->ld * sizeof(float) >= kOOB || c->side[s].rows >= (1 << 24))
+            return false;  // 32-bit buffer offsets, 24-bit row ids in the gather
     return (uint64_t)c->split_threshold * 4u < kOOB;
 }
 

@@ -1,5 +1,6 @@
 // row_common.h -- device helpers shared by the matrix-core row kernels.
 #pragma once
+#include <type_traits>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -90,8 +91,14 @@ __device__ __forceinline__ float bm_normal_f32(uint32_t wr, uint32_t wa, bool si
 // of the neighbour row of rating 4g + l / 16, which is both the A operand of
 // block row bi and the B operand of block column bj.  Software-pipelined:
 // ids of chunk c+2 and rows of chunk c+1 are in flight while chunk c is
-// multiplied.  Ratings past the end read as 0 (buffer range check).
-template <int NB, int kUnroll>
+// multiplied.  Ratings past the end read as 0 (buffer range check); only the
+// last chunk of an item checks for them.  Row offsets use the full-rate
+// 24-bit multiply (the gathered factor has fewer than 2^24 rows).  With
+// PADOK the caller ignores every Gram and rhs entry outside the leading
+// K x K block, so all blocks load at immediate offsets from one address
+// (components >= K then hold whatever follows the row); otherwise
+// components >= K read as 0 through lane_off.
+template <int NB, int kUnroll, bool PADOK>
 __device__ __forceinline__ void gram_item_pipe(const RowItem &it, const int32_t *__restrict__ nbr,
                                           const float *__restrict__ rc,
                                           __amdgpu_buffer_rsrc_t ysrc, uint32_t ldy4,
@@ -110,15 +117,30 @@ __device__ __forceinline__ void gram_item_pipe(const RowItem &it, const int32_t 
 #pragma unroll
         for (int g = 0; g < kUnroll; ++g) jb[buf][g] = buf_u32(jsrc, (ch * kChunk + 4 * g + kq) * 4u);
     };
-    auto load_rows = [&](int buf, uint32_t ch) {
+    auto load_rows_t = [&](int buf, uint32_t ch, auto checkc) {
+        constexpr bool CHECK = decltype(checkc)::value;
 #pragma unroll
         for (int g = 0; g < kUnroll; ++g) {
             const uint32_t t = ch * kChunk + 4 * g + kq;
             rb[buf][g] = buf_f32(rsrc, t * 4u);  // 0 past the end
-            const uint32_t base = t < cnt ? jb[buf][g] * ldy4 : kOOB;
+            uint32_t base = __umul24(jb[buf][g], ldy4);
+            if constexpr (CHECK) base = t < cnt ? base : kOOB;
+            if constexpr (PADOK) {
+                const uint32_t a = base + lane_off[0];
 #pragma unroll
-            for (int bi = 0; bi < NB; ++bi) yb[buf][g][bi] = buf_f32(ysrc, base + lane_off[bi]);
+                for (int bi = 0; bi < NB; ++bi) yb[buf][g][bi] = buf_f32(ysrc, a + 64u * bi);
+            } else {
+#pragma unroll
+                for (int bi = 0; bi < NB; ++bi) yb[buf][g][bi] = buf_f32(ysrc, base + lane_off[bi]);
+            }
         }
+    };
+    // only the last chunk (and the prefetch past it) can hold ratings past the end
+    auto load_rows = [&](int buf, uint32_t ch) {
+        if (ch + 1 < nchunk)
+            load_rows_t(buf, ch, std::integral_constant<bool, false>{});
+        else
+            load_rows_t(buf, ch, std::integral_constant<bool, true>{});
     };
     auto compute = [&](int buf) {
 #pragma unroll
@@ -153,14 +175,14 @@ __device__ __forceinline__ void gram_item_pipe(const RowItem &it, const int32_t 
 // Gram and rhs of one work item into the accumulators (whole wave): the
 // pipelined per-group form, four groups (16 ratings) per stage for rows of
 // up to 32 components and two for wider rows (register budget).
-template <int NB>
+template <int NB, bool PADOK = false>
 __device__ __forceinline__ void gram_item(const RowItem &it, const int32_t *__restrict__ nbr,
                                           const float *__restrict__ rc,
                                           __amdgpu_buffer_rsrc_t ysrc, uint32_t ldy4,
                                           const uint32_t (&lane_off)[NB], int kq,
                                           floatx4 (&acc)[NB * (NB + 1) / 2], float (&bacc)[NB])
 {
-    gram_item_pipe<NB, (NB <= 2 ? 4 : 2)>(it, nbr, rc, ysrc, ldy4, lane_off, kq, acc, bacc);
+    gram_item_pipe<NB, (NB <= 2 ? 4 : 2), PADOK>(it, nbr, rc, ysrc, ldy4, lane_off, kq, acc, bacc);
 }
 
 }  // namespace

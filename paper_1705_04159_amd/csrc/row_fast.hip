@@ -112,8 +112,11 @@ __global__ __launch_bounds__(256) void prior_packed(int K, int KP, const float *
     LamPk[e] = (r < K && cc < K) ? Lam[r * K + cc] : 0.f;
 }
 
+// At least six waves per SIMD asked of the register allocator (K = 32: 71
+// registers, so seven fit), which hides more of the gather latency than
+// the unrestricted allocation's extra unrolling.
 template <int NB, int RPW, int WPB>
-__global__ __launch_bounds__(64 * WPB) void row_fast_f32(
+__global__ __launch_bounds__(64 * WPB, 6) void row_fast_f32(
     int K, float alpha, const RowItem *__restrict__ items, int64_t n_items,
     const int32_t *__restrict__ nbr, const float *__restrict__ rc, const float *__restrict__ Y,
     int ldy, uint32_t y_bytes, const float *__restrict__ LamPk, const float *__restrict__ Lmu,
@@ -169,7 +172,7 @@ __global__ __launch_bounds__(64 * WPB) void row_fast_f32(
         float bacc[NB];
 #pragma unroll
         for (int bi = 0; bi < NB; ++bi) bacc[bi] = 0.f;
-        gram_item<NB>(it, nbr, rc, ysrc, ldy4, lane_off, kq, acc, bacc);
+        gram_item<NB, true>(it, nbr, rc, ysrc, ldy4, lane_off, kq, acc, bacc);
         // sum the rhs over the four rating slots of each 16-lane column
 #pragma unroll
         for (int bi = 0; bi < NB; ++bi) {
@@ -280,7 +283,7 @@ __global__ __launch_bounds__(64 * WPB) void foldin_draw_f32(
         float bacc[NB];
 #pragma unroll
         for (int bi = 0; bi < NB; ++bi) bacc[bi] = 0.f;
-        gram_item<NB>(it, nbr, rc, ysrc, ldy4, lane_off, kq, acc, bacc);
+        gram_item<NB, true>(it, nbr, rc, ysrc, ldy4, lane_off, kq, acc, bacc);
 #pragma unroll
         for (int bi = 0; bi < NB; ++bi) {
             bacc[bi] += __shfl_xor(bacc[bi], 16);
@@ -459,7 +462,8 @@ bool fast_path_available(const bpmf_ctx *c)
 {
     if (c->prec != 1 || c->K > 64) return false;
     for (int s = 0; s < 2; ++s)
-        if ((uint64_t)c->side[s].rows * c->ld * sizeof(float) >= kOOB) return false;
+        if ((uint64_t)c->side[s].rows * c->ld * sizeof(float) >= kOOB || c->side[s].rows >= (1 << 24))
+            return false;  // 32-bit buffer offsets, 24-bit row ids in the gather
     return (uint64_t)c->split_threshold * 4u < kOOB;
 }
 
