@@ -45,8 +45,10 @@ __device__ __forceinline__ double group_dot(int K, const T *u, const T *v, int g
 }
 
 // One group of G lanes per test pair, grid-stride over pairs with a fixed
-// grid.  Writes per-block sums of squared errors (running mean, sample).
-// FP32 factors are read as float4 (rows are padded to a multiple of 4).
+// grid, four pairs per group in flight (their ids, values and running sums
+// are loaded before any row, so the dependent loads of the four overlap).
+// Writes per-block sums of squared errors (running mean, sample).  FP32
+// factors are read as float4 (rows are padded to a multiple of 4).
 template <typename T, int G>
 __global__ __launch_bounds__(256) void predict_test(
     int K, int ld, int64_t n, const int32_t *__restrict__ row, const int32_t *__restrict__ col,
@@ -55,6 +57,7 @@ __global__ __launch_bounds__(256) void predict_test(
     double *__restrict__ part)
 {
     constexpr int GPB = 256 / G;  // groups per block
+    constexpr int P = 4;          // pairs per group in flight
     __shared__ double red[2][GPB];
     const uint32_t t = ctr[0];
     const uint32_t cnt = ctr[2];
@@ -63,33 +66,55 @@ __global__ __launch_bounds__(256) void predict_test(
     const int grp = threadIdx.x / G;
     const int64_t groups_total = (int64_t)gridDim.x * GPB;
     double sa = 0.0, sl = 0.0;
-    for (int64_t e = (int64_t)blockIdx.x * GPB + grp; e < n; e += groups_total) {
-        const T *u = U + (size_t)row[e] * ld;
-        const T *v = V + (size_t)col[e] * ld;
-        T s = T(0);
-        if constexpr (sizeof(T) == 4) {
-            for (int k = 4 * g; k < K; k += 4 * G) {
-                const float4 a = *reinterpret_cast<const float4 *>(u + k);
-                const float4 b = *reinterpret_cast<const float4 *>(v + k);
-                s += a.x * b.x + a.y * b.y + a.z * b.z + a.w * b.w;  // padding entries are 0
+    for (int64_t e0 = (int64_t)blockIdx.x * GPB + grp; e0 < n; e0 += P * groups_total) {
+        int64_t e[P];
+        bool ok[P];
+        int32_t ri[P], ci[P];
+        float rv[P];
+        double prev[P];
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+            e[q] = e0 + q * groups_total;
+            ok[q] = e[q] < n;
+            ri[q] = ok[q] ? row[e[q]] : 0;
+            ci[q] = ok[q] ? col[e[q]] : 0;
+            rv[q] = ok[q] ? val[e[q]] : 0.f;
+            prev[q] = ok[q] && (use || cnt) ? pred_sum[e[q]] : 0.0;
+        }
+        T s[P];
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+            const T *u = U + (size_t)ri[q] * ld;
+            const T *v = V + (size_t)ci[q] * ld;
+            s[q] = T(0);
+            if constexpr (sizeof(T) == 4) {
+                for (int k = 4 * g; k < K; k += 4 * G) {
+                    const float4 a = *reinterpret_cast<const float4 *>(u + k);
+                    const float4 b = *reinterpret_cast<const float4 *>(v + k);
+                    s[q] += a.x * b.x + a.y * b.y + a.z * b.z + a.w * b.w;  // padding entries are 0
+                }
+            } else {
+                for (int k = g; k < K; k += G) s[q] += u[k] * v[k];
             }
-        } else {
-            for (int k = g; k < K; k += G) s += u[k] * v[k];
         }
 #pragma unroll
-        for (int off = G / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, G);
-        const double p = (double)s + rbar;
-        double avg;
-        if (use) {
-            const double ps = pred_sum[e] + p;
-            avg = ps / (double)(cnt + 1);
-            if (g == 0) pred_sum[e] = ps;
-        } else {
-            avg = cnt ? pred_sum[e] / (double)cnt : p;
+        for (int q = 0; q < P; ++q) {
+#pragma unroll
+            for (int off = G / 2; off > 0; off >>= 1) s[q] += __shfl_xor(s[q], off, G);
+            if (!ok[q]) continue;
+            const double p = (double)s[q] + rbar;
+            double avg;
+            if (use) {
+                const double ps = prev[q] + p;
+                avg = ps / (double)(cnt + 1);
+                if (g == 0) pred_sum[e[q]] = ps;
+            } else {
+                avg = cnt ? prev[q] / (double)cnt : p;
+            }
+            const double r = (double)rv[q];
+            sa += (avg - r) * (avg - r);
+            sl += (p - r) * (p - r);
         }
-        const double r = (double)val[e];
-        sa += (avg - r) * (avg - r);
-        sl += (p - r) * (p - r);
     }
     if (g == 0) {
         red[0][grp] = sa;
@@ -114,6 +139,7 @@ __global__ __launch_bounds__(256) void predict_finalize(int nblk, int64_t n,
     __shared__ double red[2][256];
     const int tid = threadIdx.x;
     double sa = 0.0, sl = 0.0;
+#pragma unroll 8
     for (int b = tid; b < nblk; b += 256) {
         sa += part[2 * b];
         sl += part[2 * b + 1];

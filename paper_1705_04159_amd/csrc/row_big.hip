@@ -87,12 +87,14 @@ __device__ __forceinline__ void gram_item_bf16(const RowItem &it, const int32_t 
     for (uint32_t ch = 0; ch < nchunk; ++ch) {
         uint32_t base[8];
         float r[8];
+        const bool last = ch + 1 == nchunk;  // only the last chunk can run past the end
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const uint32_t t = ch * 32 + 8 * kq + e;
             const uint32_t j = buf_u32(jsrc, t * 4u);
             r[e] = buf_f32(rsrc, t * 4u);
-            base[e] = t < cnt ? j * ldy2 : kOOB;
+            base[e] = __umul24(j, ldy2);  // fewer than 2^24 rows
+            if (last) base[e] = t < cnt ? base[e] : kOOB;
         }
         // raw BF16 bits; pairs packed into dwords form the MFMA operand
         uint32_t yr[NB][8];

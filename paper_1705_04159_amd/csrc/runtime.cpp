@@ -490,11 +490,26 @@ int bpmf_create(int64_t M, int64_t N, const int64_t *csr_ptr, const int32_t *csr
         CK(dalloc(&c->test_val, n_test));
         CK(dalloc(&c->pred_sum, n_test));
         if (n_test) {
-            CK(hipMemcpy(c->test_row, test_row, sizeof(int32_t) * n_test, hipMemcpyHostToDevice));
-            CK(hipMemcpy(c->test_col, test_col, sizeof(int32_t) * n_test, hipMemcpyHostToDevice));
-            CK(hipMemcpy(c->test_val, test_val, sizeof(float) * n_test, hipMemcpyHostToDevice));
+            // held in user order (stable counting sort): the pairs of one user
+            // are neighbours, so the prediction kernel reads each user's row
+            // once per wave instead of once per pair; only the order of the
+            // FP64 error sums depends on it
+            std::vector<int64_t> start(M + 1, 0);
+            for (int64_t e = 0; e < n_test; ++e) ++start[test_row[e] + 1];
+            for (int64_t i = 0; i < M; ++i) start[i + 1] += start[i];
+            std::vector<int32_t> tr(n_test), tc(n_test);
+            std::vector<float> tv(n_test);
+            for (int64_t e = 0; e < n_test; ++e) {
+                const int64_t q = start[test_row[e]]++;
+                tr[q] = test_row[e];
+                tc[q] = test_col[e];
+                tv[q] = test_val[e];
+            }
+            CK(hipMemcpy(c->test_row, tr.data(), sizeof(int32_t) * n_test, hipMemcpyHostToDevice));
+            CK(hipMemcpy(c->test_col, tc.data(), sizeof(int32_t) * n_test, hipMemcpyHostToDevice));
+            CK(hipMemcpy(c->test_val, tv.data(), sizeof(float) * n_test, hipMemcpyHostToDevice));
         }
-        c->rmse_blocks = (int)std::min<int64_t>(16384, std::max<int64_t>(1, (n_test + 31) / 32));
+        c->rmse_blocks = (int)std::min<int64_t>(8192, std::max<int64_t>(1, (n_test + 127) / 128));
         CK(dalloc(&c->rmse_part, 2 * (size_t)c->rmse_blocks));
         c->hist_cap = 64;
         CK(dalloc(&c->rmse_hist, 2 * (size_t)c->hist_cap));
