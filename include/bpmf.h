@@ -214,12 +214,14 @@ int bpmf_autotune(bpmf_ctx *c, uint32_t n_sweeps, int32_t *chosen_split, int32_t
  * rank-one path where it does not apply. */
 int bpmf_set_plan(bpmf_ctx *c, int32_t split_threshold, int32_t fast_kmax, int32_t lowrank_dmax);
 
-/* Mean device time (ms) of one launch of the row-update kernel (the work
- * items of the row loops of Algorithm 1, split-row finishing excluded) over
- * the sweeps of the most recent bpmf_run_sweeps call: ms[0] for the V side,
- * ms[1] for the U side.  Measured inside the sweep graph with HIP events
- * recorded on the kernel's own stream just before and after it, one set per
- * replay (the first 1023 replays and the last).  Caller-owned ms[2].
+/* Mean device time (ms) of one side's row update (the item loop of
+ * Algorithm 1: every work item -- segments of split rows, whole rows, rows on
+ * the rank-one path -- and the finishing of split rows; not the BF16 shadow
+ * copy) over the sweeps of the most recent bpmf_run_sweeps call: ms[0] for
+ * the V side, ms[1] for the U side.  Measured inside the sweep graph with HIP
+ * events recorded just before the side's first kernel and after its last
+ * (both on the stream that joins the update's branches), one set per replay
+ * (the first 1023 replays and the last).  Caller-owned ms[2].
  * BPMF_E_INVAL if no sweeps were timed. */
 int bpmf_row_kernel_ms(bpmf_ctx *c, double *ms);
 

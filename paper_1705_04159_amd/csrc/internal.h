@@ -40,6 +40,15 @@ struct FoldItem {
 
 struct FoldinState;  // fold-in server (foldin.cpp)
 
+// Stages of one side's row update (the item loop of Algorithm 1), in an
+// order that is also a valid serial order: the working copies of the prior
+// the row kernels read; the segments of split rows (partial sums); the whole
+// rows and the rank-one path; the finishing of split rows (needs the
+// segments); the BF16 shadow of the factor (needs everything).  Whole rows
+// depend only on the prior, so the sweep graph runs them beside the
+// segments and the finishing.
+enum UpdateStage { kStagePrior = 0, kStageSegments = 1, kStageRows = 2, kStageFinish = 3, kStageShadow = 4 };
+
 struct Side {
     int64_t rows = 0;
     int64_t *ptr = nullptr;  // device [rows + 1] neighbour offsets
@@ -79,7 +88,9 @@ struct bpmf_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     hipStream_t stream2 = nullptr;          // second stream for overlapped hyper draws
+    hipStream_t stream3 = nullptr;          // whole rows beside the split rows in the graph
     hipEvent_t fork_ev[3] = {};             // fork/join events of the sweep graph
+    hipEvent_t stage_ev[2] = {};            // fork/join of a side's whole-row branch
     int64_t M = 0, N = 0, nnz = 0, n_test = 0;
     int K = 0, ld = 0, prec = 1;
     double alpha = 2, beta0 = 2, nu0 = 0, rbar = 0;

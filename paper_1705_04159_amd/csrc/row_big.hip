@@ -465,7 +465,13 @@ hipError_t launch_big(bpmf_ctx *c, Side &sd, Side &ot, hipStream_t s, int stage)
 {
     const size_t lds = sizeof(float) * kBigWPB * BigLds<NB>::TOTAL;
     const floatx4 *img = (const floatx4 *)sd.Lam_img;
-    if (stage == 1) {
+    if (stage == kStagePrior) {
+        // the prior image of this sweep (read by the whole rows and the finishing)
+        hipLaunchKernelGGL((prior_image<NB>), dim3((NB * (NB + 1) / 2 * 256 + 255) / 256), dim3(256), 0, s,
+                           c->K, (const float *)sd.Lam_w, sd.Lam_img);
+        return hipGetLastError();
+    }
+    if (stage == kStageFinish) {
         if (sd.n_fin == 0) return hipSuccess;
         hipError_t e = launch_part_reduce(c, sd, s, big_slot_elems<NB>());
         if (e != hipSuccess) return e;
@@ -476,10 +482,8 @@ hipError_t launch_big(bpmf_ctx *c, Side &sd, Side &ot, hipStream_t s, int stage)
                            c->ctr);
         return hipGetLastError();
     }
-    // the prior image of this sweep, segments of split rows (items
-    // [0, n_slots)), then whole rows
-    hipLaunchKernelGGL((prior_image<NB>), dim3((NB * (NB + 1) / 2 * 256 + 255) / 256), dim3(256), 0, s, c->K,
-                       (const float *)sd.Lam_w, sd.Lam_img);
+    if (stage != kStageSegments && stage != kStageRows) return hipSuccess;
+    // segments of split rows are items [0, n_slots), whole rows follow
     const int64_t n_seg = sd.n_slots, n_rows = sd.n_items - sd.n_slots - sd.n_low;
     const bool bf = c->prec == 2;
     const void *ysrc = bf ? (const void *)ot.Xbf : (const void *)ot.X;
@@ -493,12 +497,16 @@ hipError_t launch_big(bpmf_ctx *c, Side &sd, Side &ot, hipStream_t s, int stage)
                            (const float *)sd.Lmu_w, (float *)sd.X, c->ld, (float *)c->part,
                            c->seed, sd.stream_row, c->ctr);
     };
-    if (bf) {
-        go(row_big<NB, true, true>, 0, n_seg, 0);
-        go(row_big<NB, true, false>, n_seg, n_rows, lds);
+    if (stage == kStageSegments) {
+        if (bf)
+            go(row_big<NB, true, true>, 0, n_seg, 0);
+        else
+            go(row_big<NB, false, true>, 0, n_seg, 0);
     } else {
-        go(row_big<NB, false, true>, 0, n_seg, 0);
-        go(row_big<NB, false, false>, n_seg, n_rows, lds);
+        if (bf)
+            go(row_big<NB, true, false>, n_seg, n_rows, lds);
+        else
+            go(row_big<NB, false, false>, n_seg, n_rows, lds);
     }
     return hipGetLastError();
 }

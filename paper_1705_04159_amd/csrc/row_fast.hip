@@ -117,7 +117,7 @@ __global__ __launch_bounds__(256) void prior_packed(int K, int KP, const float *
 // the unrestricted allocation's extra unrolling.
 template <int NB, int RPW, int WPB>
 __global__ __launch_bounds__(64 * WPB, 6) void row_fast_f32(
-    int K, float alpha, const RowItem *__restrict__ items, int64_t n_items,
+    int K, float alpha, const RowItem *__restrict__ items, int64_t item0, int64_t n_items,
     const int32_t *__restrict__ nbr, const float *__restrict__ rc, const float *__restrict__ Y,
     int ldy, uint32_t y_bytes, const float *__restrict__ LamPk, const float *__restrict__ Lmu,
     float *__restrict__ X, int ldx, float *__restrict__ part, uint64_t seed, uint32_t stream,
@@ -130,7 +130,7 @@ __global__ __launch_bounds__(64 * WPB, 6) void row_fast_f32(
     extern __shared__ float smem_f[];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
-    const int64_t first = ((int64_t)blockIdx.x * WPB + wave) * RPW;
+    const int64_t first = item0 + ((int64_t)blockIdx.x * WPB + wave) * RPW;
     if (first >= n_items) return;
     float *Ps = smem_f + wave * RPW * REGION;
     const int col = lane & 15;
@@ -393,20 +393,20 @@ hipError_t launch_finish_f32(bpmf_ctx *c, Side &sd, hipStream_t s)
     return hipGetLastError();
 }
 
+// Work items [item0, item_end): the segments of split rows are [0, n_slots),
+// the whole rows follow, the rank-one path takes the last n_low.
 template <int NB, int RPW, int WPB>
-hipError_t launch_f32(bpmf_ctx *c, Side &sd, Side &ot, hipStream_t s)
+hipError_t launch_f32(bpmf_ctx *c, Side &sd, Side &ot, hipStream_t s, int64_t item0, int64_t item_end)
 {
     constexpr int KP = 16 * NB;
     const size_t lds = sizeof(float) * WPB * RPW * (KP * (KP + 1) / 2 + KP);
-    const int64_t n_items = sd.n_items - sd.n_low;  // the rank-one path takes the tail
+    const int64_t count = item_end - item0;
     const int64_t per_block = (int64_t)WPB * RPW;
-    const unsigned grid = (unsigned)((n_items + per_block - 1) / per_block);
+    const unsigned grid = (unsigned)((count + per_block - 1) / per_block);
     const uint32_t y_bytes = (uint32_t)(ot.rows * c->ld * sizeof(float));
-    if (n_items == 0) return hipSuccess;
-    hipLaunchKernelGGL(prior_packed, dim3((KP * (KP + 1) / 2 + 255) / 256), dim3(256), 0, s, c->K, KP,
-                       (const float *)sd.Lam_w, sd.Lam_pk);
+    if (count <= 0) return hipSuccess;
     hipLaunchKernelGGL((row_fast_f32<NB, RPW, WPB>), dim3(grid), dim3(64 * WPB), lds, s, c->K,
-                       (float)c->alpha, sd.items, n_items, sd.nbr, (const float *)sd.rc,
+                       (float)c->alpha, sd.items, item0, item_end, sd.nbr, (const float *)sd.rc,
                        (const float *)ot.X, c->ld, y_bytes, (const float *)sd.Lam_pk,
                        (const float *)sd.Lmu_w, (float *)sd.X, c->ld, (float *)c->part, c->seed,
                        sd.stream_row, c->ctr);
@@ -478,20 +478,34 @@ hipError_t launch_row_fast(bpmf_ctx *c, int side_id, hipStream_t s, int stage, b
     Side &sd = c->side[side_id];
     Side &ot = c->side[1 - side_id];
     const int nb = (c->K + 15) / 16;
-    if (stage == 1) {
+    switch (stage) {
+    case kStagePrior: {
+        const int KP = 16 * nb;
+        hipLaunchKernelGGL(prior_packed, dim3((KP * (KP + 1) / 2 + 255) / 256), dim3(256), 0, s, c->K, KP,
+                           (const float *)sd.Lam_w, sd.Lam_pk);
+        return hipGetLastError();
+    }
+    case kStageFinish:
         switch (nb) {
         case 1: return launch_finish_f32<1, 4>(c, sd, s);
         case 2: return launch_finish_f32<2, 4>(c, sd, s);
         case 3: return launch_finish_f32<3, 2>(c, sd, s);
         default: return launch_finish_f32<4, 2>(c, sd, s);
         }
+    case kStageSegments: {
+        // segments and whole rows in one launch: the heavy segments start
+        // first and the whole rows fill in behind them, which balances the
+        // load better than two launches (measured); the rank-one path (whole
+        // rows stage) still runs beside it
+        const int64_t e = sd.n_items - sd.n_low;
+        switch (nb) {
+        case 1: return launch_f32<1, 4, 4>(c, sd, ot, s, 0, e);
+        case 2: return launch_f32<2, 2, 4>(c, sd, ot, s, 0, e);
+        case 3: return launch_f32<3, 1, 2>(c, sd, ot, s, 0, e);
+        default: return launch_f32<4, 1, 2>(c, sd, ot, s, 0, e);
+        }
     }
-    if (sd.n_items == 0) return hipSuccess;
-    switch (nb) {
-    case 1: return launch_f32<1, 4, 4>(c, sd, ot, s);
-    case 2: return launch_f32<2, 2, 4>(c, sd, ot, s);
-    case 3: return launch_f32<3, 1, 2>(c, sd, ot, s);
-    default: return launch_f32<4, 1, 2>(c, sd, ot, s);
+    default: return hipSuccess;
     }
 }
 

@@ -227,6 +227,8 @@ size_t row_generic_lds_bytes(int K, int prec)
     return prec == 0 ? lds_bytes<double>(K) : lds_bytes<float>(K);
 }
 
+// One workgroup per work item; every item (segments and whole rows) in the
+// segments stage, the split rows in the finishing stage.
 hipError_t launch_row_generic(bpmf_ctx *c, int side_id, hipStream_t s, int stage)
 {
     Side &sd = c->side[side_id];
@@ -234,14 +236,14 @@ hipError_t launch_row_generic(bpmf_ctx *c, int side_id, hipStream_t s, int stage
     const int K = c->K;
     if (c->prec == 0) {
         size_t lds = lds_bytes<double>(K);
-        if (stage == 0 && sd.n_items > 0)
+        if (stage == kStageSegments && sd.n_items > 0)
             hipLaunchKernelGGL((row_update_generic<double, double>), dim3((unsigned)sd.n_items),
                                dim3(kThreads), lds, s, K, c->alpha, sd.items, sd.nbr,
                                (const double *)sd.rc, (const double *)ot.X, c->ld,
                                (const double *)sd.Lam_w, (const double *)sd.Lmu_w,
                                (double *)sd.X, c->ld, (double *)c->part, c->seed, sd.stream_row,
                                c->ctr);
-        if (stage == 1 && sd.n_fin > 0)
+        if (stage == kStageFinish && sd.n_fin > 0)
             hipLaunchKernelGGL((row_finish_generic<double>), dim3((unsigned)sd.n_fin),
                                dim3(kThreads), lds, s, K, c->alpha, sd.fin,
                                (const double *)c->part, (const double *)sd.Lam_w,
@@ -249,7 +251,7 @@ hipError_t launch_row_generic(bpmf_ctx *c, int side_id, hipStream_t s, int stage
                                sd.stream_row, c->ctr);
     } else {
         size_t lds = lds_bytes<float>(K);
-        if (stage == 0 && sd.n_items > 0) {
+        if (stage == kStageSegments && sd.n_items > 0) {
             if (c->prec == 2)
                 hipLaunchKernelGGL((row_update_generic<float, uint16_t>),
                                    dim3((unsigned)sd.n_items), dim3(kThreads), lds, s, K,
@@ -265,7 +267,7 @@ hipError_t launch_row_generic(bpmf_ctx *c, int side_id, hipStream_t s, int stage
                                    (float *)sd.X, c->ld, (float *)c->part, c->seed,
                                    sd.stream_row, c->ctr);
         }
-        if (stage == 1 && sd.n_fin > 0)
+        if (stage == kStageFinish && sd.n_fin > 0)
             hipLaunchKernelGGL((row_finish_generic<float>), dim3((unsigned)sd.n_fin),
                                dim3(kThreads), lds, s, K, (float)c->alpha, sd.fin,
                                (const float *)c->part, (const float *)sd.Lam_w,

@@ -165,10 +165,10 @@ hipError_t alloc_lowrank(bpmf_ctx *c, Side &sd, int64_t other_rows)
 
 size_t elem_bytes(const bpmf_ctx *c) { return c->prec == 0 ? sizeof(double) : sizeof(float); }
 
-// Stage 0: the row kernel over all work items (whole rows and segments of
-// split rows).  Stage 1: finishing the split rows, then the BF16 copy.
+// One stage of a side's row update (see UpdateStage).
 hipError_t enqueue_update_stage(bpmf_ctx *c, int side_id, hipStream_t s, int stage)
 {
+    if (stage == kStageShadow) return c->prec == 2 ? launch_to_bf16(c, side_id, s) : hipSuccess;
     bool handled = false;
     hipError_t e = launch_row_fast(c, side_id, s, stage, &handled);
     if (e != hipSuccess) return e;
@@ -176,21 +176,25 @@ hipError_t enqueue_update_stage(bpmf_ctx *c, int side_id, hipStream_t s, int sta
     if (e != hipSuccess) return e;
     if (!handled) e = launch_row_generic(c, side_id, s, stage);
     if (e != hipSuccess) return e;
-    if (stage == 0 && c->side[side_id].n_low) e = launch_row_lowrank(c, side_id, s);
-    if (e != hipSuccess) return e;
-    if (stage == 1 && c->prec == 2) e = launch_to_bf16(c, side_id, s);
+    if (stage == kStageRows && c->side[side_id].n_low) e = launch_row_lowrank(c, side_id, s);
     return e;
+}
+
+hipError_t enqueue_update_stages(bpmf_ctx *c, int side_id, hipStream_t s, int first, int last)
+{
+    for (int st = first; st <= last; ++st)
+        if (hipError_t e = enqueue_update_stage(c, side_id, s, st)) return e;
+    return hipSuccess;
 }
 
 hipError_t enqueue_update(bpmf_ctx *c, int side_id, hipStream_t s)
 {
-    hipError_t e = enqueue_update_stage(c, side_id, s, 0);
-    if (e != hipSuccess) return e;
-    return enqueue_update_stage(c, side_id, s, 1);
+    return enqueue_update_stages(c, side_id, s, kStagePrior, kStageShadow);
 }
 
 // Algorithm 1 once, eagerly, with an event after every phase:
-// [hyper V][rows V][split V][hyper U][rows U][split U][predict] -> 7 intervals.
+// [hyper V][rows V][split V][hyper U][rows U][split U][predict] -> 7 intervals
+// (rows: prior, segments and whole rows; split: finishing and BF16 shadow).
 hipError_t enqueue_sweep_profiled(bpmf_ctx *c, hipStream_t s, hipEvent_t *ev)
 {
     hipError_t e;
@@ -200,9 +204,9 @@ hipError_t enqueue_sweep_profiled(bpmf_ctx *c, hipStream_t s, hipEvent_t *ev)
     for (int side : {BPMF_SIDE_V, BPMF_SIDE_U}) {
         if ((e = launch_hyper(c, side, s)) != hipSuccess) return e;
         if ((e = hipEventRecord(ev[q++], s)) != hipSuccess) return e;
-        if ((e = enqueue_update_stage(c, side, s, 0)) != hipSuccess) return e;
+        if ((e = enqueue_update_stages(c, side, s, kStagePrior, kStageRows)) != hipSuccess) return e;
         if ((e = hipEventRecord(ev[q++], s)) != hipSuccess) return e;
-        if ((e = enqueue_update_stage(c, side, s, 1)) != hipSuccess) return e;
+        if ((e = enqueue_update_stages(c, side, s, kStageFinish, kStageShadow)) != hipSuccess) return e;
         if ((e = hipEventRecord(ev[q++], s)) != hipSuccess) return e;
     }
     if ((e = launch_predict_test(c, s)) != hipSuccess) return e;
@@ -215,15 +219,40 @@ hipError_t enqueue_sweep_profiled(bpmf_ctx *c, hipStream_t s, hipEvent_t *ev)
 // overlaps on a second stream: the U draw of sweep t needs only U of sweep
 // t-1, so it runs beside the V update; the V draw of sweep t+1 needs only V
 // of sweep t, so it runs beside the U update.  The sweep ends by advancing t.
-// Row update of one side inside the captured sweep, with external event
-// records around the row kernel (stage 0) for timing.
+// Row update of one side inside the captured sweep: the whole rows on a
+// branch of their own beside the segments and finishing of the split rows,
+// with external event records around the update (all but the BF16 shadow)
+// for timing.
+// Whether the whole-rows stage launches anything of its own (the rank-one
+// path, or the blocked kernel's whole rows); without it the update stays on
+// one branch (a fork and join cost more than they hide).
+static bool rows_branch(const bpmf_ctx *c, const Side &sd)
+{
+    if (sd.n_low > 0) return true;
+    const bool fast = fast_path_available(c) && c->K <= c->fast_kmax;
+    return !fast && big_path_available(c) && sd.n_items - sd.n_slots - sd.n_low > 0;
+}
+
 hipError_t enqueue_update_timed(bpmf_ctx *c, int side_id, hipStream_t s, hipEvent_t a, hipEvent_t b)
 {
     hipError_t e;
+    hipStream_t s3 = c->stream3;
     if ((e = hipEventRecordWithFlags(a, s, hipEventRecordExternal)) != hipSuccess) return e;
-    if ((e = enqueue_update_stage(c, side_id, s, 0)) != hipSuccess) return e;
+    if (!rows_branch(c, c->side[side_id])) {
+        if ((e = enqueue_update_stages(c, side_id, s, kStagePrior, kStageFinish)) != hipSuccess) return e;
+        if ((e = hipEventRecordWithFlags(b, s, hipEventRecordExternal)) != hipSuccess) return e;
+        return enqueue_update_stage(c, side_id, s, kStageShadow);
+    }
+    if ((e = enqueue_update_stage(c, side_id, s, kStagePrior)) != hipSuccess) return e;
+    if ((e = hipEventRecord(c->stage_ev[0], s)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(s3, c->stage_ev[0], 0)) != hipSuccess) return e;
+    if ((e = enqueue_update_stage(c, side_id, s3, kStageRows)) != hipSuccess) return e;
+    if ((e = hipEventRecord(c->stage_ev[1], s3)) != hipSuccess) return e;
+    if ((e = enqueue_update_stages(c, side_id, s, kStageSegments, kStageSegments)) != hipSuccess) return e;
+    if ((e = enqueue_update_stage(c, side_id, s, kStageFinish)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(s, c->stage_ev[1], 0)) != hipSuccess) return e;
     if ((e = hipEventRecordWithFlags(b, s, hipEventRecordExternal)) != hipSuccess) return e;
-    return enqueue_update_stage(c, side_id, s, 1);
+    return enqueue_update_stage(c, side_id, s, kStageShadow);
 }
 
 hipError_t enqueue_sweep(bpmf_ctx *c, hipStream_t s)
@@ -396,7 +425,9 @@ int bpmf_create(int64_t M, int64_t N, const int64_t *csr_ptr, const int32_t *csr
         CK(hipGetDevice(&c->device));
         CK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
         CK(hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking));
+        CK(hipStreamCreateWithFlags(&c->stream3, hipStreamNonBlocking));
         for (auto &ev : c->fork_ev) CK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        for (auto &ev : c->stage_ev) CK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
         CK(hipEventCreate(&c->ev0));
         CK(hipEventCreate(&c->ev1));
         for (auto &ev : c->tev) CK(hipEventCreate(&ev));
@@ -550,7 +581,10 @@ void bpmf_destroy(bpmf_ctx *c)
     for (void *p : ps) (void)hipFree(p);
     for (auto &ev : c->fork_ev)
         if (ev) (void)hipEventDestroy(ev);
+    for (auto &ev : c->stage_ev)
+        if (ev) (void)hipEventDestroy(ev);
     if (c->stream2) (void)hipStreamDestroy(c->stream2);
+    if (c->stream3) (void)hipStreamDestroy(c->stream3);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     if (c->stream) (void)hipStreamDestroy(c->stream);
