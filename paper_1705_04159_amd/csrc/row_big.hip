@@ -410,8 +410,8 @@ __global__ __launch_bounds__(64 * kBigWPB, big_waves<NB>()) void row_big(
     }
 }
 
-// Split rows: the summed partial Gram (first slot) into the accumulators,
-// then the same factorisation.
+// Split rows: the partial Gram slots of the row, summed in slot order into
+// the accumulators, then the same factorisation.
 template <int NB>
 __global__ __launch_bounds__(64 * kBigWPB, big_waves<NB>()) void row_finish_big(
     int K, float alpha, const FinishItem *__restrict__ fin, int64_t n_fin,
@@ -429,15 +429,27 @@ __global__ __launch_bounds__(64 * kBigWPB, big_waves<NB>()) void row_finish_big(
     const int col = lane & 15;
     const int kq = lane >> 4;
     const FinishItem f = fin[fid];
+    // the row's partial slots summed in slot order
     const float *src = part + (size_t)f.first * big_slot_elems<NB>();
     floatx4 acc[NBLK];
 #pragma unroll
-    for (int q = 0; q < NBLK; ++q) acc[q] = reinterpret_cast<const floatx4 *>(src)[q * 64 + lane];
+    for (int q = 0; q < NBLK; ++q) acc[q] = floatx4{0.f, 0.f, 0.f, 0.f};
+    float bs[2] = {0.f, 0.f};
+    for (int sl = 0; sl < f.count; ++sl) {
+        const float *sq = src + (size_t)sl * big_slot_elems<NB>();
+#pragma unroll
+        for (int q = 0; q < NBLK; ++q) acc[q] += reinterpret_cast<const floatx4 *>(sq)[q * 64 + lane];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int c = lane + 64 * h;
+            if (c < 16 * NB) bs[h] += sq[NBLK * 256 + c];
+        }
+    }
     float *bv = lds + BigLds<NB>::PAN + BigLds<NB>::LDG + BigLds<NB>::INVD;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const int c = lane + 64 * h;
-        if (c < 16 * NB) bv[c] = c < K ? alpha * src[NBLK * 256 + c] + Lmu[c] : 0.f;
+        if (c < 16 * NB) bv[c] = c < K ? alpha * bs[h] + Lmu[c] : 0.f;
     }
     wave_sync();
     blocked_chol_sample<NB>(acc, lds, K, alpha, img, (uint32_t)f.row, ctr[0], seed, stream,
@@ -473,8 +485,6 @@ hipError_t launch_big(bpmf_ctx *c, Side &sd, Side &ot, hipStream_t s, int stage)
     }
     if (stage == kStageFinish) {
         if (sd.n_fin == 0) return hipSuccess;
-        hipError_t e = launch_part_reduce(c, sd, s, big_slot_elems<NB>());
-        if (e != hipSuccess) return e;
         const unsigned grid = (unsigned)((sd.n_fin + kBigWPB - 1) / kBigWPB);
         hipLaunchKernelGGL((row_finish_big<NB>), dim3(grid), dim3(64 * kBigWPB), lds, s, c->K,
                            (float)c->alpha, sd.fin, sd.n_fin, (const float *)c->part, img,
