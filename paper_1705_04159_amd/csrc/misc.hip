@@ -223,8 +223,8 @@ hipError_t launch_predict_test(bpmf_ctx *c, hipStream_t s)
                            c->n_test, c->test_row, c->test_col, c->test_val,
                            (const double *)c->side[0].X, (const double *)c->side[1].X, c->rbar,
                            c->pred_sum, c->ctr, c->burn_in, c->rmse_part);
-    else if (c->ld <= 32)
-        hipLaunchKernelGGL((predict_test<float, 8>), dim3(nblk), dim3(256), 0, s, c->K, c->ld,
+    else if (c->ld <= 32)  // four lanes per pair: twice the pairs in flight per wavefront
+        hipLaunchKernelGGL((predict_test<float, 4>), dim3(nblk), dim3(256), 0, s, c->K, c->ld,
                            c->n_test, c->test_row, c->test_col, c->test_val,
                            (const float *)c->side[0].X, (const float *)c->side[1].X, c->rbar,
                            c->pred_sum, c->ctr, c->burn_in, c->rmse_part);
