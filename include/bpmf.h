@@ -192,7 +192,8 @@ int bpmf_last_time_ms(bpmf_ctx *c, double *ms);
  * A candidate replaces the current plan only if it is at least 2% faster.
  * The chain state (factors, hyperparameters, running predictions, sweep
  * counter) is restored afterwards, so the chain continues as if no trial had
- * run; only the plan changes.  Outputs (each may be NULL): the chosen values,
+ * run; only the plan changes, and the sweep graph of the chosen plan is
+ * captured before returning.  Outputs (each may be NULL): the chosen values,
  * the number of candidates tried (at most 64) and, per candidate, its values
  * and mean ms per sweep (caller arrays of 64). */
 int bpmf_autotune(bpmf_ctx *c, uint32_t n_sweeps, int32_t *chosen_split, int32_t *chosen_kmax,
@@ -207,8 +208,9 @@ int bpmf_autotune(bpmf_ctx *c, uint32_t n_sweeps, int32_t *chosen_split, int32_t
  * at most that many ratings takes the rank-one update path -- unlike the
  * autotuner, without weighing the transform of the gathered factor).  The
  * work items, finishing items and partial-sum workspace are rebuilt and the
- * sweep graph is re-captured on the next bpmf_run_sweeps; the chain state is
- * untouched and the samples do not depend on the plan beyond rounding.  Used
+ * sweep graph is re-captured (not launched) before returning; the chain
+ * state is untouched and the samples do not depend on the plan beyond
+ * rounding.  Used
  * to time each kernel family per degree (the per-item cost against degree
  * of Sec. III, Fig. 2).  BPMF_E_INVAL for a value out of range or the
  * rank-one path where it does not apply. */

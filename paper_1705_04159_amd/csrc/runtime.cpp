@@ -667,6 +667,8 @@ static int find_timing_nodes(bpmf_ctx *c)
 // Re-plan both sides for a new split threshold / kernel family: work items,
 // finishing items and the partial-sum workspace; the sweep graph is rebuilt
 // on the next bpmf_run_sweeps.
+static int ensure_graph(bpmf_ctx *c);
+
 static int replan(bpmf_ctx *c, int split, int fast_kmax, int low_dmax, bool force_low = false)
 {
     HIPCK(c, hipStreamSynchronize(c->stream));
@@ -833,6 +835,7 @@ int bpmf_autotune(bpmf_ctx *c, uint32_t n_sweeps, int32_t *chosen_split, int32_t
     if (rc == BPMF_OK) rc = replan(c, best_split, best_kmax, best_low);
     if (rc == BPMF_OK) rc = snapshot_restore(c, sn);
     if (rc == BPMF_OK) rc = refresh_lowrank(c);
+    if (rc == BPMF_OK) rc = ensure_graph(c);  // the chosen plan's graph, ready for timed sweeps
     snapshot_free(sn);
     if (rc != BPMF_OK) return rc;
     if (chosen_split) *chosen_split = best_split;
@@ -840,6 +843,30 @@ int bpmf_autotune(bpmf_ctx *c, uint32_t n_sweeps, int32_t *chosen_split, int32_t
     if (chosen_low) *chosen_low = best_low;
     if (n_tried) *n_tried = std::min(q, 64);
     return BPMF_OK;
+}
+
+// Capture and instantiate the sweep graph for the current plan if there is
+// none (plan changes drop it), without launching it.
+static int ensure_graph(bpmf_ctx *c)
+{
+    if (c->graph) return BPMF_OK;
+    hipGraph_t g = nullptr;
+    HIPCK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = enqueue_sweep(c, c->stream);
+    hipError_t e2 = hipStreamEndCapture(c->stream, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (g) hipGraphDestroy(g);
+        return fail(c, BPMF_E_DEVICE, "graph capture failed: %s / %s", hipGetErrorString(e),
+                    hipGetErrorString(e2));
+    }
+    e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        hipGraphDestroy(g);
+        c->graph = nullptr;
+        return fail(c, BPMF_E_DEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
+    }
+    c->graph_src = g;
+    return find_timing_nodes(c);
 }
 
 int bpmf_set_plan(bpmf_ctx *c, int32_t split_threshold, int32_t fast_kmax, int32_t lowrank_dmax)
@@ -853,7 +880,8 @@ int bpmf_set_plan(bpmf_ctx *c, int32_t split_threshold, int32_t fast_kmax, int32
     if (lowrank_dmax && !lowrank_available(c))
         return fail(c, BPMF_E_INVAL, "the rank-one path needs FP32 factors and K <= 64");
     if (int rc = replan(c, split_threshold, fast_kmax, lowrank_dmax, true)) return rc;
-    return refresh_lowrank(c);
+    if (int rc = refresh_lowrank(c)) return rc;
+    return ensure_graph(c);  // so that the next timed sweeps do not include the capture
 }
 
 int bpmf_run_sweeps(bpmf_ctx *c, uint32_t t0, uint32_t n, double *rmse_avg, double *rmse_last)
@@ -877,25 +905,7 @@ int bpmf_run_sweeps(bpmf_ctx *c, uint32_t t0, uint32_t n, double *rmse_avg, doub
             c->graph_src = nullptr;
         }
     }
-    if (!c->graph) {
-        hipGraph_t g = nullptr;
-        HIPCK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-        hipError_t e = enqueue_sweep(c, c->stream);
-        hipError_t e2 = hipStreamEndCapture(c->stream, &g);
-        if (e != hipSuccess || e2 != hipSuccess) {
-            if (g) hipGraphDestroy(g);
-            return fail(c, BPMF_E_DEVICE, "graph capture failed: %s / %s", hipGetErrorString(e),
-                        hipGetErrorString(e2));
-        }
-        e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
-        if (e != hipSuccess) {
-            hipGraphDestroy(g);
-            c->graph = nullptr;
-            return fail(c, BPMF_E_DEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
-        }
-        c->graph_src = g;
-        if (int r = find_timing_nodes(c)) return r;
-    }
+    if (int r = ensure_graph(c)) return r;
     // one set of four timing events per replay (replays past kTimedSweeps
     // share the last set, so the mean covers the first kTimedSweeps - 1 and
     // the final one)
