@@ -910,10 +910,17 @@ int bpmf_run_sweeps(bpmf_ctx *c, uint32_t t0, uint32_t n, double *rmse_avg, doub
     // share the last set, so the mean covers the first kTimedSweeps - 1 and
     // the final one)
     const uint32_t n_sets = c->timing_nodes ? std::min<uint32_t>(n, kTimedSweeps) : 0;
-    while (c->tpool.size() < 4 * (size_t)n_sets) {
-        hipEvent_t ev = nullptr;
-        HIPCK(c, hipEventCreate(&ev));
-        c->tpool.push_back(ev);
+    if (c->tpool.size() < 4 * (size_t)n_sets) {
+        // new events are recorded once before their first use in the graph:
+        // an event's first record sets it up, which would otherwise happen
+        // inside the timed replays
+        while (c->tpool.size() < 4 * (size_t)n_sets) {
+            hipEvent_t ev = nullptr;
+            HIPCK(c, hipEventCreate(&ev));
+            HIPCK(c, hipEventRecord(ev, c->stream));
+            c->tpool.push_back(ev);
+        }
+        HIPCK(c, hipStreamSynchronize(c->stream));
     }
     c->row_ms[0] = c->row_ms[1] = -1.0;
     HIPCK(c, hipEventRecord(c->ev0, c->stream));
