@@ -184,38 +184,49 @@ __global__ __launch_bounds__(256) void hyper_reduce(int E, int nblk, const doubl
     if (lane == 0) stats[e] = s;
 }
 
-// In-place Cholesky of a packed lower K x K matrix by the whole workgroup.
-// Clears *ok on a non-positive pivot.
+// In-place Cholesky of a packed lower K x K matrix (K <= 128) by the whole
+// workgroup, right-looking with the column scaling deferred so that each
+// pivot costs one barrier: step k subtracts P[i][k] P[j][k] / P[k][k] from
+// the trailing entries (i >= j > k), reading column k unscaled; at the end
+// column k is divided by sqrt(P[k][k]) and the pivot replaced by the root.
+// Clears *ok on a non-positive pivot (which is then taken as 1).
 __device__ void chol_packed(int K, double *P, int *ok)
 {
+    __shared__ double root[128];
     const int tid = threadIdx.x;
     for (int k = 0; k < K; ++k) {
-        if (tid == 0) {
-            double d = P[pk(k, k)];
-            if (!(d > 0.0)) {
-                *ok = 0;
-                d = 1.0;
-            }
-            P[pk(k, k)] = sqrt(d);
-        }
-        __syncthreads();
-        const double dk = P[pk(k, k)];
-        for (int i = k + 1 + tid; i < K; i += kThreads) P[pk(i, k)] /= dk;
-        __syncthreads();
+        double d = P[pk(k, k)];
+        if (!(d > 0.0)) d = 1.0;
+        const double rd = 1.0 / d;
         const int m = K - k - 1;
         const int n = m * (m + 1) / 2;
         for (int q = tid; q < n; q += kThreads) {
             int ii, jj;
             tri_index(q, ii, jj);
             const int i = k + 1 + ii, j = k + 1 + jj;
-            P[pk(i, j)] -= P[pk(i, k)] * P[pk(j, k)];
+            P[pk(i, j)] -= P[pk(i, k)] * P[pk(j, k)] * rd;
         }
         __syncthreads();
     }
+    for (int k = tid; k < K; k += kThreads) {
+        const double d = P[pk(k, k)];
+        if (!(d > 0.0)) *ok = 0;
+        root[k] = sqrt(d > 0.0 ? d : 1.0);
+    }
+    __syncthreads();
+    const int KK2 = K * (K + 1) / 2;
+    for (int e = tid; e < KK2; e += kThreads) {
+        int i, j;
+        tri_index(e, i, j);
+        P[e] = i == j ? root[j] : P[e] / root[j];
+    }
+    __syncthreads();
 }
 
-// X = C^-1 for a packed lower C (X packed lower, distinct storage):
-// forward substitution on the identity, one pivot row per step.
+// X = C^-1 for a packed lower C (X packed lower, distinct storage): forward
+// substitution on the identity with the row scaling deferred (one barrier
+// per pivot row): step k subtracts C[i][k] X[k][j] / C[k][k] from the rows
+// i > k, X[k] still unscaled; every row i is divided by C[i][i] at the end.
 __device__ void tri_inverse_packed(int K, const double *C, double *Xp)
 {
     const int tid = threadIdx.x;
@@ -226,18 +237,22 @@ __device__ void tri_inverse_packed(int K, const double *C, double *Xp)
         Xp[e] = i == j ? 1.0 : 0.0;
     }
     __syncthreads();
-    for (int k = 0; k < K; ++k) {
-        const double inv = 1.0 / C[pk(k, k)];
-        for (int j = tid; j <= k; j += kThreads) Xp[pk(k, j)] *= inv;  // row k final
-        __syncthreads();
-        // rows i > k: X[i][j] -= C[i][k] X[k][j], j <= k
+    for (int k = 0; k < K - 1; ++k) {
+        const double rck = 1.0 / C[pk(k, k)];
+        // rows i > k: X[i][j] -= C[i][k] X[k][j] / C[k][k], j <= k
         const int rows = K - k - 1, cols = k + 1;
         for (int q = tid; q < rows * cols; q += kThreads) {
             const int i = k + 1 + q / cols, j = q - (q / cols) * cols;
-            Xp[pk(i, j)] -= C[pk(i, k)] * Xp[pk(k, j)];
+            Xp[pk(i, j)] -= C[pk(i, k)] * Xp[pk(k, j)] * rck;
         }
         __syncthreads();
     }
+    for (int e = tid; e < KK2; e += kThreads) {
+        int i, j;
+        tri_index(e, i, j);
+        Xp[e] /= C[pk(i, i)];
+    }
+    __syncthreads();
 }
 
 template <typename T>
@@ -324,14 +339,16 @@ __global__ __launch_bounds__(kThreads) void hyper_draw(
         for (int l = 0; l < 4 && 4 * blk + l < K; ++l) zv[4 * blk + l] = z[l];
     }
     __syncthreads();
-    // x = B^-T z (column oriented), in zv
-    for (int i = K - 1; i >= 0; --i) {
-        if (tid == 0) zv[i] /= Bm[pk(i, i)];
-        __syncthreads();
-        const double xi = zv[i];
+    // x = B^-T z (column oriented, one barrier per step), in zv: step i
+    // takes x_i = zv[i] / B[i][i] (zv[i] final) and updates zv[j], j < i;
+    // the divisions are applied to zv at the end
+    for (int i = K - 1; i > 0; --i) {
+        const double xi = zv[i] / Bm[pk(i, i)];
         for (int j = tid; j < i; j += kThreads) zv[j] -= Bm[pk(i, j)] * xi;
         __syncthreads();
     }
+    for (int i = tid; i < K; i += kThreads) zv[i] /= Bm[pk(i, i)];
+    __syncthreads();
     const double rs = 1.0 / sqrt(beta_s);
     for (int k = tid; k < K; k += kThreads) {
         mu[k] = mus[k] + zv[k] * rs;
