@@ -278,6 +278,36 @@ def test_chain_planted_c1_matches_oracle(bp, orc, prec):
     s.close()
 
 
+@pytest.mark.parametrize("K,prec,plan", [(48, "fp32", (128, 32, 0)), (16, "fp32", (128, 32, 8)),
+                                         (32, "bf16", (128, 32, 0))])
+def test_graph_branches_equal_eager(bp, K, prec, plan):
+    """The sweep graph runs a side's whole rows (blocked kernel, rank-one
+    path) on a branch beside its split-row segments and finishing; the chain
+    equals eager stage-by-stage calls bit for bit."""
+    r = synth.random_small(11, 3000, 150, 24000, 10, empty_rows=20)
+    a = bp.Sampler(r, K, prec=prec, seed=5)
+    b = bp.Sampler(r, K, prec=prec, seed=5)
+    for s in (a, b):
+        if prec == "fp32":
+            s.set_plan(*plan)
+        else:
+            s.set_plan(plan[0], plan[1], 0)
+    if plan[2]:
+        assert a.lowrank_rows(bp.SIDE_U) > 100
+    _, last = a.run_sweeps(1, 3)
+    for t in (1, 2, 3):
+        b.sample_hyper(bp.SIDE_V, t)
+        b.update_side(bp.SIDE_V, t)
+        b.sample_hyper(bp.SIDE_U, t)
+        b.update_side(bp.SIDE_U, t)
+        _, el = b.predict_test(t)
+    assert np.array_equal(a.get_factor(bp.SIDE_U), b.get_factor(bp.SIDE_U))
+    assert np.array_equal(a.get_factor(bp.SIDE_V), b.get_factor(bp.SIDE_V))
+    assert last[-1] == el
+    a.close()
+    b.close()
+
+
 def test_graph_replay_equals_eager(bp):
     r = synth.random_small(8, 500, 250, 9000, 8)
     a = bp.Sampler(r, 8, prec="fp32", seed=5)
