@@ -408,7 +408,7 @@ def k100_compare(steps, seed, autotune=True, with_peaks=True):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="movielens", choices=sorted(WORKLOADS))
     ap.add_argument("--prec", default=None, choices=["fp64", "fp32", "bf16"])
