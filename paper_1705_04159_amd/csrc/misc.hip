@@ -228,8 +228,8 @@ hipError_t launch_predict_test(bpmf_ctx *c, hipStream_t s)
                            c->n_test, c->test_row, c->test_col, c->test_val,
                            (const float *)c->side[0].X, (const float *)c->side[1].X, c->rbar,
                            c->pred_sum, c->ctr, c->burn_in, c->rmse_part);
-    else
-        hipLaunchKernelGGL((predict_test<float, 16>), dim3(nblk), dim3(256), 0, s, c->K, c->ld,
+    else  // eight lanes per pair, several float4 steps each
+        hipLaunchKernelGGL((predict_test<float, 8>), dim3(nblk), dim3(256), 0, s, c->K, c->ld,
                            c->n_test, c->test_row, c->test_col, c->test_val,
                            (const float *)c->side[0].X, (const float *)c->side[1].X, c->rbar,
                            c->pred_sum, c->ctr, c->burn_in, c->rmse_part);
