@@ -500,7 +500,7 @@ hipError_t launch_row_fast(bpmf_ctx *c, int side_id, hipStream_t s, int stage, b
         const int64_t e = sd.n_items - sd.n_low;
         switch (nb) {
         case 1: return launch_f32<1, 4, 4>(c, sd, ot, s, 0, e);
-        case 2: return launch_f32<2, 2, 4>(c, sd, ot, s, 0, e);
+        case 2: return launch_f32<2, 2, 1>(c, sd, ot, s, 0, e);  // one-wave blocks: measured best
         case 3: return launch_f32<3, 1, 2>(c, sd, ot, s, 0, e);
         default: return launch_f32<4, 1, 2>(c, sd, ot, s, 0, e);
         }
