@@ -38,7 +38,7 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kBigWPB = 2;     // waves per workgroup (independent)
+constexpr int kBigWPB = 1;     // waves per workgroup (independent; one-wave groups measured best)
 constexpr int kPS = 17;        // panel row stride (floats)
 
 // Waves per SIMD the register allocation must allow (left alone, the
