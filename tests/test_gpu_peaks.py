@@ -9,10 +9,6 @@ pytestmark = pytest.mark.gpu
 
 @pytest.fixture(scope="module")
 def bp():
-    import torch
-
-    if not torch.cuda.is_available():
-        pytest.skip("no GPU")
     import paper_1705_04159_amd as bp
 
     return bp
