@@ -187,7 +187,7 @@ int bpmf_last_time_ms(bpmf_ctx *c, double *ms);
  *   - for FP32 with 32 < K <= 64, whether rows take the column-per-lane
  *     (kmax 64) or the blocked (kmax 32) kernel;
  *   - for FP32 with K <= 64, the degree up to which rows take the rank-one
- *     update path (0 = off, 4, 8; a side uses it only where the saved
+ *     update path (0 = off, 8, 16; a side uses it only where the saved
  *     factorisations outweigh transforming the gathered factor).
  * A candidate replaces the current plan only if it is at least 2% faster.
  * The chain state (factors, hyperparameters, running predictions, sweep
@@ -204,8 +204,8 @@ int bpmf_autotune(bpmf_ctx *c, uint32_t n_sweeps, int32_t *chosen_split, int32_t
  * (1..2^24; rows with more ratings are cut into segments of
  * max(128, split_threshold / 2)), fast_kmax (0..64; FP32 factors with
  * K <= fast_kmax take the column-per-lane kernel, larger K the blocked one)
- * and lowrank_dmax (0, 4 or 8; with FP32 factors and K <= 64 every row with
- * at most that many ratings takes the rank-one update path -- unlike the
+ * and lowrank_dmax (0, 4, 8 or 16; with FP32 factors and K <= 64 every row
+ * with at most that many ratings takes the rank-one update path -- unlike the
  * autotuner, without weighing the transform of the gathered factor).  The
  * work items, finishing items and partial-sum workspace are rebuilt and the
  * sweep graph is re-captured (not launched) before returning; the chain

@@ -75,6 +75,7 @@ struct Side {
     // work items; L_Lam^-1 and L_Lam^T mu from the hyper draw, and the
     // gathered factor premultiplied by L_Lam^-1
     int64_t n_low = 0;
+    int64_t n_low_small = 0;  // the last of those with at most 8 ratings
     void *Linv_w = nullptr;   // device [K * K] FP32
     void *Ltmu_w = nullptr;   // device [K] FP32
     float *Yt = nullptr;      // device [other rows * ld]

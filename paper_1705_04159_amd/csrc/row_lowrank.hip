@@ -261,8 +261,11 @@ __global__ __launch_bounds__(64 * kLowWPB) void row_lowrank(
 // The low-rank path: FP32 factors, K <= 64.
 bool lowrank_available(const bpmf_ctx *c) { return c->prec == 1 && c->K <= 64; }
 
-// Stage 0 of a side with low-rank rows: transform the gathered factor, then
-// the rows [n_items - n_low, n_items).
+// The rows stage of a side with low-rank rows: transform the gathered
+// factor, then the rows [n_items - n_low, n_items).  With a cut-off above 8
+// the rows with 9..16 ratings (first in the suffix: degrees descend) take a
+// 16-factor instance and the rest the 8-factor one, so that the larger
+// register footprint costs only the rows that need it.
 hipError_t launch_row_lowrank(bpmf_ctx *c, int side_id, hipStream_t s)
 {
     Side &sd = c->side[side_id];
@@ -270,32 +273,41 @@ hipError_t launch_row_lowrank(bpmf_ctx *c, int side_id, hipStream_t s)
     if (sd.n_low == 0) return hipSuccess;
     const int nb = (c->K + 15) / 16;
     const int64_t item0 = sd.n_items - sd.n_low;
-    auto go = [&](auto cc, auto dc) {
-        constexpr int C = decltype(cc)::value, D = decltype(dc)::value;
+    const int64_t item_small = sd.n_items - sd.n_low_small;
+    auto go = [&](auto cc) {
+        constexpr int C = decltype(cc)::value;
         constexpr int KP = 16 * C;
         const int64_t tot = ot.rows * (int64_t)KP;
         hipLaunchKernelGGL((transform_rows<KP>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
                            c->K, (const float *)ot.X, c->ld, ot.rows, (const float *)sd.Linv_w, sd.Yt);
-        const int64_t per_block = 4 * kLowWPB;
-        const unsigned grid = (unsigned)((sd.n_low + per_block - 1) / per_block);
-        hipLaunchKernelGGL((row_lowrank<C, D>), dim3(grid), dim3(64 * kLowWPB), 0, s, c->K,
-                           (float)c->alpha, sd.items, item0, sd.n_items, sd.nbr, (const float *)sd.rc,
-                           (const float *)sd.Yt, c->ld, (const float *)sd.Linv_w,
-                           (const float *)sd.Ltmu_w, (float *)sd.X, c->ld, c->seed, sd.stream_row,
-                           c->ctr);
+        auto rows = [&](auto dc, int64_t beg, int64_t end) {
+            constexpr int D = decltype(dc)::value;
+            if (end <= beg) return;
+            const int64_t per_block = 4 * kLowWPB;
+            const unsigned grid = (unsigned)((end - beg + per_block - 1) / per_block);
+            hipLaunchKernelGGL((row_lowrank<C, D>), dim3(grid), dim3(64 * kLowWPB), 0, s, c->K,
+                               (float)c->alpha, sd.items, beg, end, sd.nbr, (const float *)sd.rc,
+                               (const float *)sd.Yt, c->ld, (const float *)sd.Linv_w,
+                               (const float *)sd.Ltmu_w, (float *)sd.X, c->ld, c->seed, sd.stream_row,
+                               c->ctr);
+        };
+        using D4 = std::integral_constant<int, 4>;
+        using D8 = std::integral_constant<int, 8>;
+        using D16 = std::integral_constant<int, 16>;
+        if (c->low_dmax > 8) {
+            rows(D16{}, item0, item_small);
+            rows(D8{}, item_small, sd.n_items);
+        } else if (c->low_dmax > 4) {
+            rows(D8{}, item0, sd.n_items);
+        } else {
+            rows(D4{}, item0, sd.n_items);
+        }
     };
-    using I1 = std::integral_constant<int, 1>;
-    using I2 = std::integral_constant<int, 2>;
-    using I3 = std::integral_constant<int, 3>;
-    using I4 = std::integral_constant<int, 4>;
-    using D4 = std::integral_constant<int, 4>;
-    using D8 = std::integral_constant<int, 8>;
-    const bool d8 = c->low_dmax > 4;
     switch (nb) {
-    case 1: d8 ? go(I1{}, D8{}) : go(I1{}, D4{}); break;
-    case 2: d8 ? go(I2{}, D8{}) : go(I2{}, D4{}); break;
-    case 3: d8 ? go(I3{}, D8{}) : go(I3{}, D4{}); break;
-    default: d8 ? go(I4{}, D8{}) : go(I4{}, D4{}); break;
+    case 1: go(std::integral_constant<int, 1>{}); break;
+    case 2: go(std::integral_constant<int, 2>{}); break;
+    case 3: go(std::integral_constant<int, 3>{}); break;
+    default: go(std::integral_constant<int, 4>{}); break;
     }
     return hipGetLastError();
 }

@@ -112,7 +112,8 @@ bool spd_inverse_host(int K, const std::vector<double> &A, std::vector<double> &
 // `seg` ratings whose partial sums land in consecutive slots.
 void plan_side(const std::vector<int64_t> &ptr, int64_t rows, int64_t split, int64_t seg,
                std::vector<int32_t> &perm, int64_t &n_split, std::vector<RowItem> &items,
-               std::vector<FinishItem> &fin, int64_t &n_slots, int64_t low_dmax, int64_t &n_low)
+               std::vector<FinishItem> &fin, int64_t &n_slots, int64_t low_dmax, int64_t &n_low,
+               int64_t &n_low_small)
 {
     perm.resize(rows);
     std::iota(perm.begin(), perm.end(), 0);
@@ -135,11 +136,13 @@ void plan_side(const std::vector<int64_t> &ptr, int64_t rows, int64_t split, int
         }
         fin.push_back(f);
     }
-    n_low = 0;
+    n_low = n_low_small = 0;
     for (int64_t q = n_split; q < rows; ++q) {
         int32_t r = perm[q];
         items.push_back(RowItem{r, -1, ptr[r], ptr[r + 1]});
-        if (ptr[r + 1] - ptr[r] <= low_dmax) ++n_low;  // a suffix: degrees descend
+        const int64_t d = ptr[r + 1] - ptr[r];
+        if (d <= low_dmax) ++n_low;  // a suffix: degrees descend
+        if (d <= std::min<int64_t>(low_dmax, 8)) ++n_low_small;
     }
 }
 
@@ -474,11 +477,12 @@ int bpmf_create(int64_t M, int64_t N, const int64_t *csr_ptr, const int32_t *csr
             sd.hptr = *ptrs[sid];
             std::vector<RowItem> items;
             std::vector<FinishItem> fin;
-            int64_t n_low = 0;
+            int64_t n_low = 0, n_low_small = 0;
             plan_side(*ptrs[sid], sd.rows, c->split_threshold,
                       std::max<int64_t>(128, c->split_threshold / 2), sd.perm, sd.n_split, items,
-                      fin, sd.n_slots, c->low_dmax, n_low);
+                      fin, sd.n_slots, c->low_dmax, n_low, n_low_small);
             sd.n_low = low_rows_used(c, n_low, sid == 0 ? N : M);
+            sd.n_low_small = sd.n_low ? n_low_small : 0;
             if (sd.n_low) CK(alloc_lowrank(c, sd, sid == 0 ? N : M));
             sd.n_items = (int64_t)items.size();
             sd.n_fin = (int64_t)fin.size();
@@ -679,11 +683,12 @@ static int replan(bpmf_ctx *c, int split, int fast_kmax, int low_dmax, bool forc
         Side &sd = c->side[sid];
         std::vector<RowItem> items;
         std::vector<FinishItem> fin;
-        int64_t n_low = 0;
+        int64_t n_low = 0, n_low_small = 0;
         plan_side(sd.hptr, sd.rows, split, std::max<int64_t>(128, split / 2), sd.perm, sd.n_split,
-                  items, fin, sd.n_slots, low_dmax, n_low);
+                  items, fin, sd.n_slots, low_dmax, n_low, n_low_small);
         const int64_t other = c->side[1 - sid].rows;
         sd.n_low = force_low && lowrank_available(c) ? n_low : low_rows_used(c, n_low, other);
+        sd.n_low_small = sd.n_low ? n_low_small : 0;
         if (sd.n_low) HIPCK(c, alloc_lowrank(c, sd, other));
         (void)hipFree(sd.items);
         (void)hipFree(sd.fin);
@@ -792,7 +797,7 @@ int bpmf_autotune(bpmf_ctx *c, uint32_t n_sweeps, int32_t *chosen_split, int32_t
     std::vector<int> kmaxes = {c->fast_kmax};
     if (c->prec == BPMF_FP32 && c->K > 32 && c->K <= 64) kmaxes = {32, 64};
     std::vector<int> lows = {c->low_dmax};
-    if (lowrank_available(c)) lows = {0, 4, 8};
+    if (lowrank_available(c)) lows = {0, 8, 16};
     const int old_split = c->split_threshold, old_kmax = c->fast_kmax, old_low = c->low_dmax;
     ChainSnapshot sn;
     if (int r = snapshot_take(c, sn)) {
@@ -875,8 +880,8 @@ int bpmf_set_plan(bpmf_ctx *c, int32_t split_threshold, int32_t fast_kmax, int32
     if (split_threshold < 1 || split_threshold > (1 << 24))
         return fail(c, BPMF_E_INVAL, "split_threshold must be 1..2^24");
     if (fast_kmax < 0 || fast_kmax > 64) return fail(c, BPMF_E_INVAL, "fast_kmax must be 0..64");
-    if (lowrank_dmax != 0 && lowrank_dmax != 4 && lowrank_dmax != 8)
-        return fail(c, BPMF_E_INVAL, "lowrank_dmax must be 0, 4 or 8");
+    if (lowrank_dmax != 0 && lowrank_dmax != 4 && lowrank_dmax != 8 && lowrank_dmax != 16)
+        return fail(c, BPMF_E_INVAL, "lowrank_dmax must be 0, 4, 8 or 16");
     if (lowrank_dmax && !lowrank_available(c))
         return fail(c, BPMF_E_INVAL, "the rank-one path needs FP32 factors and K <= 64");
     if (int rc = replan(c, split_threshold, fast_kmax, lowrank_dmax, true)) return rc;

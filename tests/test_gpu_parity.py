@@ -279,7 +279,7 @@ def test_chain_planted_c1_matches_oracle(bp, orc, prec):
 
 
 @pytest.mark.parametrize("K,prec,plan", [(48, "fp32", (128, 32, 0)), (16, "fp32", (128, 32, 8)),
-                                         (32, "bf16", (128, 32, 0))])
+                                         (40, "fp32", (128, 32, 16)), (32, "bf16", (128, 32, 0))])
 def test_graph_branches_equal_eager(bp, K, prec, plan):
     """The sweep graph runs a side's whole rows (blocked kernel, rank-one
     path) on a branch beside its split-row segments and finishing; the chain
@@ -389,7 +389,7 @@ def test_autotune_keeps_the_chain(bp, K):
     assert len(tried) >= 2 and all(ms > 0 for _, _, _, ms in tried)
     assert (split, kmax, low) in [(s, k, l) for s, k, l, _ in tried]
     assert {k for _, k, _, _ in tried} == ({32, 64} if K == 48 else {32})
-    assert {l for _, _, l, _ in tried} == {0, 4, 8}
+    assert {l for _, _, l, _ in tried} == {0, 8, 16}
     for side in (bp.SIDE_U, bp.SIDE_V):
         assert np.array_equal(a.get_factor(side), b.get_factor(side))
         ma, la = a.get_hyper(side)
@@ -403,15 +403,18 @@ def test_autotune_keeps_the_chain(bp, K):
 
 
 @pytest.mark.parametrize("K,plan", [(16, (128, 32, 8)), (32, (128, 0, 0)), (32, (1 << 24, 32, 4)),
-                                    (48, (256, 64, 8))])
+                                    (48, (256, 64, 8)), (32, (128, 32, 16)), (64, (1 << 24, 32, 16))])
 def test_set_plan_single_step(bp, orc, K, plan):
     """A plan fixed by hand (split threshold 128: movies with 129-207
     ratings in two segments; the blocked kernel at K = 32, the
     column-per-lane kernel at K = 48, the rank-one path forced for every user
-    with at most 4 or 8 ratings) gives the oracle's draws on both sides."""
+    with at most 4, 8 or 16 ratings -- at 16 the users with 9..16 ratings on
+    the 16-factor instance, the rest on the 8-factor one) gives the oracle's
+    draws on both sides."""
     r = synth.random_small(11, 3000, 150, 24000, 10, empty_rows=20)
     deg_u, deg_v = np.diff(r.csr_ptr), np.bincount(r.csr_col, minlength=r.N)
     assert (deg_v > 128).sum() > 50 and (deg_u <= 4).sum() > 100 and (deg_u == 0).any()
+    assert ((deg_u > 8) & (deg_u <= 16)).sum() > 100
     s = bp.Sampler(r, K, prec="fp32", seed=1)
     s.set_plan(*plan)
     if plan[2]:
