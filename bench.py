@@ -141,7 +141,7 @@ def sweep_roofline(K, prec, r, ms_per_step, peaks):
 FIG2_DEGREES = (1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096, 8192)
 # kernel family: (split threshold, fast_kmax, rank-one cut-off, applies to degree d)
 FIG2_VARIANTS = {
-    "rank-one (VALU)": (1 << 24, 32, 8, lambda d: d <= 8),
+    "rank-one (VALU)": (1 << 24, 32, 16, lambda d: d <= 16),
     "MFMA, column-per-lane factorisation": (1 << 24, 32, 0, lambda d: True),
     "MFMA, blocked factorisation": (1 << 24, 0, 0, lambda d: True),
     "split into segments of 128": (128, 32, 0, lambda d: d > 128),
