@@ -168,16 +168,24 @@ hipError_t alloc_lowrank(bpmf_ctx *c, Side &sd, int64_t other_rows)
 
 size_t elem_bytes(const bpmf_ctx *c) { return c->prec == 0 ? sizeof(double) : sizeof(float); }
 
-// One stage of a side's row update (see UpdateStage).
-hipError_t enqueue_update_stage(bpmf_ctx *c, int side_id, hipStream_t s, int stage)
+// One stage of a side's row update (see UpdateStage), without the rank-one
+// rows of the whole-rows stage.
+static hipError_t enqueue_stage_kernels(bpmf_ctx *c, int side_id, hipStream_t s, int stage)
 {
-    if (stage == kStageShadow) return c->prec == 2 ? launch_to_bf16(c, side_id, s) : hipSuccess;
     bool handled = false;
     hipError_t e = launch_row_fast(c, side_id, s, stage, &handled);
     if (e != hipSuccess) return e;
     if (!handled) e = launch_row_big(c, side_id, s, stage, &handled);
     if (e != hipSuccess) return e;
     if (!handled) e = launch_row_generic(c, side_id, s, stage);
+    return e;
+}
+
+// One stage of a side's row update (see UpdateStage).
+hipError_t enqueue_update_stage(bpmf_ctx *c, int side_id, hipStream_t s, int stage)
+{
+    if (stage == kStageShadow) return c->prec == 2 ? launch_to_bf16(c, side_id, s) : hipSuccess;
+    hipError_t e = enqueue_stage_kernels(c, side_id, s, stage);
     if (e != hipSuccess) return e;
     if (stage == kStageRows && c->side[side_id].n_low) e = launch_row_lowrank(c, side_id, s);
     return e;
@@ -222,10 +230,10 @@ hipError_t enqueue_sweep_profiled(bpmf_ctx *c, hipStream_t s, hipEvent_t *ev)
 // overlaps on a second stream: the U draw of sweep t needs only U of sweep
 // t-1, so it runs beside the V update; the V draw of sweep t+1 needs only V
 // of sweep t, so it runs beside the U update.  The sweep ends by advancing t.
-// Row update of one side inside the captured sweep: the whole rows on a
-// branch of their own beside the segments and finishing of the split rows,
-// with external event records around the update (all but the BF16 shadow)
-// for timing.
+// Row update of one side inside the captured sweep: the rank-one rows (or,
+// without them, the factorisation kernels' whole rows) on a branch of their
+// own beside the segments and finishing of the split rows, with external
+// event records around the update (all but the BF16 shadow) for timing.
 // Whether the whole-rows stage launches anything of its own (the rank-one
 // path, or the blocked kernel's whole rows); without it the update stays on
 // one branch (a fork and join cost more than they hide).
@@ -249,9 +257,18 @@ hipError_t enqueue_update_timed(bpmf_ctx *c, int side_id, hipStream_t s, hipEven
     if ((e = enqueue_update_stage(c, side_id, s, kStagePrior)) != hipSuccess) return e;
     if ((e = hipEventRecord(c->stage_ev[0], s)) != hipSuccess) return e;
     if ((e = hipStreamWaitEvent(s3, c->stage_ev[0], 0)) != hipSuccess) return e;
-    if ((e = enqueue_update_stage(c, side_id, s3, kStageRows)) != hipSuccess) return e;
+    // With rank-one rows the branch takes only those (the longest part), and
+    // the factorisation kernels' whole rows follow the segments; otherwise
+    // the branch takes the whole rows.
+    const bool low = c->side[side_id].n_low > 0;
+    if (low) {
+        if ((e = launch_row_lowrank(c, side_id, s3)) != hipSuccess) return e;
+    } else if ((e = enqueue_stage_kernels(c, side_id, s3, kStageRows)) != hipSuccess) {
+        return e;
+    }
     if ((e = hipEventRecord(c->stage_ev[1], s3)) != hipSuccess) return e;
     if ((e = enqueue_update_stages(c, side_id, s, kStageSegments, kStageSegments)) != hipSuccess) return e;
+    if (low && (e = enqueue_stage_kernels(c, side_id, s, kStageRows)) != hipSuccess) return e;
     if ((e = enqueue_update_stage(c, side_id, s, kStageFinish)) != hipSuccess) return e;
     if ((e = hipStreamWaitEvent(s, c->stage_ev[1], 0)) != hipSuccess) return e;
     if ((e = hipEventRecordWithFlags(b, s, hipEventRecordExternal)) != hipSuccess) return e;
