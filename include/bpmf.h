@@ -26,7 +26,8 @@
  *   - Matrices are row-major.  Factors are rows x K.  Ratings are CSR with
  *     int64 row offsets, int32 column ids strictly increasing within a row
  *     and float32 values.
- *   - A context owns all device memory (hipMalloc) and one HIP stream; it is
+ *   - A context owns all device memory (hipMalloc) and its HIP streams (the
+ *     Gibbs calls go to params.stream when the caller gives one); it is
  *     bound to the device that was current at bpmf_create.
  *   - Gibbs calls on one context must not run concurrently.
  *   - Every call returns BPMF_OK (0) or a negative status; on failure the
@@ -60,7 +61,10 @@ enum {
     BPMF_E_BUSY = -6,      /* fold-in queue full; retry later */
     BPMF_E_TOOBIG = -7,    /* fold-in request larger than the memory pool */
     BPMF_E_NOSAMPLES = -8, /* fold-in before any bpmf_store_sample */
-    BPMF_E_NOTFOUND = -9   /* unknown fold-in request id */
+    BPMF_E_NOTFOUND = -9,  /* unknown fold-in request id */
+    BPMF_E_NOTSPD = -10    /* a precision matrix was not positive definite in working precision
+                              (row draw or hyper draw); not sticky, but the rows or
+                              hyperparameters drawn by that call are undefined */
 };
 
 /* Sides of the factorisation: U holds the M users, V the N movies. */
@@ -91,6 +95,10 @@ typedef struct bpmf_params {
     int32_t split_threshold; /* rows with more ratings are split across wavefronts (0: library
                                 default, 2048 for K <= 64 and 8192 above) */
     uint64_t foldin_pool_bytes; /* fold-in device memory budget (0: 256 MiB) */
+    void *stream;         /* hipStream_t the Gibbs calls are queued on (NULL: the context
+                             creates its own); a caller's stream is borrowed, never destroyed,
+                             and must outlive the context; it must not be the legacy null
+                             stream (the sweep graph is captured on it) */
 } bpmf_params;
 
 /* Fill *p with the defaults above for latent dimension K. */
@@ -119,7 +127,9 @@ int bpmf_sample_hyper(bpmf_ctx *c, int32_t side, uint32_t t);
 
 /* Algorithm 1, the item loop of one side for sweep t: every row of the side
  * is redrawn from its conditional given the other factor and the side's
- * current hyperparameters (row noise stream 1 for U, 2 for V). */
+ * current hyperparameters (row noise stream 1 for U, 2 for V).
+ * BPMF_E_NOTSPD if some row's P = Lambda + alpha sum y y^T had a
+ * non-positive pivot in working precision (those rows are undefined). */
 int bpmf_update_side(bpmf_ctx *c, int32_t side, uint32_t t);
 
 /* Algorithm 1 for sweeps t0 .. t0+n-1 (each: hyper V, update V, hyper U,
@@ -138,7 +148,9 @@ int bpmf_profile_sweeps(bpmf_ctx *c, uint32_t t0, uint32_t n, double *phase_ms);
 
 /* Algorithm 1, "predict rating and compute RMSE".  n == 0: predict the
  * registered test set with the current factors, fold the prediction into the
- * running mean as sweep t (if t > burn_in), and return the two RMSEs.
+ * running mean as sweep t (if t > burn_in), and return the two RMSEs (t is
+ * explicit here, as on every call that depends on the sweep index, so that
+ * an eager sequence of calls reproduces bpmf_run_sweeps exactly).
  * n > 0: predict the n given (row, col) pairs into out[n] (float,
  * u_row . v_col + mean rating) without touching the running mean; the RMSE
  * pointers are then ignored. */
@@ -155,6 +167,16 @@ int bpmf_set_factor_f64(bpmf_ctx *c, int32_t side, const double *host);
 /* Hyperparameters of a side: mu (K) and Lambda (K x K), FP64. */
 int bpmf_get_hyper(bpmf_ctx *c, int32_t side, double *mu, double *Lambda);
 int bpmf_set_hyper(bpmf_ctx *c, int32_t side, const double *mu, const double *Lambda);
+
+/* Chain state beyond the factors and hyperparameters, for checkpoint and
+ * resume: the running sum of test predictions over the sweeps t > burn_in
+ * (pred_sum[n_test], FP64, in the order the test pairs were given to
+ * bpmf_create) and the number of sweeps in it (*n_avg).  Restoring it with
+ * the factors lets a resumed chain report the same RMSE of the running mean
+ * as an uninterrupted one (the next sweep index is passed explicitly to
+ * bpmf_run_sweeps).  Either pointer may be NULL on get. */
+int bpmf_get_chain_state(bpmf_ctx *c, double *pred_sum, uint32_t *n_avg);
+int bpmf_set_chain_state(bpmf_ctx *c, const double *pred_sum, uint32_t n_avg);
 
 /* The CSC the library uses (N+1 offsets, nnz row ids, nnz centred values as
  * stored: float, or double in FP64 mode, r - mean).  For verification. */
@@ -243,11 +265,11 @@ int bpmf_row_kernel_ms(bpmf_ctx *c, double *ms);
 
 /* Snapshot the current V and the user-side (mu_U, Lambda_U) into the next
  * slot of a device-resident ring of params.foldin_S samples (the oldest is
- * overwritten).  The first call allocates the ring and two batch slots and
- * starts the scheduler thread; params.foldin_pool_bytes (default 256 MiB)
- * bounds the rated movies in flight: each batch admits requests while their
- * ratings fit pool/16 (8 B per rating, two batches).  Blocks until in-flight fold-in
- * batches finished.  A Gibbs call: not concurrent with other Gibbs calls on
+ * overwritten).  The first call allocates the ring and four batch slots
+ * (each with its own stream) and starts the scheduler thread;
+ * params.foldin_pool_bytes (default 256 MiB) bounds the rated movies in
+ * flight: each batch admits requests while their ratings fit pool/32 (8 B
+ * per rating, four batches).  Blocks until in-flight fold-in batches finished.  A Gibbs call: not concurrent with other Gibbs calls on
  * c, and the first call must return before any bpmf_foldin_submit. */
 int bpmf_store_sample(bpmf_ctx *c);
 
@@ -257,9 +279,10 @@ int bpmf_store_sample(bpmf_ctx *c);
  * Thread-safe.  Errors: BPMF_E_NOSAMPLES before any stored sample,
  * BPMF_E_RANGE / BPMF_E_FORMAT for bad ids, duplicates or non-finite
  * ratings, BPMF_E_TOOBIG if n exceeds one batch's rating capacity,
- * BPMF_E_BUSY if 2^20 requests are pending.  Requests are batched as they
- * arrive (continuous batching on a separate stream); a request's result does
- * not depend on what it is batched with. */
+ * BPMF_E_BUSY if 2^20 requests are pending.  Requests are batched by size
+ * class as they arrive (continuous batching; up to four batches on the
+ * device at once, each on its own stream); a request's result does not
+ * depend on what it is batched with. */
 int bpmf_foldin_submit(bpmf_ctx *c, int32_t n, const int32_t *movie, const float *rating,
                        int32_t top_n, uint64_t *req_id);
 
@@ -273,6 +296,13 @@ int bpmf_foldin_poll(bpmf_ctx *c, uint64_t req_id, int32_t *movie_out, float *me
 
 /* Block until every submitted request has completed. */
 int bpmf_foldin_drain(bpmf_ctx *c);
+
+/* Scheduler statistics since the first bpmf_store_sample (any pointer may
+ * be NULL): batches launched, requests launched, the most requests in one
+ * batch, and the most batches on the device at the same time (each staging
+ * slot has its own stream, so batches overlap). */
+int bpmf_foldin_stats(bpmf_ctx *c, int64_t *batches, int64_t *requests, int32_t *max_batch_requests,
+                      int32_t *max_inflight_batches);
 
 /* Number of samples currently in the ring. */
 int bpmf_foldin_samples(const bpmf_ctx *c);

@@ -25,17 +25,18 @@ PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16_GRAM, "bf16_gram": BF16_G
 
 OK, PENDING = 0, 1
 E_INVAL, E_RANGE, E_FORMAT, E_NOMEM, E_DEVICE = -1, -2, -3, -4, -5
-E_BUSY, E_TOOBIG, E_NOSAMPLES, E_NOTFOUND = -6, -7, -8, -9
+E_BUSY, E_TOOBIG, E_NOSAMPLES, E_NOTFOUND, E_NOTSPD = -6, -7, -8, -9, -10
 
 # Every symbol the C ABI exports (include/bpmf.h).
 EXPORTS = [
     "bpmf_default_params", "bpmf_create", "bpmf_sample_hyper", "bpmf_update_side",
     "bpmf_run_sweeps", "bpmf_profile_sweeps", "bpmf_predict", "bpmf_get_factor", "bpmf_set_factor",
     "bpmf_get_factor_f64", "bpmf_set_factor_f64", "bpmf_get_hyper", "bpmf_set_hyper",
-    "bpmf_get_csc", "bpmf_get_plan", "bpmf_mean_rating", "bpmf_synchronize",
+    "bpmf_get_csc", "bpmf_get_chain_state", "bpmf_set_chain_state", "bpmf_get_plan",
+    "bpmf_mean_rating", "bpmf_synchronize",
     "bpmf_last_time_ms", "bpmf_row_kernel_ms", "bpmf_autotune", "bpmf_set_plan", "bpmf_last_error", "bpmf_destroy", "bpmf_store_sample",
     "bpmf_foldin_submit", "bpmf_foldin_poll", "bpmf_foldin_drain", "bpmf_foldin_samples",
-    "bpmf_foldin_capacity",
+    "bpmf_foldin_capacity", "bpmf_foldin_stats",
     # include/bpmf_peaks.h
     "bpmf_peak_triad", "bpmf_peak_compute", "bpmf_peak_gather",
 ]
@@ -64,6 +65,7 @@ class Params(ctypes.Structure):
         ("foldin_S", ctypes.c_int32),
         ("split_threshold", ctypes.c_int32),
         ("foldin_pool_bytes", ctypes.c_uint64),
+        ("stream", ctypes.c_void_p),
     ]
 
 
@@ -94,6 +96,8 @@ def lib() -> ctypes.CDLL:
         L.bpmf_get_hyper.argtypes = [P, i32, P, P]
         L.bpmf_set_hyper.argtypes = [P, i32, P, P]
         L.bpmf_get_csc.argtypes = [P, P, P, P]
+        L.bpmf_get_chain_state.argtypes = [P, P, P]
+        L.bpmf_set_chain_state.argtypes = [P, P, u32]
         L.bpmf_get_plan.argtypes = [P, i32, P, P, P]
         L.bpmf_mean_rating.argtypes = [P]
         L.bpmf_mean_rating.restype = dbl
@@ -113,6 +117,7 @@ def lib() -> ctypes.CDLL:
         L.bpmf_foldin_samples.argtypes = [P]
         L.bpmf_foldin_capacity.argtypes = [P]
         L.bpmf_foldin_capacity.restype = i64
+        L.bpmf_foldin_stats.argtypes = [P, P, P, P, P]
         L.bpmf_peak_triad.argtypes = [i64, i32, P]
         L.bpmf_peak_compute.argtypes = [i32, i32, P]
         L.bpmf_peak_gather.argtypes = [i64, i32, i64, i32, P]
@@ -164,7 +169,7 @@ class Sampler:
 
     def __init__(self, ratings, K, prec="fp32", alpha=2.0, beta0=2.0, nu0=None, mu0=None,
                  W0=None, seed=0, center=True, burn_in=0, split_threshold=0, csc=None,
-                 foldin_S=16, foldin_pool_bytes=0):
+                 foldin_S=16, foldin_pool_bytes=0, stream=None):
         L = lib()
         self.M, self.N, self.K = int(ratings.M), int(ratings.N), int(K)
         self.prec = PRECISIONS[prec] if isinstance(prec, str) else int(prec)
@@ -183,6 +188,7 @@ class Sampler:
         p.split_threshold = int(split_threshold)
         p.foldin_S = int(foldin_S)
         p.foldin_pool_bytes = int(foldin_pool_bytes)
+        p.stream = None if stream is None else int(stream)  # a hipStream_t handle
         ptr = _c(ratings.csr_ptr, np.int64)
         col = _c(ratings.csr_col, np.int32)
         val = _c(ratings.csr_val, np.float32)
@@ -288,6 +294,19 @@ class Sampler:
         Lam = _c(Lam, np.float64)
         self._check(lib().bpmf_set_hyper(self._ctx, side, _ptr(mu), _ptr(Lam)))
 
+    def get_chain_state(self):
+        """(running sum of test predictions in the caller's pair order, number
+        of sweeps in it)."""
+        ps = np.zeros(self.n_test)
+        n = ctypes.c_uint32()
+        self._check(lib().bpmf_get_chain_state(self._ctx, _ptr(ps), ctypes.byref(n)))
+        return ps, n.value
+
+    def set_chain_state(self, pred_sum, n_avg):
+        ps = _c(pred_sum, np.float64)
+        assert ps.shape == (self.n_test,)
+        self._check(lib().bpmf_set_chain_state(self._ctx, _ptr(ps), int(n_avg)))
+
     def get_csc(self):
         ptr = np.zeros(self.N + 1, np.int64)
         row = np.zeros(self.nnz, np.int32)
@@ -347,6 +366,15 @@ class Sampler:
             return None
         self._check(rc)
         return ids, mean, var, lat.value
+
+    def foldin_stats(self):
+        """(batches launched, requests launched, most requests in one batch,
+        most batches on the device at once)."""
+        nb, nr = ctypes.c_int64(), ctypes.c_int64()
+        mb, mi = ctypes.c_int32(), ctypes.c_int32()
+        self._check(lib().bpmf_foldin_stats(self._ctx, ctypes.byref(nb), ctypes.byref(nr),
+                                            ctypes.byref(mb), ctypes.byref(mi)))
+        return nb.value, nr.value, mb.value, mi.value
 
     def foldin_capacity(self):
         return int(lib().bpmf_foldin_capacity(self._ctx))

@@ -7,16 +7,22 @@
 // scores every movie against V^(s), and the request returns the top-n
 // unrated movies by predictive mean with their predictive variance.
 //
-// Scheduling: submissions (any thread) go to a FIFO.  The scheduler thread
-// packs the oldest pending requests into a batch while they fit the batch's
-// memory (rating and request capacity of a staging slot), launches the
-// batch's H2D copy, draw, score, top-n and D2H copy on the serving stream,
-// and immediately goes on to pack the next batch into the other slot, so
-// requests that arrive while a batch runs are admitted as soon as a slot is
-// free and their work queues behind it on the device.  Completions are found
-// by polling the slots' events.  Every per-request result depends only on
-// that request (each draw, score and selection is computed independently),
-// so a request's result is the same alone and in any mix.
+// Scheduling: submissions (any thread) go to one FIFO per size class (by
+// number of ratings).  kSlots staging slots, each with its own HIP stream,
+// carry batches: whenever a slot is free the scheduler thread takes the size
+// class whose oldest request is the oldest overall, packs that class's
+// requests (oldest first) and then requests of smaller classes while they fit
+// the slot's memory (rating and request capacity), and launches the batch's
+// H2D copy, draw, score, top-n and D2H copy on the slot's stream.  A batch's
+// time is set by its largest request, so a batch never takes a request of a
+// larger class than the one it was opened for: small requests do not wait
+// behind large ones, and the batches of several slots run on the device at
+// the same time.  Requests are admitted as slots free up; a request larger
+// than a slot's rating capacity is refused at submission.  Completions are
+// found by polling each busy slot's event.  Every per-request result
+// depends only on that request (each draw, score and selection is computed
+// independently of the others in its batch), so a request's result is the
+// same alone and in any mix.
 #include <hip/hip_runtime.h>
 #include <string.h>
 
@@ -37,13 +43,19 @@
 namespace bpmf {
 
 size_t foldin_topk_lds(int N, int top_max);
+size_t foldin_score_lds(int S, int ld);
 
 namespace {
 
 using Clock = std::chrono::steady_clock;
 constexpr int kTopMax = 1024;       // largest top_n (power of two for the sort)
 constexpr int kBatchReq = 64;       // requests per batch
+constexpr int kSlots = 4;           // staging slots, one stream each
+constexpr int kClasses = 4;         // size classes of the request queue
 constexpr size_t kMaxPending = 1u << 20;
+
+// Size class of a request with n ratings: up to 32, 256, 2048, more.
+int size_class(size_t n) { return n <= 32 ? 0 : (n <= 256 ? 1 : (n <= 2048 ? 2 : 3)); }
 
 struct Request {
     uint64_t id = 0;
@@ -76,8 +88,8 @@ struct Slot {
     int32_t *h_oid = nullptr;
     float *h_omean = nullptr, *h_ovar = nullptr;
     hipEvent_t done = nullptr;
+    hipStream_t stream = nullptr;
     bool busy = false;
-    uint64_t seq = 0;
     std::vector<std::shared_ptr<Request>> reqs;
 };
 
@@ -90,18 +102,20 @@ struct FoldinState {
     float *Vring = nullptr, *Lam_ring = nullptr, *Lmu_ring = nullptr;
     std::mutex mu;
     std::condition_variable cv;
-    std::deque<std::shared_ptr<Request>> pending;
+    std::deque<std::shared_ptr<Request>> pending[kClasses];
+    size_t n_pending = 0;
     std::unordered_map<uint64_t, std::shared_ptr<Request>> table;
     uint64_t next_id = 1;
     std::thread th;
     bool stop = false;
     bool storing = false;
     int inflight = 0;
-    uint64_t launch_seq = 0;
-    hipStream_t stream = nullptr;
-    Slot slots[2];
+    Slot slots[kSlots];
     int64_t R_max = 0;  // ratings per batch
     std::string dev_err;
+    // statistics
+    int64_t n_batches = 0, n_launched = 0;
+    int max_batch = 0, max_inflight = 0;
 };
 
 namespace {
@@ -127,6 +141,7 @@ void free_slot(Slot &s)
     for (void *p : h)
         if (p) (void)hipHostFree(p);
     if (s.done) (void)hipEventDestroy(s.done);
+    if (s.stream) (void)hipStreamDestroy(s.stream);
 }
 
 hipError_t alloc_slot(Slot &s, const bpmf_ctx *c, int S, int64_t R)
@@ -157,27 +172,42 @@ hipError_t alloc_slot(Slot &s, const bpmf_ctx *c, int S, int64_t R)
     A(hal(&s.h_omean, B * kTopMax));
     A(hal(&s.h_ovar, B * kTopMax));
     A(hipEventCreateWithFlags(&s.done, hipEventDisableTiming));
+    A(hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking));
 #undef A
     return hipSuccess;
 }
 
-// Pack pending requests (oldest first) into slot `sl` and launch its work.
-// Called with the lock held; releases it while staging and launching.
+// Pack pending requests into slot `sl` and launch its work: the size class
+// holding the oldest request opens the batch, then that class and the
+// smaller ones fill it, oldest first within each class, while the slot's
+// rating and request capacity allow.  Called with the lock held; releases it
+// while staging and launching.
 hipError_t launch_batch(bpmf_ctx *c, FoldinState &f, Slot &sl, std::unique_lock<std::mutex> &lk)
 {
     sl.reqs.clear();
+    int open = -1;
+    for (int k = 0; k < kClasses; ++k)
+        if (!f.pending[k].empty() && (open < 0 || f.pending[k].front()->id < f.pending[open].front()->id))
+            open = k;
     int64_t R = 0;
-    while (!f.pending.empty() && (int)sl.reqs.size() < kBatchReq) {
-        auto &r = f.pending.front();
-        if (R + (int64_t)r->movie.size() > f.R_max && !sl.reqs.empty()) break;
-        R += (int64_t)r->movie.size();
-        sl.reqs.push_back(r);
-        f.pending.pop_front();
+    for (int k = open; k >= 0 && (int)sl.reqs.size() < kBatchReq; --k) {
+        auto &q = f.pending[k];
+        while (!q.empty() && (int)sl.reqs.size() < kBatchReq) {
+            auto &r = q.front();
+            if (R + (int64_t)r->movie.size() > f.R_max && !sl.reqs.empty()) break;
+            R += (int64_t)r->movie.size();
+            sl.reqs.push_back(r);
+            q.pop_front();
+        }
     }
+    f.n_pending -= sl.reqs.size();
     const int S = f.n_stored;
     sl.busy = true;
-    sl.seq = ++f.launch_seq;
     ++f.inflight;
+    ++f.n_batches;
+    f.n_launched += (int64_t)sl.reqs.size();
+    f.max_batch = std::max(f.max_batch, (int)sl.reqs.size());
+    f.max_inflight = std::max(f.max_inflight, f.inflight);
     lk.unlock();
     // largest requests first in the draw launch; outputs are indexed by
     // position in the batch
@@ -204,7 +234,7 @@ hipError_t launch_batch(bpmf_ctx *c, FoldinState &f, Slot &sl, std::unique_lock<
         for (int s = 0; s < S; ++s)
             sl.h_items[q++] = FoldItem{i, s, (int64_t)sl.h_beg[i], (int64_t)sl.h_beg[i + 1]};
     }
-    hipStream_t st = f.stream;
+    hipStream_t st = sl.stream;
     hipError_t e;
 #define A(x)                              \
     if ((e = (x)) != hipSuccess) return e;
@@ -252,39 +282,38 @@ void scheduler(bpmf_ctx *c)
     std::unique_lock<std::mutex> lk(f.mu);
     for (;;) {
         if (f.stop && f.inflight == 0) break;
-        Slot *free_slot = nullptr;
-        for (auto &s : f.slots)
-            if (!s.busy) free_slot = &s;
-        if (!f.stop && !f.storing && !f.pending.empty() && free_slot && f.dev_err.empty()) {
-            hipError_t e = launch_batch(c, f, *free_slot, lk);
+        bool progressed = false;
+        // collect every finished batch
+        for (auto &s : f.slots) {
+            if (!s.busy) continue;
+            hipError_t q = hipEventQuery(s.done);
+            if (q == hipErrorNotReady) continue;
+            if (q != hipSuccess) f.dev_err = hipGetErrorString(q);
+            complete_batch(f, s, Clock::now());
+            progressed = true;
+        }
+        if (progressed) f.cv.notify_all();
+        // fill every free slot
+        for (auto &s : f.slots) {
+            if (f.stop || f.storing || f.n_pending == 0 || !f.dev_err.empty()) break;
+            if (s.busy) continue;
+            hipError_t e = launch_batch(c, f, s, lk);
             if (e != hipSuccess) {
                 if (!lk.owns_lock()) lk.lock();
                 f.dev_err = hipGetErrorString(e);
+                complete_batch(f, s, Clock::now());  // its requests report the error on poll
             }
+            progressed = true;
+        }
+        if (progressed) {
             f.cv.notify_all();
             continue;
         }
         if (f.inflight > 0) {
-            // oldest busy slot
-            Slot *old = nullptr;
-            for (auto &s : f.slots)
-                if (s.busy && (!old || s.seq < old->seq)) old = &s;
-            hipError_t q = hipEventQuery(old->done);
-            if (q == hipSuccess) {
-                complete_batch(f, *old, Clock::now());
-                f.cv.notify_all();
-                continue;
-            }
-            if (q != hipErrorNotReady) {
-                f.dev_err = hipGetErrorString(q);
-                complete_batch(f, *old, Clock::now());
-                f.cv.notify_all();
-                continue;
-            }
             f.cv.wait_for(lk, std::chrono::microseconds(20));
             continue;
         }
-        f.cv.wait(lk, [&] { return f.stop || (!f.pending.empty() && !f.storing); });
+        f.cv.wait(lk, [&] { return f.stop || (f.n_pending > 0 && !f.storing); });
     }
 }
 
@@ -303,16 +332,17 @@ void foldin_destroy(bpmf_ctx *c)
     {
         std::lock_guard<std::mutex> g(f->mu);
         f->stop = true;
-        f->pending.clear();
+        for (auto &q : f->pending) q.clear();
+        f->n_pending = 0;
     }
     f->cv.notify_all();
     if (f->th.joinable()) f->th.join();
-    if (f->stream) (void)hipStreamSynchronize(f->stream);
+    for (auto &s : f->slots)
+        if (s.stream) (void)hipStreamSynchronize(s.stream);
     for (auto &s : f->slots) free_slot(s);
     (void)hipFree(f->Vring);
     (void)hipFree(f->Lam_ring);
     (void)hipFree(f->Lmu_ring);
-    if (f->stream) (void)hipStreamDestroy(f->stream);
     delete f;
     c->foldin = nullptr;
 }
@@ -328,7 +358,7 @@ int bpmf_store_sample(bpmf_ctx *c)
     if (!c) return BPMF_E_INVAL;
     if (c->sticky) return ffail(c, BPMF_E_DEVICE, "context unusable after a device error");
     if (!fast_path_available(c)) return ffail(c, BPMF_E_INVAL, "fold-in needs FP32 factors and K <= 64");
-    if ((size_t)8 * c->foldin_S * c->ld * sizeof(float) > 65536 || foldin_topk_lds((int)c->N, kTopMax) > 65536)
+    if (foldin_score_lds(c->foldin_S, c->ld) > 65536 || foldin_topk_lds((int)c->N, kTopMax) > 65536)
         return ffail(c, BPMF_E_INVAL, "fold-in: foldin_S * K or N too large for one workgroup's LDS");
     hipError_t e;
     if (!c->foldin) {
@@ -336,20 +366,20 @@ int bpmf_store_sample(bpmf_ctx *c)
         c->foldin = f;
         f->S_cap = c->foldin_S;
         const size_t vsz = (size_t)c->N * c->ld;
-        // the pool holds the rated movies of the two batches in flight (8 B
-        // per rating); score buffers and outputs are sized by the batch limit
+        // the pool holds the rated movies of the batches in flight (8 B per
+        // rating, kSlots batches); score buffers and outputs are sized by the
+        // batch limit
         const size_t pool = c->foldin_pool ? c->foldin_pool : (256ull << 20);
-        f->R_max = (int64_t)std::min<size_t>(pool / 16, 1u << 28);
+        f->R_max = (int64_t)std::min<size_t>(pool / (8 * kSlots), 1u << 28);
         if (f->R_max < 1) {
             foldin_destroy(c);
             return ffail(c, BPMF_E_INVAL, "fold-in pool too small");
         }
-        if ((e = hipStreamCreateWithFlags(&f->stream, hipStreamNonBlocking)) != hipSuccess ||
-            (e = dal(&f->Vring, vsz * f->S_cap)) != hipSuccess ||
-            (e = dal(&f->Lam_ring, (size_t)f->S_cap * c->K * c->K)) != hipSuccess ||
-            (e = dal(&f->Lmu_ring, (size_t)f->S_cap * c->K)) != hipSuccess ||
-            (e = alloc_slot(f->slots[0], c, f->S_cap, f->R_max)) != hipSuccess ||
-            (e = alloc_slot(f->slots[1], c, f->S_cap, f->R_max)) != hipSuccess) {
+        e = dal(&f->Vring, vsz * f->S_cap);
+        if (e == hipSuccess) e = dal(&f->Lam_ring, (size_t)f->S_cap * c->K * c->K);
+        if (e == hipSuccess) e = dal(&f->Lmu_ring, (size_t)f->S_cap * c->K);
+        for (int q = 0; q < kSlots && e == hipSuccess; ++q) e = alloc_slot(f->slots[q], c, f->S_cap, f->R_max);
+        if (e != hipSuccess) {
             foldin_destroy(c);
             (void)hipGetLastError();
             return ffail(c, e == hipErrorOutOfMemory ? BPMF_E_NOMEM : BPMF_E_DEVICE, hipGetErrorString(e));
@@ -416,10 +446,11 @@ int bpmf_foldin_submit(bpmf_ctx *c, int32_t n, const int32_t *movie, const float
     {
         std::lock_guard<std::mutex> g(f->mu);
         if (!f->dev_err.empty()) return BPMF_E_DEVICE;
-        if (f->pending.size() >= kMaxPending) return BPMF_E_BUSY;
+        if (f->n_pending >= kMaxPending) return BPMF_E_BUSY;
         r->id = f->next_id++;
         r->t_submit = Clock::now();
-        f->pending.push_back(r);
+        f->pending[size_class(r->movie.size())].push_back(r);
+        ++f->n_pending;
         f->table.emplace(r->id, r);
         *req_id = r->id;
     }
@@ -453,8 +484,22 @@ int bpmf_foldin_drain(bpmf_ctx *c)
     FoldinState *f = c->foldin;
     if (!f) return BPMF_OK;
     std::unique_lock<std::mutex> lk(f->mu);
-    f->cv.wait(lk, [&] { return (f->pending.empty() && f->inflight == 0) || !f->dev_err.empty(); });
+    f->cv.wait(lk, [&] { return (f->n_pending == 0 && f->inflight == 0) || !f->dev_err.empty(); });
     return f->dev_err.empty() ? BPMF_OK : BPMF_E_DEVICE;
+}
+
+int bpmf_foldin_stats(bpmf_ctx *c, int64_t *batches, int64_t *requests, int32_t *max_batch_requests,
+                      int32_t *max_inflight_batches)
+{
+    if (!c) return BPMF_E_INVAL;
+    FoldinState *f = c->foldin;
+    std::unique_lock<std::mutex> lk;
+    if (f) lk = std::unique_lock<std::mutex>(f->mu);
+    if (batches) *batches = f ? f->n_batches : 0;
+    if (requests) *requests = f ? f->n_launched : 0;
+    if (max_batch_requests) *max_batch_requests = f ? f->max_batch : 0;
+    if (max_inflight_batches) *max_inflight_batches = f ? f->max_inflight : 0;
+    return BPMF_OK;
 }
 
 int bpmf_foldin_samples(const bpmf_ctx *c)

@@ -12,24 +12,42 @@ namespace bpmf {
 namespace {
 
 constexpr int kScoreThreads = 128;
-constexpr int kReqPerBlock = 8;
-constexpr int kTopThreads = 256;
+constexpr int kReqPerBlock = 16;
+constexpr int kTopThreads = 1024;
+constexpr int kTopWaves = kTopThreads / 64;
 
-// grid (ceil(N / 128), ceil(n_req / 8)); thread = one movie, 8 requests.
-// Mean and second central moment over samples by Welford's update.
+// Block (request group rg, movie tile m) of the score grid.  Workgroups are
+// dealt to the eight XCDs round-robin by their linear id, so the request
+// groups of one movie tile are given ids 8 apart: they land on the same XCD
+// and read that tile of the stored V samples from its L2 once.
+__device__ __forceinline__ bool score_block(int n_tiles, int n_rg, int &rg, int &m)
+{
+    const int L = blockIdx.x;
+    const int r = L >> 3;
+    rg = r % n_rg;
+    m = (r / n_rg) * 8 + (L & 7);
+    return m < n_tiles;
+}
+
+// thread = one movie of the tile, kReqPerBlock requests.  Mean and second
+// central moment over samples by Welford's update.
 __global__ __launch_bounds__(kScoreThreads) void foldin_score(
     int K, int ld, int N, int S, int n_req, const float *__restrict__ Vring, int64_t v_stride,
     const float *__restrict__ U, float rbar, float inv_alpha, float *__restrict__ mean,
     float *__restrict__ var)
 {
     extern __shared__ float us[];  // [kReqPerBlock][S][ld]
-    const int b0 = blockIdx.y * kReqPerBlock;
+    const int n_tiles = (N + kScoreThreads - 1) / kScoreThreads;
+    const int n_rg = (n_req + kReqPerBlock - 1) / kReqPerBlock;
+    int rg, mt;
+    if (!score_block(n_tiles, n_rg, rg, mt)) return;
+    const int b0 = rg * kReqPerBlock;
     const int nb = min(kReqPerBlock, n_req - b0);
     const int per_req = S * ld;
     for (int q = threadIdx.x; q < nb * per_req; q += kScoreThreads)
         us[q] = U[(size_t)b0 * per_req + q];
     __syncthreads();
-    const int j = blockIdx.x * kScoreThreads + threadIdx.x;
+    const int j = mt * kScoreThreads + threadIdx.x;
     if (j >= N) return;
     float m[kReqPerBlock], m2[kReqPerBlock];
 #pragma unroll
@@ -65,10 +83,56 @@ __device__ __forceinline__ uint32_t ord_key(float f)
     return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
 
+// Inclusive prefix sum over the 64 lanes of a wave (lane order), and the
+// same from the last lane down (suffix sum).
+__device__ __forceinline__ uint32_t wave_prefix(uint32_t x)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    return x;
+}
+
+__device__ __forceinline__ uint32_t wave_suffix(uint32_t x)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_down(x, off, 64);
+        if (lane + off < 64) x += y;
+    }
+    return x;
+}
+
+// Exclusive prefix sum of one value per thread over the workgroup (thread
+// order); wsum holds kTopWaves words of LDS.
+__device__ __forceinline__ uint32_t block_excl_prefix(uint32_t x, uint32_t *wsum)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint32_t inc = wave_prefix(x);
+    if (lane == 63) wsum[w] = inc;
+    __syncthreads();
+    if (w == 0) {
+        const uint32_t v = lane < kTopWaves ? wsum[lane] : 0u;
+        const uint32_t vi = wave_prefix(v);
+        if (lane < kTopWaves) wsum[lane] = vi - v;
+    }
+    __syncthreads();
+    const uint32_t r = wsum[w] + inc - x;
+    __syncthreads();  // wsum may be reused right after
+    return r;
+}
+
 // One workgroup per request: exact top-n of the unrated movies by mean,
-// ties to the smaller id.  Radix select of the n-th largest key (4 passes of
-// 8 bits), then the keys above it plus the smallest-id ties, sorted by
-// (key desc, id asc) with a bitonic network.
+// ties to the smaller id.  Keys: order-preserving images of the means, 0 for
+// rated movies.  The n-th largest key T is found by radix selection over
+// 8-bit digits, starting below the highest bit in which the smallest and
+// largest candidate keys differ (the bits above it are common to all); then
+// the keys above T and the smallest-id keys equal to T are gathered and
+// sorted by (key desc, id asc) with a bitonic network.
 __global__ __launch_bounds__(kTopThreads) void foldin_topk(
     int N, const float *__restrict__ mean, const float *__restrict__ var,
     const int32_t *__restrict__ req_beg, const int32_t *__restrict__ nbr,
@@ -77,16 +141,22 @@ __global__ __launch_bounds__(kTopThreads) void foldin_topk(
 {
     extern __shared__ uint32_t sm[];
     const int words = (N + 31) / 32;
-    uint32_t *rated = sm;                       // bitmap
-    uint32_t *hist = rated + words;             // 256 bins
-    uint32_t *scan = hist + 256;                // kTopThreads
-    unsigned long long *sel = (unsigned long long *)(scan + kTopThreads + (words & 1));  // top_max (pow2)
-    __shared__ uint32_t s_prefix, s_remaining, s_count;
+    uint32_t *rated = sm;                    // bitmap of rated movies
+    uint32_t *hist = rated + words;          // 256 bins
+    uint32_t *wsum = hist + 256;             // kTopWaves
+    unsigned long long *sel = (unsigned long long *)(wsum + kTopWaves + (words & 1));  // top_max (pow2)
+    __shared__ uint32_t s_prefix, s_remaining, s_count, s_kmin, s_kmax;
     const int tid = threadIdx.x;
+    const int lane = tid & 63, w = tid >> 6;
     const int b = blockIdx.x;
     const float *mb = mean + (size_t)b * N;
     const float *vb = var + (size_t)b * N;
-    for (int w = tid; w < words; w += kTopThreads) rated[w] = 0u;
+    for (int q = tid; q < words; q += kTopThreads) rated[q] = 0u;
+    if (tid == 0) {
+        s_kmin = 0xFFFFFFFFu;
+        s_kmax = 0u;
+        s_count = 0u;
+    }
     __syncthreads();
     const int beg = req_beg[b], end = req_beg[b + 1];
     for (int e = beg + tid; e < end; e += kTopThreads) {
@@ -94,68 +164,84 @@ __global__ __launch_bounds__(kTopThreads) void foldin_topk(
         atomicOr(&rated[j >> 5], 1u << (j & 31));
     }
     __syncthreads();
-    int n_rated = 0;
-    for (int w = 0; w < words; ++w) n_rated += __popc(rated[w]);
-    const int want = min(min(top_n[b], top_max), N - n_rated);
-    // key 0 marks a rated movie (every real key is > 0)
+    // the request's movies are distinct (checked at submission)
+    const int want = min(min(top_n[b], top_max), N - (end - beg));
     auto key_of = [&](int j) -> uint32_t {
         return (rated[j >> 5] >> (j & 31)) & 1u ? 0u : ord_key(mb[j]);
     };
-    if (tid == 0) {
-        s_prefix = 0u;
-        s_remaining = (uint32_t)max(want, 0);
-    }
-    __syncthreads();
-    for (int shift = 24; shift >= 0 && want > 0; shift -= 8) {
-        for (int q = tid; q < 256; q += kTopThreads) hist[q] = 0u;
-        __syncthreads();
-        const uint32_t prefix = s_prefix;
-        const uint32_t hmask = shift == 24 ? 0u : (0xFFFFFFFFu << (shift + 8));
+    // smallest and largest candidate key
+    {
+        uint32_t kmin = 0xFFFFFFFFu, kmax = 0u;
         for (int j = tid; j < N; j += kTopThreads) {
             const uint32_t k = key_of(j);
-            if (k != 0u && (k & hmask) == (prefix & hmask)) atomicAdd(&hist[(k >> shift) & 0xFFu], 1u);
-        }
-        __syncthreads();
-        if (tid == 0) {
-            uint32_t rem = s_remaining, bin = 255;
-            for (int q = 255; q >= 0; --q) {
-                if (hist[q] >= rem) {
-                    bin = (uint32_t)q;
-                    break;
-                }
-                rem -= hist[q];
+            if (k) {
+                kmin = min(kmin, k);
+                kmax = max(kmax, k);
             }
-            s_prefix = prefix | (bin << shift);
-            s_remaining = rem;  // how many keys equal to the final threshold to take
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            kmin = min(kmin, (uint32_t)__shfl_xor(kmin, off, 64));
+            kmax = max(kmax, (uint32_t)__shfl_xor(kmax, off, 64));
+        }
+        if (lane == 0) {
+            atomicMin(&s_kmin, kmin);
+            atomicMax(&s_kmax, kmax);
+        }
+    }
+    __syncthreads();
+    const uint32_t kmin = s_kmin, kmax = s_kmax;
+    // bits above position p: p = 31 -> none
+    auto above = [](int p) -> uint32_t { return p >= 31 ? 0u : (0xFFFFFFFFu << (p + 1)); };
+    const int hb = want > 0 && kmin != kmax ? 31 - __clz(kmin ^ kmax) : -1;
+    uint32_t prefix = kmax & above(hb);
+    uint32_t rem = (uint32_t)max(want, 0);
+    for (int hi = hb; hi >= 0; hi -= 8) {
+        const int lo = max(hi - 7, 0);
+        const uint32_t dmask = (1u << (hi - lo + 1)) - 1u;
+        const uint32_t hmask = above(hi);
+        for (int q = tid; q < 256; q += kTopThreads) hist[q] = 0u;
+        __syncthreads();
+        for (int j = tid; j < N; j += kTopThreads) {
+            const uint32_t k = key_of(j);
+            if (k != 0u && (k & hmask) == prefix) atomicAdd(&hist[(k >> lo) & dmask], 1u);
         }
         __syncthreads();
+        if (w == 0) {
+            // lane l holds bins 4l .. 4l+3; the bin where the count from the
+            // top reaches rem holds the rem-th largest key
+            uint32_t h[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) h[q] = hist[4 * lane + q];
+            const uint32_t tot = h[0] + h[1] + h[2] + h[3];
+            uint32_t acc = wave_suffix(tot) - tot;  // keys in the bins above this lane's
+#pragma unroll
+            for (int q = 3; q >= 0; --q) {
+                if (acc < rem && acc + h[q] >= rem) {
+                    s_prefix = prefix | ((uint32_t)(4 * lane + q) << lo);
+                    s_remaining = rem - acc;
+                }
+                acc += h[q];
+            }
+        }
+        __syncthreads();
+        prefix = s_prefix;
+        rem = s_remaining;
     }
-    const uint32_t T = s_prefix;
-    const uint32_t take_eq = s_remaining;
-    // contiguous ranges per thread so that ties are taken in id order
+    const uint32_t T = prefix;     // the want-th largest key
+    const uint32_t take_eq = rem;  // keys equal to T to take (smallest ids)
+    // contiguous id ranges per thread, so that ties are taken in id order
     const int per = (N + kTopThreads - 1) / kTopThreads;
-    const int j0 = tid * per, j1 = min(N, j0 + per);
+    const int j0 = min(N, tid * per), j1 = min(N, j0 + per);
     uint32_t eq_local = 0;
     if (want > 0)
         for (int j = j0; j < j1; ++j) eq_local += key_of(j) == T ? 1u : 0u;
-    scan[tid] = eq_local;
-    if (tid == 0) s_count = 0u;
-    __syncthreads();
-    if (tid == 0) {
-        uint32_t acc = 0;
-        for (int q = 0; q < kTopThreads; ++q) {
-            const uint32_t v = scan[q];
-            scan[q] = acc;
-            acc += v;
-        }
-    }
-    __syncthreads();
+    uint32_t eq_seen = block_excl_prefix(eq_local, wsum);
     int pow2 = 1;
     while (pow2 < want) pow2 <<= 1;
     for (int q = tid; q < pow2; q += kTopThreads) sel[q] = 0ull;
     __syncthreads();
     if (want > 0) {
-        uint32_t eq_seen = scan[tid];
         for (int j = j0; j < j1; ++j) {
             const uint32_t k = key_of(j);
             bool pick = false;
@@ -212,10 +298,11 @@ hipError_t launch_foldin_score(const bpmf_ctx *c, int n_req, int S, const float 
 {
     if (n_req == 0) return hipSuccess;
     const int64_t v_stride = c->N * (int64_t)c->ld;
-    dim3 grid((unsigned)((c->N + kScoreThreads - 1) / kScoreThreads),
-              (unsigned)((n_req + kReqPerBlock - 1) / kReqPerBlock));
+    const int n_tiles = (int)((c->N + kScoreThreads - 1) / kScoreThreads);
+    const int n_rg = (n_req + kReqPerBlock - 1) / kReqPerBlock;
+    const unsigned grid = (unsigned)((n_tiles + 7) / 8 * 8 * n_rg);
     const size_t lds = sizeof(float) * kReqPerBlock * S * c->ld;
-    hipLaunchKernelGGL(foldin_score, grid, dim3(kScoreThreads), lds, s, c->K, c->ld, (int)c->N, S,
+    hipLaunchKernelGGL(foldin_score, dim3(grid), dim3(kScoreThreads), lds, s, c->K, c->ld, (int)c->N, S,
                        n_req, Vring, v_stride, U, (float)c->rbar, (float)(1.0 / c->alpha), mean, var);
     return hipGetLastError();
 }
@@ -223,8 +310,10 @@ hipError_t launch_foldin_score(const bpmf_ctx *c, int n_req, int S, const float 
 size_t foldin_topk_lds(int N, int top_max)
 {
     const int words = (N + 31) / 32;
-    return sizeof(uint32_t) * (words + 256 + kTopThreads + 1) + sizeof(unsigned long long) * top_max + 16;
+    return sizeof(uint32_t) * (words + 256 + kTopWaves + 1) + sizeof(unsigned long long) * top_max + 16;
 }
+
+size_t foldin_score_lds(int S, int ld) { return sizeof(float) * kReqPerBlock * S * ld; }
 
 hipError_t launch_foldin_topk(const bpmf_ctx *c, int n_req, const float *mean, const float *var,
                               const int32_t *req_beg, const int32_t *nbr, const int32_t *top_n,

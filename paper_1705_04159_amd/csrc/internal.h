@@ -87,7 +87,8 @@ struct Side {
 
 struct bpmf_ctx {
     int device = 0;
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;           // Gibbs calls (the caller's, or our own)
+    bool own_stream = true;
     hipStream_t stream2 = nullptr;          // second stream for overlapped hyper draws
     hipStream_t stream3 = nullptr;          // whole rows beside the split rows in the graph
     hipEvent_t fork_ev[3] = {};             // fork/join events of the sweep graph
@@ -106,6 +107,7 @@ struct bpmf_ctx {
     int32_t *test_row = nullptr, *test_col = nullptr;
     float *test_val = nullptr;
     double *pred_sum = nullptr;
+    std::vector<int64_t> test_src;  // test pair q (held in user order) is the caller's pair test_src[q]
     double *rmse_part = nullptr;  // per-block partial sums of squared errors
     int rmse_blocks = 0;
     double *rmse_hist = nullptr;  // [2 * hist_cap] (avg, last) per sweep of a run
@@ -115,7 +117,7 @@ struct bpmf_ctx {
     int hyp_blocks = 0;
     double *hyp_stats[2] = {};    // [K + K(K+1)/2]
     double *hyp_scratch[2] = {};  // [4 * K * K + 8 * K]
-    int *hyp_status = nullptr;    // device flag: 1 = ok
+    int *hyp_status = nullptr;    // device flags, 1 = ok: [0] hyper draw, [1] row draws (pivots)
     int hyp_lds_max = 65536;      // LDS bytes the draw kernel may use
     // split partials
     void *part = nullptr;

@@ -137,7 +137,7 @@ __device__ __forceinline__ void blocked_chol_sample(floatx4 (&acc)[NB * (NB + 1)
                                                     int K, float alpha,
                                                     const floatx4 *__restrict__ img, uint32_t row,
                                                     uint32_t t, uint64_t seed, uint32_t stream,
-                                                    float *__restrict__ xrow)
+                                                    float *__restrict__ xrow, int *__restrict__ status)
 {
     using L = BigLds<NB>;
     float *pan = lds;
@@ -195,6 +195,7 @@ __device__ __forceinline__ void blocked_chol_sample(floatx4 (&acc)[NB * (NB + 1)
                 });
                 db = __builtin_fmaf(bcast16<k>(db), nf, db);
             });
+            if (kq == 0 && !(mydiag > 0.f)) *status = 0;  // P not positive definite in FP32
             const float inv_s = __builtin_amdgcn_rsqf(mydiag);
             if (kq == 0) {
 #pragma unroll
@@ -362,7 +363,7 @@ __global__ __launch_bounds__(64 * kBigWPB, big_waves<NB>()) void row_big(
     const int32_t *__restrict__ nbr, const float *__restrict__ rc, const void *__restrict__ Y,
     int ldy, uint32_t y_bytes, const floatx4 *__restrict__ img, const float *__restrict__ Lmu,
     float *__restrict__ X, int ldx, float *__restrict__ part, uint64_t seed, uint32_t stream,
-    const uint32_t *__restrict__ ctr)
+    const uint32_t *__restrict__ ctr, int *__restrict__ status)
 {
     constexpr int NBLK = NB * (NB + 1) / 2;
     extern __shared__ float smem_f[];
@@ -406,7 +407,7 @@ __global__ __launch_bounds__(64 * kBigWPB, big_waves<NB>()) void row_big(
             }
         wave_sync();
         blocked_chol_sample<NB>(acc, lds, K, alpha, img, (uint32_t)it.row, ctr[0], seed, stream,
-                                X + (size_t)it.row * ldx);
+                                X + (size_t)it.row * ldx, status);
     }
 }
 
@@ -417,7 +418,7 @@ __global__ __launch_bounds__(64 * kBigWPB, big_waves<NB>()) void row_finish_big(
     int K, float alpha, const FinishItem *__restrict__ fin, int64_t n_fin,
     const float *__restrict__ part, const floatx4 *__restrict__ img, const float *__restrict__ Lmu,
     float *__restrict__ X, int ldx, uint64_t seed, uint32_t stream,
-    const uint32_t *__restrict__ ctr)
+    const uint32_t *__restrict__ ctr, int *__restrict__ status)
 {
     constexpr int NBLK = NB * (NB + 1) / 2;
     extern __shared__ float smem_f[];
@@ -453,7 +454,7 @@ __global__ __launch_bounds__(64 * kBigWPB, big_waves<NB>()) void row_finish_big(
     }
     wave_sync();
     blocked_chol_sample<NB>(acc, lds, K, alpha, img, (uint32_t)f.row, ctr[0], seed, stream,
-                            X + (size_t)f.row * ldx);
+                            X + (size_t)f.row * ldx, status);
 }
 
 // The prior Lambda (identity on the padding) in the accumulator layout:
@@ -489,7 +490,7 @@ hipError_t launch_big(bpmf_ctx *c, Side &sd, Side &ot, hipStream_t s, int stage)
         hipLaunchKernelGGL((row_finish_big<NB>), dim3(grid), dim3(64 * kBigWPB), lds, s, c->K,
                            (float)c->alpha, sd.fin, sd.n_fin, (const float *)c->part, img,
                            (const float *)sd.Lmu_w, (float *)sd.X, c->ld, c->seed, sd.stream_row,
-                           c->ctr);
+                           c->ctr, c->hyp_status + 1);
         return hipGetLastError();
     }
     if (stage != kStageSegments && stage != kStageRows) return hipSuccess;
@@ -505,7 +506,7 @@ hipError_t launch_big(bpmf_ctx *c, Side &sd, Side &ot, hipStream_t s, int stage)
                            (float)c->alpha, sd.items, item0, item0 + count, sd.nbr,
                            (const float *)sd.rc, ysrc, c->ld, y_bytes, img,
                            (const float *)sd.Lmu_w, (float *)sd.X, c->ld, (float *)c->part,
-                           c->seed, sd.stream_row, c->ctr);
+                           c->seed, sd.stream_row, c->ctr, c->hyp_status + 1);
     };
     if (stage == kStageSegments) {
         if (bf)

@@ -50,11 +50,13 @@ namespace {
 // Factor and sample one row held column-per-lane: lane c of the group has
 // v[r] = P[r][c] for r < KP (identity outside the leading K x K block) and
 // v[KP] = b_c.  The normals come from Philox counters (c0, c1, stream<<24 |
-// block, c3).  Returns x_c (meaningful for c < K).
+// block, c3).  Returns x_c (meaningful for c < K).  A live lane whose pivot
+// is not positive (P lost definiteness in FP32) clears *status.
 template <int KP, int RPW>
 __device__ __forceinline__ float chol_sample_column(float (&v)[KP + 1], int K, int c, uint32_t c0,
                                                     uint32_t c1, uint32_t c3, uint64_t seed,
-                                                    uint32_t stream)
+                                                    uint32_t stream, bool live,
+                                                    int *__restrict__ status)
 {
     float mydiag = 1.f;
     static_for<0, KP>([&](auto kc) {
@@ -73,6 +75,7 @@ __device__ __forceinline__ float chol_sample_column(float (&v)[KP + 1], int K, i
             v[r] -= f * prk[r];
         });
     });
+    if (live && !(mydiag > 0.f) && status) *status = 0;
     const float inv_s = __builtin_amdgcn_rsqf(mydiag);
 #pragma unroll
     for (int r = 0; r < KP; ++r) v[r] *= inv_s;  // column c of L (rows > c)
@@ -121,7 +124,7 @@ __global__ __launch_bounds__(64 * WPB, 6) void row_fast_f32(
     const int32_t *__restrict__ nbr, const float *__restrict__ rc, const float *__restrict__ Y,
     int ldy, uint32_t y_bytes, const float *__restrict__ LamPk, const float *__restrict__ Lmu,
     float *__restrict__ X, int ldx, float *__restrict__ part, uint64_t seed, uint32_t stream,
-    const uint32_t *__restrict__ ctr)
+    const uint32_t *__restrict__ ctr, int *__restrict__ status)
 {
     constexpr int KP = 16 * NB;
     constexpr int NBLK = NB * (NB + 1) / 2;
@@ -234,7 +237,8 @@ __global__ __launch_bounds__(64 * WPB, 6) void row_fast_f32(
 #pragma unroll
     for (int r = 0; r < KP; ++r) v[r] = (live && r < K) ? P[r >= cc ? pk(r, cc) : pk(cc, r)] : (r == c ? 1.f : 0.f);
     v[KP] = live ? alpha * P[KP * (KP + 1) / 2 + cc] + Lmu[c] : 0.f;
-    const float x = chol_sample_column<KP, RPW>(v, K, c, (uint32_t)my_row, ctr[0], 0u, seed, stream);
+    const float x = chol_sample_column<KP, RPW>(v, K, c, (uint32_t)my_row, ctr[0], 0u, seed, stream,
+                                                live, status);
     if (live) X[(size_t)my_row * ldx + c] = x;
 }
 
@@ -248,7 +252,7 @@ __global__ __launch_bounds__(64 * WPB) void foldin_draw_f32(
     const int32_t *__restrict__ nbr, const float *__restrict__ rc, const float *__restrict__ Vring,
     int64_t v_stride, int ldy, uint32_t y_bytes, const float *__restrict__ Lam_ring,
     const float *__restrict__ Lmu_ring, const uint64_t *__restrict__ req_ids, int n_samples,
-    float *__restrict__ U, int ldu, uint64_t seed, uint32_t stream)
+    float *__restrict__ U, int ldu, uint64_t seed, uint32_t stream, int *__restrict__ status)
 {
     constexpr int KP = 16 * NB;
     constexpr int LDP = KP + 1;
@@ -332,7 +336,7 @@ __global__ __launch_bounds__(64 * WPB) void foldin_draw_f32(
     v[KP] = live ? alpha * P[KP * (KP + 1) / 2 + cc] + Lmu[c] : 0.f;
     const uint64_t key = my_req >= 0 ? req_ids[my_req] : 0ull;
     const float x = chol_sample_column<KP, RPW>(v, K, c, (uint32_t)key, (uint32_t)my_s,
-                                                (uint32_t)(key >> 32), seed, stream);
+                                                (uint32_t)(key >> 32), seed, stream, live, status);
     const int64_t out_row = (int64_t)my_req * n_samples + my_s;
     if (live) U[(size_t)out_row * ldu + c] = x;
 }
@@ -359,7 +363,7 @@ __global__ __launch_bounds__(64 * WPB) void row_finish_fast(
     int K, float alpha, const FinishItem *__restrict__ fin, int64_t n_fin,
     const float *__restrict__ part, const float *__restrict__ Lam, const float *__restrict__ Lmu,
     float *__restrict__ X, int ldx, uint64_t seed, uint32_t stream,
-    const uint32_t *__restrict__ ctr)
+    const uint32_t *__restrict__ ctr, int *__restrict__ status)
 {
     constexpr int KP = 16 * NB;
     const int c = threadIdx.x & 63;
@@ -375,7 +379,8 @@ __global__ __launch_bounds__(64 * WPB) void row_finish_fast(
         v[r] = (live && r < K) ? alpha * src[r >= c ? pk(r, c) : pk(c, r)] + Lam[r * K + c]
                                : (r == c ? 1.f : 0.f);
     v[KP] = live ? alpha * src[KK2 + c] + Lmu[c] : 0.f;
-    const float x = chol_sample_column<KP, 1>(v, K, c, (uint32_t)f.row, ctr[0], 0u, seed, stream);
+    const float x = chol_sample_column<KP, 1>(v, K, c, (uint32_t)f.row, ctr[0], 0u, seed, stream,
+                                              live, status);
     if (live) X[(size_t)f.row * ldx + c] = x;
 }
 
@@ -389,7 +394,7 @@ hipError_t launch_finish_f32(bpmf_ctx *c, Side &sd, hipStream_t s)
     hipLaunchKernelGGL((row_finish_fast<NB, WPB>), dim3(grid), dim3(64 * WPB), 0, s, c->K,
                        (float)c->alpha, sd.fin, sd.n_fin, (const float *)c->part,
                        (const float *)sd.Lam_w, (const float *)sd.Lmu_w, (float *)sd.X, c->ld,
-                       c->seed, sd.stream_row, c->ctr);
+                       c->seed, sd.stream_row, c->ctr, c->hyp_status + 1);
     return hipGetLastError();
 }
 
@@ -409,7 +414,7 @@ hipError_t launch_f32(bpmf_ctx *c, Side &sd, Side &ot, hipStream_t s, int64_t it
                        (float)c->alpha, sd.items, item0, item_end, sd.nbr, (const float *)sd.rc,
                        (const float *)ot.X, c->ld, y_bytes, (const float *)sd.Lam_pk,
                        (const float *)sd.Lmu_w, (float *)sd.X, c->ld, (float *)c->part, c->seed,
-                       sd.stream_row, c->ctr);
+                       sd.stream_row, c->ctr, c->hyp_status + 1);
     return hipGetLastError();
 }
 
@@ -441,7 +446,8 @@ hipError_t launch_foldin_draw(const bpmf_ctx *c, const FoldItem *items, int64_t 
         const unsigned grid = (unsigned)((n_items + per_block - 1) / per_block);
         hipLaunchKernelGGL((foldin_draw_f32<NB, RPW, WPB>), dim3(grid), dim3(64 * WPB), lds, s, c->K,
                            (float)c->alpha, items, n_items, nbr, rc, Vring, v_stride, c->ld, y_bytes,
-                           Lam_ring, Lmu_ring, req_ids, n_samples, U, c->ld, c->seed, 7u);
+                           Lam_ring, Lmu_ring, req_ids, n_samples, U, c->ld, c->seed, 7u,
+                           (int *)nullptr);
     };
     using I = std::integral_constant<int, 1>;
     using II = std::integral_constant<int, 2>;

@@ -61,15 +61,16 @@ __device__ __forceinline__ Smem<T> carve(char *base, int K)
 
 // Cholesky of the packed lower P (in place), forward solve of b, add the
 // row's normals, back solve; the result is left in s.b.  A non-positive
-// pivot propagates NaN into the row, which the caller can detect.
+// pivot clears *status and propagates NaN into the row.
 template <typename T>
 __device__ void factor_and_sample(int K, Smem<T> s, uint64_t seed, uint32_t stream, uint32_t t,
-                                  uint32_t row)
+                                  uint32_t row, int *__restrict__ status)
 {
     const int tid = threadIdx.x;
     for (int k = 0; k < K; ++k) {
         if (tid == 0) {
             T d = s.P[pk(k, k)];
+            if (!(d > T(0))) *status = 0;
             s.P[pk(k, k)] = d > T(0) ? sqrt(d) : T(NAN);
         }
         __syncthreads();
@@ -116,7 +117,7 @@ __global__ __launch_bounds__(kThreads) void row_update_generic(
     int K, T alpha, const RowItem *__restrict__ items, const int32_t *__restrict__ nbr,
     const T *__restrict__ rc, const YT *__restrict__ Y, int ldy, const T *__restrict__ Lam,
     const T *__restrict__ Lmu, T *__restrict__ X, int ldx, T *__restrict__ part, uint64_t seed,
-    uint32_t stream, const uint32_t *__restrict__ ctr)
+    uint32_t stream, const uint32_t *__restrict__ ctr, int *__restrict__ status)
 {
     extern __shared__ __align__(16) char smem_raw[];
     Smem<T> s = carve<T>(smem_raw, K);
@@ -180,7 +181,7 @@ __global__ __launch_bounds__(kThreads) void row_update_generic(
     }
     if (tid < K) s.b[tid] = Lmu[tid] + alpha * bacc;
     __syncthreads();
-    factor_and_sample<T>(K, s, seed, stream, ctr[0], (uint32_t)it.row);
+    factor_and_sample<T>(K, s, seed, stream, ctr[0], (uint32_t)it.row, status);
     if (tid < K) X[(size_t)it.row * ldx + tid] = s.b[tid];
 }
 
@@ -190,7 +191,7 @@ template <typename T>
 __global__ __launch_bounds__(kThreads) void row_finish_generic(
     int K, T alpha, const FinishItem *__restrict__ fin, const T *__restrict__ part,
     const T *__restrict__ Lam, const T *__restrict__ Lmu, T *__restrict__ X, int ldx,
-    uint64_t seed, uint32_t stream, const uint32_t *__restrict__ ctr)
+    uint64_t seed, uint32_t stream, const uint32_t *__restrict__ ctr, int *__restrict__ status)
 {
     extern __shared__ __align__(16) char smem_raw[];
     Smem<T> s = carve<T>(smem_raw, K);
@@ -209,7 +210,7 @@ __global__ __launch_bounds__(kThreads) void row_finish_generic(
         }
     }
     __syncthreads();
-    factor_and_sample<T>(K, s, seed, stream, ctr[0], (uint32_t)f.row);
+    factor_and_sample<T>(K, s, seed, stream, ctr[0], (uint32_t)f.row, status);
     if (tid < K) X[(size_t)f.row * ldx + tid] = s.b[tid];
 }
 
@@ -234,6 +235,9 @@ hipError_t launch_row_generic(bpmf_ctx *c, int side_id, hipStream_t s, int stage
     Side &sd = c->side[side_id];
     Side &ot = c->side[1 - side_id];
     const int K = c->K;
+    // this kernel draws every work item: a side must not also have rows on
+    // the rank-one path (lowrank_available excludes every case that lands here)
+    if (sd.n_low != 0) return hipErrorInvalidValue;
     if (c->prec == 0) {
         size_t lds = lds_bytes<double>(K);
         if (stage == kStageSegments && sd.n_items > 0)
@@ -242,13 +246,13 @@ hipError_t launch_row_generic(bpmf_ctx *c, int side_id, hipStream_t s, int stage
                                (const double *)sd.rc, (const double *)ot.X, c->ld,
                                (const double *)sd.Lam_w, (const double *)sd.Lmu_w,
                                (double *)sd.X, c->ld, (double *)c->part, c->seed, sd.stream_row,
-                               c->ctr);
+                               c->ctr, c->hyp_status + 1);
         if (stage == kStageFinish && sd.n_fin > 0)
             hipLaunchKernelGGL((row_finish_generic<double>), dim3((unsigned)sd.n_fin),
                                dim3(kThreads), lds, s, K, c->alpha, sd.fin,
                                (const double *)c->part, (const double *)sd.Lam_w,
                                (const double *)sd.Lmu_w, (double *)sd.X, c->ld, c->seed,
-                               sd.stream_row, c->ctr);
+                               sd.stream_row, c->ctr, c->hyp_status + 1);
     } else {
         size_t lds = lds_bytes<float>(K);
         if (stage == kStageSegments && sd.n_items > 0) {
@@ -258,21 +262,22 @@ hipError_t launch_row_generic(bpmf_ctx *c, int side_id, hipStream_t s, int stage
                                    (float)c->alpha, sd.items, sd.nbr, (const float *)sd.rc,
                                    (const uint16_t *)ot.Xbf, c->ld, (const float *)sd.Lam_w,
                                    (const float *)sd.Lmu_w, (float *)sd.X, c->ld,
-                                   (float *)c->part, c->seed, sd.stream_row, c->ctr);
+                                   (float *)c->part, c->seed, sd.stream_row, c->ctr,
+                                   c->hyp_status + 1);
             else
                 hipLaunchKernelGGL((row_update_generic<float, float>), dim3((unsigned)sd.n_items),
                                    dim3(kThreads), lds, s, K, (float)c->alpha, sd.items, sd.nbr,
                                    (const float *)sd.rc, (const float *)ot.X, c->ld,
                                    (const float *)sd.Lam_w, (const float *)sd.Lmu_w,
                                    (float *)sd.X, c->ld, (float *)c->part, c->seed,
-                                   sd.stream_row, c->ctr);
+                                   sd.stream_row, c->ctr, c->hyp_status + 1);
         }
         if (stage == kStageFinish && sd.n_fin > 0)
             hipLaunchKernelGGL((row_finish_generic<float>), dim3((unsigned)sd.n_fin),
                                dim3(kThreads), lds, s, K, (float)c->alpha, sd.fin,
                                (const float *)c->part, (const float *)sd.Lam_w,
                                (const float *)sd.Lmu_w, (float *)sd.X, c->ld, c->seed,
-                               sd.stream_row, c->ctr);
+                               sd.stream_row, c->ctr, c->hyp_status + 1);
     }
     return hipGetLastError();
 }

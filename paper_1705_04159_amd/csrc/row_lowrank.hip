@@ -258,8 +258,11 @@ __global__ __launch_bounds__(64 * kLowWPB) void row_lowrank(
 
 }  // namespace
 
-// The low-rank path: FP32 factors, K <= 64.
-bool lowrank_available(const bpmf_ctx *c) { return c->prec == 1 && c->K <= 64; }
+// The low-rank path: FP32 factors, K <= 64, and the buffer-offset and row-id
+// limits of the matrix-core kernels (the same as the column-per-lane
+// kernel's), so that the factorisation kernels that run beside it stop at
+// the rank-one rows: the generic kernel would draw every row.
+bool lowrank_available(const bpmf_ctx *c) { return c->prec == 1 && c->K <= 64 && fast_path_available(c); }
 
 // The rows stage of a side with low-rank rows: transform the gathered
 // factor, then the rows [n_items - n_low, n_items).  With a cut-off above 8

@@ -322,6 +322,7 @@ void bpmf_default_params(bpmf_params *p, int32_t K)
     p->foldin_S = 16;
     p->split_threshold = 0;
     p->foldin_pool_bytes = 0;
+    p->stream = nullptr;
 }
 
 const char *bpmf_last_error(const bpmf_ctx *c) { return c ? c->err.c_str() : g_create_err.c_str(); }
@@ -416,6 +417,8 @@ int bpmf_create(int64_t M, int64_t N, const int64_t *csr_ptr, const int32_t *csr
     c->nu0 = p->nu0;
     c->seed = p->seed;
     c->burn_in = p->burn_in;
+    c->side[0].rows = M;
+    c->side[1].rows = N;
     // default: rows above 2048 ratings are split (above 8192 for K > 64, where
     // a segment's partial sums are large and its Gram long enough to keep
     // the waves busy)
@@ -443,7 +446,12 @@ int bpmf_create(int64_t M, int64_t N, const int64_t *csr_ptr, const int32_t *csr
     } while (0)
     {
         CK(hipGetDevice(&c->device));
-        CK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+        if (p->stream) {
+            c->stream = (hipStream_t)p->stream;
+            c->own_stream = false;
+        } else {
+            CK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+        }
         CK(hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking));
         CK(hipStreamCreateWithFlags(&c->stream3, hipStreamNonBlocking));
         for (auto &ev : c->fork_ev) CK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
@@ -531,10 +539,10 @@ int bpmf_create(int64_t M, int64_t N, const int64_t *csr_ptr, const int32_t *csr
             CK(dalloc(&c->hyp_stats[sid], (size_t)(K + KK2)));
             CK(dalloc(&c->hyp_scratch[sid], (size_t)4 * K * K + 8 * K));
         }
-        CK(dalloc(&c->hyp_status, 1));
+        CK(dalloc(&c->hyp_status, 2));
         {
-            int one = 1;
-            CK(hipMemcpy(c->hyp_status, &one, sizeof(int), hipMemcpyHostToDevice));
+            const int ones[2] = {1, 1};
+            CK(hipMemcpy(c->hyp_status, ones, sizeof(ones), hipMemcpyHostToDevice));
         }
         // test set
         CK(dalloc(&c->test_row, n_test));
@@ -551,8 +559,10 @@ int bpmf_create(int64_t M, int64_t N, const int64_t *csr_ptr, const int32_t *csr
             for (int64_t i = 0; i < M; ++i) start[i + 1] += start[i];
             std::vector<int32_t> tr(n_test), tc(n_test);
             std::vector<float> tv(n_test);
+            c->test_src.resize(n_test);
             for (int64_t e = 0; e < n_test; ++e) {
                 const int64_t q = start[test_row[e]]++;
+                c->test_src[q] = e;
                 tr[q] = test_row[e];
                 tc[q] = test_col[e];
                 tv[q] = test_val[e];
@@ -608,7 +618,7 @@ void bpmf_destroy(bpmf_ctx *c)
     if (c->stream3) (void)hipStreamDestroy(c->stream3);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
-    if (c->stream) (void)hipStreamDestroy(c->stream);
+    if (c->stream && c->own_stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
 
@@ -628,14 +638,18 @@ static int timed_end(bpmf_ctx *c)
     return BPMF_OK;
 }
 
-static int check_hyper_status(bpmf_ctx *c)
+// The device flags the kernels clear on a non-positive pivot (hyper draw,
+// row draws); read and re-armed after every call that launches them.
+static int check_status(bpmf_ctx *c)
 {
-    int st = 1;
-    HIPCK(c, hipMemcpy(&st, c->hyp_status, sizeof(int), hipMemcpyDeviceToHost));
-    if (!st) {
-        int one = 1;
-        HIPCK(c, hipMemcpy(c->hyp_status, &one, sizeof(int), hipMemcpyHostToDevice));
-        return fail(c, BPMF_E_DEVICE, "hyperparameter draw hit a non-SPD matrix");
+    int st[2] = {1, 1};
+    HIPCK(c, hipMemcpy(st, c->hyp_status, sizeof(st), hipMemcpyDeviceToHost));
+    if (!st[0] || !st[1]) {
+        const int ones[2] = {1, 1};
+        HIPCK(c, hipMemcpy(c->hyp_status, ones, sizeof(ones), hipMemcpyHostToDevice));
+        return fail(c, BPMF_E_NOTSPD, "%s",
+                    !st[0] ? "hyperparameter draw hit a matrix that is not positive definite"
+                           : "a row's precision matrix was not positive definite in working precision");
     }
     return BPMF_OK;
 }
@@ -648,7 +662,7 @@ int bpmf_sample_hyper(bpmf_ctx *c, int32_t side, uint32_t t)
     HIPCK(c, launch_set_counter(c->ctr, 0, t, c->stream));
     HIPCK(c, launch_hyper(c, side, c->stream));
     if (int r = timed_end(c)) return r;
-    return check_hyper_status(c);
+    return check_status(c);
 }
 
 int bpmf_update_side(bpmf_ctx *c, int32_t side, uint32_t t)
@@ -658,7 +672,8 @@ int bpmf_update_side(bpmf_ctx *c, int32_t side, uint32_t t)
     HIPCK(c, hipEventRecord(c->ev0, c->stream));
     HIPCK(c, launch_set_counter(c->ctr, 0, t, c->stream));
     HIPCK(c, enqueue_update(c, side, c->stream));
-    return timed_end(c);
+    if (int r = timed_end(c)) return r;
+    return check_status(c);
 }
 
 // The external event-record nodes of the captured sweep (V start, V end,
@@ -959,7 +974,7 @@ int bpmf_run_sweeps(bpmf_ctx *c, uint32_t t0, uint32_t n, double *rmse_avg, doub
         HIPCK(c, hipGraphLaunch(c->graph, c->stream));
     }
     if (int r = timed_end(c)) return r;
-    if (int r = check_hyper_status(c)) return r;
+    if (int r = check_status(c)) return r;
     double acc[2] = {0.0, 0.0};
     for (uint32_t q = 0; q < n_sets; ++q)
         for (int sd = 0; sd < 2; ++sd) {
@@ -1006,7 +1021,7 @@ int bpmf_profile_sweeps(bpmf_ctx *c, uint32_t t0, uint32_t n, double *phase_ms)
     for (auto &e : ev) (void)hipEventDestroy(e);
     if (rc != BPMF_OK) return rc;
     for (int q = 0; q < 7; ++q) phase_ms[q] = acc[q] / n;
-    return check_hyper_status(c);
+    return check_status(c);
 }
 
 int bpmf_predict(bpmf_ctx *c, uint32_t t, int64_t n, const int32_t *row, const int32_t *col,
@@ -1134,6 +1149,35 @@ int bpmf_set_hyper(bpmf_ctx *c, int32_t side, const double *mu, const double *La
                        hipMemcpyHostToDevice));
     HIPCK(c, launch_prior_to_working(c, side, c->stream));
     HIPCK(c, hipStreamSynchronize(c->stream));
+    return BPMF_OK;
+}
+
+int bpmf_get_chain_state(bpmf_ctx *c, double *pred_sum, uint32_t *n_avg)
+{
+    STICKY(c);
+    HIPCK(c, hipStreamSynchronize(c->stream));
+    if (n_avg) HIPCK(c, hipMemcpy(n_avg, c->ctr + 2, sizeof(uint32_t), hipMemcpyDeviceToHost));
+    if (pred_sum && c->n_test) {
+        std::vector<double> h(c->n_test);
+        HIPCK(c, hipMemcpy(h.data(), c->pred_sum, sizeof(double) * c->n_test, hipMemcpyDeviceToHost));
+        for (int64_t q = 0; q < c->n_test; ++q) pred_sum[c->test_src[q]] = h[q];
+    }
+    return BPMF_OK;
+}
+
+int bpmf_set_chain_state(bpmf_ctx *c, const double *pred_sum, uint32_t n_avg)
+{
+    STICKY(c);
+    if (!pred_sum && c->n_test) return fail(c, BPMF_E_INVAL, "null prediction sums");
+    for (int64_t e = 0; e < c->n_test; ++e)
+        if (!isfinite(pred_sum[e])) return fail(c, BPMF_E_FORMAT, "non-finite prediction sum at %lld", (long long)e);
+    HIPCK(c, hipStreamSynchronize(c->stream));
+    if (c->n_test) {
+        std::vector<double> h(c->n_test);
+        for (int64_t q = 0; q < c->n_test; ++q) h[q] = pred_sum[c->test_src[q]];
+        HIPCK(c, hipMemcpy(c->pred_sum, h.data(), sizeof(double) * c->n_test, hipMemcpyHostToDevice));
+    }
+    HIPCK(c, hipMemcpy(c->ctr + 2, &n_avg, sizeof(uint32_t), hipMemcpyHostToDevice));
     return BPMF_OK;
 }
 
