@@ -117,32 +117,62 @@ def test_foldin_ring_keeps_last_S(bp, orc):
 
 
 def test_foldin_alone_equals_mixed(bp):
-    """A request's result is identical whether it runs alone or batched with
-    many others that arrive while it is on the GPU."""
+    """121 requests (0 to 399 ratings, every size class but the largest; top-n
+    between 1 and 100) run one at a time in context A -- each submitted only
+    after the previous one completed -- and in one burst in context B.  Every
+    request's result (ids, means, variances) is bit-identical between the two,
+    A's batches held one request each, and B's scheduler packed several
+    requests per batch and had several batches on the device at once."""
     r = synth.random_small(23, 800, 400, 20000, 16)
     K, seed = 32, 7
     rng = np.random.default_rng(1)
-    movie = rng.choice(r.N, 150, replace=False).astype(np.int32)
-    rating = rng.normal(3.5, 1.0, 150).astype(np.float32)
+    reqs = []
+    for i in range(121):
+        n = 150 if i == 0 else int(rng.integers(0, 400))
+        movie = rng.choice(r.N, n, replace=False).astype(np.int32)
+        rating = rng.normal(3.5, 1.0, n).astype(np.float32)
+        reqs.append((movie, rating, int(rng.integers(1, 101))))
     a, _ = _chain_with_samples(bp, r, K, seed, n_samples=3, S=8)
-    rid_a = a.foldin_submit(movie, rating, 50)
-    res_a = _wait(a, rid_a, 50)
+    res_a = []
+    for movie, rating, top in reqs:
+        rid = a.foldin_submit(movie, rating, top)
+        res_a.append((rid, _wait(a, rid, top)))
+    stats_a = a.foldin_stats()
     a.close()
     b, _ = _chain_with_samples(bp, r, K, seed, n_samples=3, S=8)
-    rid_b = b.foldin_submit(movie, rating, 50)
-    others = []
-    for i in range(120):
-        n = int(rng.integers(0, 300))
-        m = rng.choice(r.N, n, replace=False).astype(np.int32)
-        others.append(b.foldin_submit(m, rng.normal(3.5, 1, n).astype(np.float32), 10))
-    res_b = _wait(b, rid_b, 50)
-    assert rid_a == rid_b == 1
-    for x, y in zip(res_a[:3], res_b[:3]):
-        assert np.array_equal(x, y)
-    b.foldin_drain()
-    for o in others:
-        assert b.foldin_poll(o, 10) is not None
+    rids = [b.foldin_submit(movie, rating, top) for movie, rating, top in reqs]
+    res_b = [(rid, _wait(b, rid, top)) for rid, (_, _, top) in zip(rids, reqs)]
+    stats_b = b.foldin_stats()
     b.close()
+    print("alone: batches %d, requests %d, max per batch %d, max in flight %d" % stats_a)
+    print("burst: batches %d, requests %d, max per batch %d, max in flight %d" % stats_b)
+    assert stats_a[:3] == (121, 121, 1)
+    assert stats_b[1] == 121 and stats_b[2] > 1 and stats_b[3] > 1
+    for (ra, xa), (rb, xb) in zip(res_a, res_b):
+        assert ra == rb  # the same request id, hence the same noise
+        for u, v in zip(xa[:3], xb[:3]):
+            assert np.array_equal(u, v)
+
+
+def test_foldin_serving_size_matches_oracle(bp, orc):
+    """Fold-in at the serving workload's size: N = 26,744 movies, K = 32,
+    16 stored samples, requests of 1 to 5,000 ratings (the largest request
+    size), top-100, against the oracle's fold-in."""
+    r = synth.random_small(26, 3000, 26744, 240000, 8)
+    K, seed = 32, 41
+    s, store = _chain_with_samples(bp, r, K, seed, n_samples=16, S=16)
+    assert s.foldin_samples() == 16
+    rng = np.random.default_rng(5)
+    pop = np.bincount(r.csr_col, minlength=r.N) + 1.0
+    reqs = []
+    for n in [1, 9, 71, 587, 2600, 5000]:
+        movie = rng.choice(r.N, n, replace=False, p=pop / pop.sum()).astype(np.int32)
+        rating = np.clip(rng.normal(3.5, 1.0, n), 0.5, 5.0).astype(np.float32)
+        reqs.append((movie, rating, s.foldin_submit(movie, rating, 100)))
+    for movie, rating, rid in reqs:
+        res = _wait(s, rid, 100)
+        _check_against_oracle(orc, s, store, movie, rating, rid, res, 100, seed)
+    s.close()
 
 
 def test_foldin_errors(bp):
@@ -171,9 +201,10 @@ def test_foldin_errors(bp):
         s.foldin_poll(rid, 5)
     assert e.value.code == bp.E_NOTFOUND
     s.close()
-    # a request larger than one batch's rating capacity (pool / 16 ratings)
+    # a request larger than one batch's rating capacity (pool / 32 ratings:
+    # 8 B per rating, four batch slots)
     big = synth.random_small(25, 100, 3000, 3000, 4)
-    t = bp.Sampler(big, 4, prec="fp32", seed=2, foldin_S=2, foldin_pool_bytes=16 * 1000)
+    t = bp.Sampler(big, 4, prec="fp32", seed=2, foldin_S=2, foldin_pool_bytes=32 * 1000)
     t.run_sweeps(1, 1)
     t.store_sample()
     assert t.foldin_capacity() == 1000
