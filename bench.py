@@ -42,19 +42,35 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-def algorithmic(K, nnz, rows_finished, rows_written, gather_row_bytes, src_bytes):
-    """Per-launch algorithmic work of the row kernel of one side.
+def algorithmic(K, deg, n_low, other_rows, gather_row_bytes, src_bytes):
+    """Per-launch algorithmic work of one side's row update (every row).
 
-    FLOP: K(K+1) + 2K per rating (lower-triangle Gram + rhs) and
-    K^3/3 + 2K^2 per finished row (Cholesky + two triangular solves).
-    Bytes: 8 per rating (neighbour id + rating), the gathered row (K x
-    element size) per rating when the gathered factor exceeds one L2, and
-    the written row.  Returns (Gram flops, factorisation flops, bytes)."""
-    gram = nnz * (K * (K + 1) + 2 * K)
-    fact = rows_finished * (K ** 3 / 3.0 + 2 * K * K)
+    Rows that are factorised (all but the n_low of smallest degree): K(K+1) +
+    2K FLOP per rating (lower-triangle Gram + rhs) and K^3/3 + 2K^2 per row
+    (Cholesky + two triangular solves).  Rows on the rank-one path (degree
+    d): 2K d^2 + 12 K d + K^2 FLOP (the d rank-one factors, each applied to the
+    later gathered rows, the rhs and the two solves through the d factors,
+    and the product with chol(Lambda)^-T), plus K^2 per row of the other side
+    for its transform by chol(Lambda)^-1 when the side has such rows.
+    Bytes: 8 per rating (neighbour id + rating), the gathered row (K x element
+    size) per rating when the gathered factor exceeds one L2, and the written
+    row.  Returns (Gram FLOP, factorisation FLOP, bytes)."""
+    deg = np.sort(np.asarray(deg, np.int64))  # ascending: the rank-one rows are the first n_low
+    low = deg[:n_low].astype(np.float64)
+    full = deg[n_low:]
+    gram = float(full.sum()) * (K * (K + 1) + 2 * K)
+    fact = len(full) * (K ** 3 / 3.0 + 2 * K * K)
+    if n_low:
+        fact += float((2 * K * low * low + 12 * K * low + K * K).sum()) + float(other_rows) * K * K
+    nnz = int(deg.sum())
     gather = gather_row_bytes * nnz if src_bytes > L2_BYTES else 0
-    byts = 8 * nnz + gather + 4 * K * rows_written
+    byts = 8 * nnz + gather + 4 * K * len(deg)
     return gram, fact, byts
+
+
+def side_degrees(r):
+    """Degrees of the rows of each side: users (CSR rows) and movies (columns)."""
+    return {"U": np.diff(r.csr_ptr), "V": np.bincount(r.csr_col, minlength=r.N)}
 
 
 PEAK_FP64_TFLOPS = 78.6  # MI355X dense FP64 (matrix cores), TFLOP/s
@@ -85,7 +101,7 @@ def measure_peaks(row_bytes, src_bytes):
     return out
 
 
-def sweep_roofline(K, prec, r, ms_per_step, peaks):
+def sweep_roofline(K, prec, r, ms_per_step, peaks, n_low=None):
     """T_roof of one sweep: the sum over the two sides of
     max(matrix-core time, vector time, memory time) of that side's row
     updates, with the algorithmic work of `algorithmic` for every row and
@@ -98,11 +114,13 @@ def sweep_roofline(K, prec, r, ms_per_step, peaks):
     is T_roof over the measured sweep time."""
     esize = 8 if prec == "fp64" else (2 if prec == "bf16" else 4)
     ld = K if prec == "fp64" else (K + 3) // 4 * 4
-    sides = {"V": (r.N, r.M * ld * esize), "U": (r.M, r.N * ld * esize)}
+    sides = {"V": (r.N, r.M * ld * esize, r.M), "U": (r.M, r.N * ld * esize, r.N)}
+    degs = side_degrees(r)
+    n_low = n_low or {}
     res = {"sides": {}}
     tot_spec = tot_meas = 0.0
-    for name, (rows, src) in sides.items():
-        gram, fact, byts = algorithmic(K, r.nnz, rows, rows, ld * esize, src)
+    for name, (rows, src, other) in sides.items():
+        gram, fact, byts = algorithmic(K, degs[name], n_low.get(name, 0), other, ld * esize, src)
         gathered = ld * esize * r.nnz
         compulsory = byts - (gathered if src > L2_BYTES else 0)
         if prec == "fp64":
@@ -236,6 +254,64 @@ def profiled_traffic(workload, K, prec, side):
     return None
 
 
+def kernel_roofline(K, prec, r, k_ms, peaks, n_low, steps):
+    """Roofline of the dominant kernel: the row update of the side that takes
+    longer per launch (every kernel of that side's update, timed inside the
+    timed sweeps), with its algorithmic FLOP and bytes per launch against
+    the peak of its own arithmetic (FP32 matrix cores; in the BF16-Gram form
+    the Gram at the BF16 peak and the factorisation at the FP32 one,
+    time-weighted) or HBM, whichever bound is higher; also against the peaks
+    measured on this GPU, and the HBM traffic of the committed counter
+    summary for this workload and side (None if there is none or the
+    kernel's sources changed since)."""
+    esize = 8 if prec == "fp64" else (2 if prec == "bf16" else 4)
+    ld = K if prec == "fp64" else (K + 3) // 4 * 4
+    degs = side_degrees(r)
+    cand = {
+        "rows_V": algorithmic(K, degs["V"], n_low.get("V", 0), r.M, ld * esize, r.M * ld * esize),
+        "rows_U": algorithmic(K, degs["U"], n_low.get("U", 0), r.N, ld * esize, r.N * ld * esize),
+    }
+    dom = max(cand, key=lambda n: k_ms[n])
+    gram, fact, byts = cand[dom]
+    flops = gram + fact
+    sec = k_ms[dom] / 1000.0
+    peak = PEAK_FP64_TFLOPS if prec == "fp64" else PEAK_FP32_TFLOPS
+    if prec == "bf16":
+        peak = flops / (gram / PEAK_BF16_TFLOPS + fact / PEAK_FP32_TFLOPS)
+    t_mfma = flops / (peak * 1e12)
+    t_hbm = byts / (PEAK_HBM_GBS * 1e9)
+    if t_hbm > t_mfma:
+        roof = {"bound": "hbm", "achieved": round(byts / sec / 1e9, 1), "peak": PEAK_HBM_GBS,
+                "unit": "GB/s"}
+    else:
+        roof = {"bound": "mfma", "achieved": round(flops / sec / 1e12, 3), "peak": round(peak, 1),
+                "unit": "TFLOP/s"}
+    roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
+    if peaks:
+        if roof["bound"] == "hbm":
+            src = (r.M if dom == "rows_V" else r.N) * ld * esize
+            gathered = ld * esize * r.nnz
+            t_meas = ((byts - gathered) / (peaks["hbm_triad_gbs"] * 1e9)
+                      + gathered / (peaks["gather_gbs"][str(int(src))] * 1e9))
+            roof["peak_measured"] = round(byts / t_meas / 1e9, 1)
+        else:
+            p32 = peaks["fp32_mfma_tflops"]
+            pm = p32
+            if prec == "bf16":
+                pm = flops / (gram / peaks["bf16_mfma_tflops"]
+                              + fact / max(p32, peaks["fp32_valu_tflops"]))
+            elif prec == "fp64":
+                pm = peaks["fp64_mfma_tflops"]
+            roof["peak_measured"] = round(pm, 2)
+        roof["frac_measured"] = round(roof["achieved"] / roof["peak_measured"], 4)
+    roof["flop_per_launch"] = round(flops)
+    roof["bytes_per_launch"] = int(byts)
+    roof["traffic"] = profiled_traffic(r.name, K, prec, dom[-1])
+    roof["kernel"] = ("row update, side %s (every kernel of the side's update; mean of %d "
+                      "sweeps in the timed region, %.4f ms)" % (dom[-1], steps, k_ms[dom]))
+    return roof
+
+
 def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -365,43 +441,74 @@ def foldin_bench(s, r, rate, seconds, seed, top_n=100, warm_seconds=0.0):
     }
 
 
+def timed_config(r, K, prec, steps, seed, autotune=True, with_peaks=True, warm=2):
+    """One workload in one precision: measured peaks (optional), autotuned
+    plan (outside the timed region), `warm` warm-up sweeps, then `steps`
+    timed sweeps of the sweep graph (wall clock around them, device idle on
+    both sides); reports throughput, held-out RMSE, the row-update time per
+    side measured inside the timed sweeps, the dominant kernel's roofline and
+    the sweep roofline."""
+    import paper_1705_04159_amd as bp
+
+    peaks = None
+    esize = 8 if prec == "fp64" else (2 if prec == "bf16" else 4)
+    ld = K if prec == "fp64" else (K + 3) // 4 * 4
+    if with_peaks:
+        peaks = measure_peaks(ld * esize, (r.M * ld * esize, r.N * ld * esize))
+    s = bp.Sampler(r, K, prec=prec, seed=seed)
+    plan = None
+    if autotune:
+        split, kmax, low, tried = s.autotune(3)
+        plan = {"split_threshold": split, "fast_kmax": kmax, "lowrank_dmax": low,
+                "tried": [[a, b, c_, round(m, 4)] for a, b, c_, m in tried]}
+    s.run_sweeps(1, warm)  # warm-up with the timed plan
+    s.synchronize()
+    t0 = time.perf_counter()
+    avg, last = s.run_sweeps(warm + 1, steps)
+    s.synchronize()
+    ms = 1000.0 * (time.perf_counter() - t0) / steps
+    kv, ku = s.row_kernel_ms()
+    k_ms = {"rows_V": kv, "rows_U": ku}
+    n_low = {"U": s.lowrank_rows(bp.SIDE_U), "V": s.lowrank_rows(bp.SIDE_V)}
+    s.close()
+    return {"ms_per_step": round(ms, 3), "row_updates_per_s": round((r.M + r.N) / ms * 1e3, 1),
+            "ratings_per_s": round(2 * r.nnz / ms * 1e3, 1),
+            "rmse_avg": round(float(avg[-1]), 5), "rmse_last": round(float(last[-1]), 5),
+            "row_kernel_ms": {"rows_V": round(kv, 3), "rows_U": round(ku, 3)},
+            "lowrank_rows": n_low, "autotune": plan,
+            "roofline": kernel_roofline(K, prec, r, k_ms, peaks, n_low, steps),
+            "sweep_roofline": sweep_roofline(K, prec, r, ms, peaks, n_low),
+            "peaks_measured": peaks}
+
+
 def k100_compare(steps, seed, autotune=True, with_peaks=True):
     """The 100M-rating shape at K = 100: the same chain (same seed, same
     Philox draws) in FP32 and in the BF16-Gram form, `steps` timed sweeps
     each after two warm-up sweeps; reports throughput and the held-out RMSE
     of both, and their ratio."""
-    import paper_1705_04159_amd as bp
-
     t = time.perf_counter()
     r = synth.netflix_like()
     log("generated %s: M=%d N=%d nnz=%d in %.1fs" % (r.name, r.M, r.N, r.nnz, time.perf_counter() - t))
     out = {"workload": r.name, "M": r.M, "N": r.N, "nnz_train": r.nnz, "K": 100, "steps": steps}
     for prec in ("fp32", "bf16"):
-        peaks = None
-        if with_peaks:
-            rb = (100 + 3) // 4 * 4 * (2 if prec == "bf16" else 4)  # row stride of the gathered factor
-            peaks = measure_peaks(rb, (r.M * rb, r.N * rb))
-        s = bp.Sampler(r, 100, prec=prec, seed=seed)
-        split = None
-        if autotune:
-            split, _, _, _ = s.autotune(3)
-        s.run_sweeps(1, 2)  # warm-up with the timed plan
-        s.synchronize()
-        t0 = time.perf_counter()
-        avg, last = s.run_sweeps(3, steps)
-        s.synchronize()
-        ms = 1000.0 * (time.perf_counter() - t0) / steps
-        kv, ku = s.row_kernel_ms()
-        s.close()
-        out[prec] = {"ms_per_step": round(ms, 3), "row_updates_per_s": round((r.M + r.N) / ms * 1e3, 1),
-                     "ratings_per_s": round(2 * r.nnz / ms * 1e3, 1),
-                     "rmse_avg": round(float(avg[-1]), 5), "rmse_last": round(float(last[-1]), 5),
-                     "row_kernel_ms": {"rows_V": round(kv, 3), "rows_U": round(ku, 3)},
-                     "split_threshold": split,
-                     "sweep_roofline": sweep_roofline(100, prec, r, ms, peaks)}
-        log("K=100 %s: %s" % (prec, out[prec]))
+        out[prec] = timed_config(r, 100, prec, steps, seed, autotune, with_peaks)
+        log("K=100 %s: %s" % (prec, {k: v for k, v in out[prec].items() if k != "peaks_measured"}))
     out["bf16_speedup"] = round(out["fp32"]["ms_per_step"] / out["bf16"]["ms_per_step"], 3)
     out["rmse_avg_rel_diff"] = round(out["bf16"]["rmse_avg"] / out["fp32"]["rmse_avg"] - 1.0, 6)
+    return out
+
+
+def chembl_compare(steps, seed, autotune=True, with_peaks=True):
+    """The compound x protein shape (483,500 x 5,775, 2,000,000 observations,
+    20 columns holding 30%), K = 64, FP32: `steps` timed sweeps after the
+    autotuner and two warm-up sweeps."""
+    t = time.perf_counter()
+    r = synth.chembl_like()
+    log("generated %s: M=%d N=%d nnz=%d in %.1fs" % (r.name, r.M, r.N, r.nnz, time.perf_counter() - t))
+    out = {"workload": r.name, "M": r.M, "N": r.N, "nnz_train": r.nnz, "K": 64, "precision": "fp32",
+           "steps": steps}
+    out.update(timed_config(r, 64, "fp32", steps, seed, autotune, with_peaks))
+    log("compound x protein: %s" % {k: v for k, v in out.items() if k != "peaks_measured"})
     return out
 
 
@@ -417,14 +524,17 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=5)
     ap.add_argument("--foldin-rate", type=float, default=5000.0)
-    ap.add_argument("--foldin-seconds", type=float, default=3.0)
-    ap.add_argument("--foldin-warmup-seconds", type=float, default=0.0)
+    ap.add_argument("--foldin-seconds", type=float, default=10.0)
+    ap.add_argument("--foldin-warmup-seconds", type=float, default=2.0)
     ap.add_argument("--foldin-sweep", default="1000,2500,10000,20000,40000,80000",
                     help="offered loads (req/s) of the 1-s load sweep, comma separated; empty: none")
     ap.add_argument("--no-foldin", action="store_true")
     ap.add_argument("--k100-steps", type=int, default=50,
                     help="sweeps of the K = 100 comparison (100M-rating shape, FP32 vs BF16-Gram)")
     ap.add_argument("--no-k100", action="store_true")
+    ap.add_argument("--chembl-steps", type=int, default=50,
+                    help="sweeps of the compound x protein comparison (K = 64, FP32)")
+    ap.add_argument("--no-chembl", action="store_true")
     ap.add_argument("--fig2", action="store_true",
                     help="only time each kernel family per row against the row's degree (K = 32, "
                          "N = 26,744) and fit the fixed + per-rating cost model; one JSON line")
@@ -510,50 +620,8 @@ def main():
     k_ms = dict(zip(["rows_V", "rows_U"], s.row_kernel_ms()))
     log("row kernel per launch (ms, timed sweeps): %s" % {k: round(v, 4) for k, v in k_ms.items()})
     # the timed stage of a side is its whole row update (every row finished)
-    cand = {
-        "rows_V": algorithmic(K, r.nnz, r.N, r.N, K * esize, r.M * K * esize),
-        "rows_U": algorithmic(K, r.nnz, r.M, r.M, K * esize, r.N * K * esize),
-    }
-    dom = max(cand, key=lambda n: k_ms[n])
-    gram, fact, byts = cand[dom]
-    flops = gram + fact
-    sec = k_ms[dom] / 1000.0
-    # peak of the contraction's own type: in the BF16-Gram mode the Gram runs
-    # at the BF16 peak and the factorisation at the FP32 one (time-weighted)
-    peak = PEAK_FP32_TFLOPS
-    if prec == "bf16":
-        peak = flops / (gram / PEAK_BF16_TFLOPS + fact / PEAK_FP32_TFLOPS)
-    t_mfma = flops / (peak * 1e12)
-    t_hbm = byts / (PEAK_HBM_GBS * 1e9)
-    if t_hbm > t_mfma:
-        roof = {"bound": "hbm", "achieved": round(byts / sec / 1e9, 1), "peak": PEAK_HBM_GBS,
-                "unit": "GB/s"}
-    else:
-        roof = {"bound": "mfma", "achieved": round(flops / sec / 1e12, 3), "peak": round(peak, 1),
-                "unit": "TFLOP/s"}
-    roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
-    if peaks:
-        # the same bound against the rates measured on this GPU
-        if roof["bound"] == "hbm":
-            src = (r.M if dom == "rows_V" else r.N) * ld * esize
-            gathered = ld * esize * r.nnz
-            t_meas = ((byts - gathered) / (peaks["hbm_triad_gbs"] * 1e9)
-                      + gathered / (peaks["gather_gbs"][str(int(src))] * 1e9))
-            roof["peak_measured"] = round(byts / t_meas / 1e9, 1)
-        else:
-            p32 = peaks["fp32_mfma_tflops"]
-            pm = p32
-            if prec == "bf16":
-                pm = flops / (gram / peaks["bf16_mfma_tflops"]
-                              + fact / max(p32, peaks["fp32_valu_tflops"]))
-            elif prec == "fp64":
-                pm = peaks["fp64_mfma_tflops"]
-            roof["peak_measured"] = round(pm, 2)
-        roof["frac_measured"] = round(roof["achieved"] / roof["peak_measured"], 4)
-    roof["traffic"] = profiled_traffic(r.name, K, prec, dom[-1])
-    roof["kernel"] = ("row update, side %s (segments, whole rows and split-row finishing; mean of %d "
-                      "sweeps in the timed region, %.4f ms)" % (dom[-1], steps, k_ms[dom]))
-
+    n_low = {"U": s.lowrank_rows(bp.SIDE_U), "V": s.lowrank_rows(bp.SIDE_V)}
+    roof = kernel_roofline(K, prec, r, k_ms, peaks, n_low, steps)
     out = {
         "metric": "Gibbs row-updates/s",
         "value": round(value, 1),
@@ -577,7 +645,8 @@ def main():
         "row_kernel_ms": {k: round(v, 4) for k, v in k_ms.items()},
         "autotune": tuned,
         "roofline": roof,
-        "sweep_roofline": sweep_roofline(K, prec, r, ms_per_step, peaks),
+        "sweep_roofline": sweep_roofline(K, prec, r, ms_per_step, peaks, n_low),
+        "lowrank_rows": n_low,
         "peaks_measured": peaks,
     }
     if not args.no_foldin and prec == "fp32" and K <= 64:
@@ -601,6 +670,9 @@ def main():
     s.close()
     if not args.no_k100 and args.workload == "movielens":
         out["k100"] = k100_compare(args.k100_steps, args.seed, not args.no_autotune, not args.no_peaks)
+    if not args.no_chembl and args.workload == "movielens":
+        out["chembl"] = chembl_compare(args.chembl_steps, args.seed, not args.no_autotune,
+                                       not args.no_peaks)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(r, K, args.cpu_seconds, args.seed)
         log("cpu baseline: %s" % out["cpu_baseline"])

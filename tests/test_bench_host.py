@@ -12,25 +12,39 @@ import bench  # noqa: E402
 
 
 def test_algorithmic_work_per_launch():
-    # K = 2: per rating K(K+1) + 2K = 10 FLOP, per row K^3/3 + 2K^2 FLOP
-    gram, fact, byts = bench.algorithmic(2, 100, 7, 9, 8, 1 << 30)
+    # K = 2: per rating K(K+1) + 2K = 10 FLOP, per row K^3/3 + 2K^2 FLOP;
+    # 9 rows with 100 ratings in all
+    deg = np.array([30, 20, 20, 10, 10, 5, 5, 0, 0])
+    gram, fact, byts = bench.algorithmic(2, deg, 0, 1000, 8, 1 << 30)
     assert gram == 1000
-    assert abs(fact - 7 * (8 / 3 + 8)) < 1e-12
+    assert abs(fact - 9 * (8 / 3 + 8)) < 1e-12
     assert byts == 8 * 100 + 8 * 100 + 4 * 2 * 9  # ids+ratings, gathered rows (source > L2), written rows
-    _, _, b_small = bench.algorithmic(2, 100, 7, 9, 8, 1 << 10)  # source fits L2: no gather bytes
+    _, _, b_small = bench.algorithmic(2, deg, 0, 1000, 8, 1 << 10)  # source fits L2: no gather bytes
     assert b_small == 8 * 100 + 4 * 2 * 9
+    # the 4 rows of smallest degree (0, 0, 5, 5) on the rank-one path: no Gram or
+    # factorisation for them, 2K d^2 + 12 K d + K^2 each, plus K^2 per row of the
+    # other side (1000 rows) for the transform
+    gram, fact, byts = bench.algorithmic(2, deg, 4, 1000, 8, 1 << 30)
+    assert gram == 90 * 10
+    low = 2 * 4 + 2 * (2 * 2 * 25 + 12 * 2 * 5 + 4)
+    assert abs(fact - (5 * (8 / 3 + 8) + low + 1000 * 4)) < 1e-9
+    assert byts == 8 * 100 + 8 * 100 + 4 * 2 * 9
 
 
 def test_sweep_roofline_spec_terms():
     """The 20M shape at K = 32: the V side (gathering a 17.7 MB U) is bound by
     HBM, the U side by the FP32 matrix cores; the sum is about 0.45 ms."""
-    r = types.SimpleNamespace(M=138493, N=26744, nnz=18000237)
+    r = types.SimpleNamespace(M=138493, N=26744, nnz=18000237,
+                              csr_ptr=np.linspace(0, 18000237, 138494).astype(np.int64),
+                              csr_col=np.arange(18000237, dtype=np.int64) % 26744)
     res = bench.sweep_roofline(32, "fp32", r, 1.0, None)
     assert res["sides"]["V"]["bound_spec"] == "hbm" and res["sides"]["U"]["bound_spec"] == "mfma"
     assert 0.43 < res["t_roof_ms_spec"] < 0.46
     assert res["frac_spec"] == res["t_roof_ms_spec"]
     # BF16-Gram at K = 100: V side HBM-bound, U side bound by the FP32 factorisation
-    r = types.SimpleNamespace(M=480189, N=17770, nnz=90432457)
+    r = types.SimpleNamespace(M=480189, N=17770, nnz=90432457,
+                              csr_ptr=np.linspace(0, 90432457, 480190).astype(np.int64),
+                              csr_col=np.arange(90432457, dtype=np.int32) % 17770)
     res = bench.sweep_roofline(100, "bf16", r, 10.0, None)
     assert res["sides"]["V"]["bound_spec"] == "hbm" and res["sides"]["U"]["bound_spec"] == "valu"
 
