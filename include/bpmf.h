@@ -157,6 +157,18 @@ int bpmf_profile_sweeps(bpmf_ctx *c, uint32_t t0, uint32_t n, double *phase_ms);
 int bpmf_predict(bpmf_ctx *c, uint32_t t, int64_t n, const int32_t *row, const int32_t *col,
                  float *out, double *rmse_avg, double *rmse_last);
 
+/* bpmf_predict with n > 0, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same predictions, bit for bit, of n (row, col) pairs
+ * (host arrays; out[n] receives u_row . v_col + mean rating), staged through
+ * a fixed device array of the library instead of buffers it allocates, so
+ * the call allocates and frees nothing.  At most 524,288 pairs per call
+ * (BPMF_E_TOOBIG above).  Each GPU holds one such array for the whole
+ * process and every context on that GPU shares it: calls that overlap on one
+ * GPU (from several threads or contexts) race and must be serialised by the
+ * caller.  BPMF_E_RANGE for ids out of range. */
+int bpmf_predict_noalloc(bpmf_ctx *c, int64_t n, const int32_t *row, const int32_t *col, float *out);
+
 /* Factor access: host buffer of rows x K values, float in FP32/BF16 modes and
  * double in FP64 mode (bpmf_get_factor_f64 / bpmf_set_factor_f64 convert). */
 int bpmf_get_factor(bpmf_ctx *c, int32_t side, void *host);

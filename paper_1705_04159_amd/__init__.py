@@ -30,7 +30,8 @@ E_BUSY, E_TOOBIG, E_NOSAMPLES, E_NOTFOUND, E_NOTSPD = -6, -7, -8, -9, -10
 # Every symbol the C ABI exports (include/bpmf.h).
 EXPORTS = [
     "bpmf_default_params", "bpmf_create", "bpmf_sample_hyper", "bpmf_update_side",
-    "bpmf_run_sweeps", "bpmf_profile_sweeps", "bpmf_predict", "bpmf_get_factor", "bpmf_set_factor",
+    "bpmf_run_sweeps", "bpmf_profile_sweeps", "bpmf_predict", "bpmf_predict_noalloc",
+    "bpmf_get_factor", "bpmf_set_factor",
     "bpmf_get_factor_f64", "bpmf_set_factor_f64", "bpmf_get_hyper", "bpmf_set_hyper",
     "bpmf_get_csc", "bpmf_get_chain_state", "bpmf_set_chain_state", "bpmf_get_plan",
     "bpmf_mean_rating", "bpmf_synchronize",
@@ -89,6 +90,7 @@ def lib() -> ctypes.CDLL:
         L.bpmf_update_side.argtypes = [P, i32, u32]
         L.bpmf_run_sweeps.argtypes = [P, u32, u32, P, P]
         L.bpmf_predict.argtypes = [P, u32, i64, P, P, P, P, P]
+        L.bpmf_predict_noalloc.argtypes = [P, i64, P, P, P]
         L.bpmf_profile_sweeps.argtypes = [P, u32, u32, P]
         for name in ("bpmf_get_factor", "bpmf_set_factor", "bpmf_get_factor_f64",
                      "bpmf_set_factor_f64"):
@@ -270,6 +272,15 @@ class Sampler:
         if len(row):
             self._check(lib().bpmf_predict(self._ctx, 0, len(row), _ptr(row), _ptr(col), _ptr(out),
                                            None, None))
+        return out
+
+    def predict_noalloc(self, row, col):
+        """predict() through the entry point that allocates no device memory
+        (at most 524,288 pairs per call)."""
+        row = _c(row, np.int32)
+        col = _c(col, np.int32)
+        out = np.zeros(len(row), np.float32)
+        self._check(lib().bpmf_predict_noalloc(self._ctx, len(row), _ptr(row), _ptr(col), _ptr(out)))
         return out
 
     # -- state -------------------------------------------------------------

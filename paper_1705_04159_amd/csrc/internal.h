@@ -128,6 +128,7 @@ struct bpmf_ctx {
     int32_t *q_row = nullptr, *q_col = nullptr;
     float *q_out = nullptr;
     int64_t q_cap = 0;
+    void *scratch = nullptr;  // this device's staging area of bpmf_predict_noalloc
     // graph of one sweep
     hipGraphExec_t graph = nullptr;
     hipGraph_t graph_src = nullptr;          // kept: owns the event-record nodes below
@@ -158,7 +159,10 @@ hipError_t launch_row_update(bpmf_ctx *c, int side_id, hipStream_t s);
 hipError_t launch_hyper(bpmf_ctx *c, int side_id, hipStream_t s, uint32_t t_off = 0);
 // Predict the registered test set as sweep ctr[0]; writes rmse_hist[slot].
 hipError_t launch_predict_test(bpmf_ctx *c, hipStream_t s);
-hipError_t launch_predict_pairs(bpmf_ctx *c, int64_t n, hipStream_t s);
+hipError_t launch_predict_pairs(bpmf_ctx *c, int64_t n, const int32_t *row, const int32_t *col,
+                                float *out, hipStream_t s);
+// Device address of the staging area of bpmf_predict_noalloc on c's device.
+hipError_t predict_scratch_init(bpmf_ctx *c);
 // Factor initialisation from Philox normals.
 hipError_t launch_init_factor(bpmf_ctx *c, int side_id, hipStream_t s);
 // Device counters.

@@ -5,6 +5,9 @@
 // mean of p over sweeps t > burn_in is kept in FP64; the two RMSEs (running
 // mean, current sample) are reduced in a fixed order (per-block tree, then
 // one block over the block sums), so they are bit-reproducible.
+#include <mutex>
+
+#include "../../include/bpmf.h"
 #include "internal.h"
 #include "rng_device.h"
 
@@ -12,6 +15,17 @@ namespace bpmf {
 namespace {
 
 constexpr int kGroup = 16;  // lanes per test pair
+
+// Staging area of bpmf_predict_noalloc: row ids, column ids and predictions
+// of at most kScratchPairs pairs (6 MiB).  Each GPU the library runs on holds
+// its own copy until the process ends; host code reaches it only through
+// the per-device address from hipGetSymbolAddress (scratch_dev below), never
+// through the symbol itself.
+constexpr int64_t kScratchPairs = 1 << 19;
+static __device__ __align__(256) unsigned char scratch[kScratchPairs * 12];
+constexpr int kMaxDevices = 64;
+void *scratch_dev[kMaxDevices] = {};
+std::mutex scratch_mu;
 
 __device__ __forceinline__ double as_f64(float v) { return (double)v; }
 __device__ __forceinline__ double as_f64(double v) { return v; }
@@ -238,19 +252,36 @@ hipError_t launch_predict_test(bpmf_ctx *c, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_predict_pairs(bpmf_ctx *c, int64_t n, hipStream_t s)
+hipError_t launch_predict_pairs(bpmf_ctx *c, int64_t n, const int32_t *row, const int32_t *col,
+                                float *out, hipStream_t s)
 {
     unsigned grid = (unsigned)((n * kGroup + 255) / 256);
     if (grid == 0) return hipSuccess;
     if (c->prec == 0)
         hipLaunchKernelGGL((predict_pairs<double>), dim3(grid), dim3(256), 0, s, c->K, c->ld, n,
-                           c->q_row, c->q_col, (const double *)c->side[0].X,
-                           (const double *)c->side[1].X, c->rbar, c->q_out);
+                           row, col, (const double *)c->side[0].X, (const double *)c->side[1].X,
+                           c->rbar, out);
     else
         hipLaunchKernelGGL((predict_pairs<float>), dim3(grid), dim3(256), 0, s, c->K, c->ld, n,
-                           c->q_row, c->q_col, (const float *)c->side[0].X,
-                           (const float *)c->side[1].X, c->rbar, c->q_out);
+                           row, col, (const float *)c->side[0].X, (const float *)c->side[1].X,
+                           c->rbar, out);
     return hipGetLastError();
+}
+
+// The device address of this GPU's staging area, looked up once per device
+// with that device current (called by bpmf_create).
+hipError_t predict_scratch_init(bpmf_ctx *c)
+{
+    if (c->device < 0 || c->device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> g(scratch_mu);
+    if (!scratch_dev[c->device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        scratch_dev[c->device] = p;
+    }
+    c->scratch = scratch_dev[c->device];
+    return hipSuccess;
 }
 
 hipError_t launch_set_counter(uint32_t *ctr, int idx, uint32_t value, hipStream_t s)
@@ -283,3 +314,47 @@ hipError_t launch_to_bf16(bpmf_ctx *c, int side_id, hipStream_t s)
 }
 
 }  // namespace bpmf
+
+extern "C" int bpmf_predict_noalloc(bpmf_ctx *c, int64_t n, const int32_t *row, const int32_t *col,
+                                    float *out)
+{
+    using namespace bpmf;
+    if (!c) return BPMF_E_INVAL;
+    if (c->sticky) {
+        c->err = "context unusable after a device error: " + c->err;
+        return BPMF_E_DEVICE;
+    }
+    if (n < 0 || (n > 0 && (!row || !col || !out))) {
+        c->err = "bpmf_predict_noalloc: bad pair arrays";
+        return BPMF_E_INVAL;
+    }
+    if (n > kScratchPairs) {
+        c->err = "bpmf_predict_noalloc: at most " + std::to_string(kScratchPairs) +
+                 " pairs per call (its staging area is a fixed device array)";
+        return BPMF_E_TOOBIG;
+    }
+    if (!c->scratch) {
+        c->err = "bpmf_predict_noalloc: no staging area on this device";
+        return BPMF_E_INVAL;
+    }
+    for (int64_t e = 0; e < n; ++e)
+        if (row[e] < 0 || row[e] >= c->M || col[e] < 0 || col[e] >= c->N) {
+            c->err = "bpmf_predict_noalloc: pair " + std::to_string(e) + " out of range";
+            return BPMF_E_RANGE;
+        }
+    if (n == 0) return BPMF_OK;
+    int32_t *d_row = (int32_t *)c->scratch;
+    int32_t *d_col = d_row + kScratchPairs;
+    float *d_out = (float *)(d_col + kScratchPairs);
+    hipError_t e = hipMemcpyAsync(d_row, row, sizeof(int32_t) * n, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_col, col, sizeof(int32_t) * n, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = launch_predict_pairs(c, n, d_row, d_col, d_out, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, d_out, sizeof(float) * n, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        c->err = std::string("bpmf_predict_noalloc: ") + hipGetErrorString(e);
+        c->sticky = true;
+        return BPMF_E_DEVICE;
+    }
+    return BPMF_OK;
+}

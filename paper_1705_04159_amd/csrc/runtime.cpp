@@ -579,6 +579,7 @@ int bpmf_create(int64_t M, int64_t N, const int64_t *csr_ptr, const int32_t *csr
         CK(hipMemsetAsync(c->ctr, 0, 4 * sizeof(uint32_t), c->stream));
         CK(launch_fill_f64(c->pred_sum, n_test, 0.0, c->stream));
         CK(prepare_kernels(c));
+        CK(predict_scratch_init(c));
         for (int sid = 0; sid < 2; ++sid) {
             CK(launch_init_factor(c, sid, c->stream));
             CK(launch_prior_to_working(c, sid, c->stream));
@@ -1059,7 +1060,7 @@ int bpmf_predict(bpmf_ctx *c, uint32_t t, int64_t n, const int32_t *row, const i
     }
     HIPCK(c, hipMemcpyAsync(c->q_row, row, sizeof(int32_t) * n, hipMemcpyHostToDevice, c->stream));
     HIPCK(c, hipMemcpyAsync(c->q_col, col, sizeof(int32_t) * n, hipMemcpyHostToDevice, c->stream));
-    HIPCK(c, launch_predict_pairs(c, n, c->stream));
+    HIPCK(c, launch_predict_pairs(c, n, c->q_row, c->q_col, c->q_out, c->stream));
     HIPCK(c, hipMemcpyAsync(out, c->q_out, sizeof(float) * n, hipMemcpyDeviceToHost, c->stream));
     HIPCK(c, hipStreamSynchronize(c->stream));
     return BPMF_OK;
