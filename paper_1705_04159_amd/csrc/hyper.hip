@@ -13,8 +13,9 @@
 // row-major order), then mu = mu* + chol(beta* Lambda)^-T z.
 //
 // Three launches: per-block FP64 moment sums over row chunks (S is formed as
-// sum x x^T - n xbar xbar^T; on the FP64 matrix cores for K <= 112), a fixed-order reduction of the block sums (one
-// wavefront per entry), and one workgroup for the K x K algebra.  The
+// sum x x^T - n xbar xbar^T; on the FP64 matrix cores for K <= 112), a
+// fixed-order reduction of the block sums (coalesced over entries), and one
+// workgroup for the K x K algebra.  The
 // algebra avoids forming W* and two of the three factorisations:
 //   * L_W is obtained from one Cholesky of the index-reversed W*^-1:
 //     J W*^-1 J = C C^T gives W*^-1 = (J C J)(J C J)^T with J C J upper
@@ -33,7 +34,8 @@
 namespace bpmf {
 namespace {
 
-constexpr int kThreads = 256;
+constexpr int kThreads = 256;      // moment sums (non-matrix-core path)
+constexpr int kDrawThreads = 1024;  // the K x K algebra of the draw (one workgroup)
 
 __device__ __forceinline__ int pk(int i, int j) { return i * (i + 1) / 2 + j; }
 
@@ -127,13 +129,23 @@ __global__ __launch_bounds__(64) void hyper_moments_mfma(int K, const XT *__rest
     double sx[NB];
 #pragma unroll
     for (int bi = 0; bi < NB; ++bi) sx[bi] = 0.0;
-    for (int64_t base = r0; base < r1; base += 4) {
+    // rows of the next step are loaded while this step's products run
+    auto load = [&](int64_t base, XT (&y)[NB]) {
         const int64_t r = base + kq;
-        double y[NB];
 #pragma unroll
         for (int bi = 0; bi < NB; ++bi) {
             const int c = 16 * bi + col;
-            y[bi] = (r < r1 && c < K) ? as_f64(X[(size_t)r * ld + c]) : 0.0;
+            y[bi] = (r < r1 && c < K) ? X[(size_t)r * ld + c] : XT(0);
+        }
+    };
+    XT ycur[NB], ynext[NB];
+    load(r0, ycur);
+    for (int64_t base = r0; base < r1; base += 4) {
+        load(base + 4, ynext);
+        double y[NB];
+#pragma unroll
+        for (int bi = 0; bi < NB; ++bi) {
+            y[bi] = as_f64(ycur[bi]);
             sx[bi] += y[bi];
         }
         int q = 0;
@@ -144,6 +156,8 @@ __global__ __launch_bounds__(64) void hyper_moments_mfma(int K, const XT *__rest
                 acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(y[bi], y[bj], acc[q], 0, 0, 0);
                 ++q;
             }
+#pragma unroll
+        for (int bi = 0; bi < NB; ++bi) ycur[bi] = ynext[bi];
     }
     double *dst = part + (size_t)blockIdx.x * E;
 #pragma unroll
@@ -169,19 +183,31 @@ __global__ __launch_bounds__(64) void hyper_moments_mfma(int K, const XT *__rest
         }
 }
 
-// stats[e] = sum over blocks of part[b][e]: one wavefront per entry, lane l
-// sums blocks l, l+64, ... in order, then a fixed butterfly across lanes.
-__global__ __launch_bounds__(256) void hyper_reduce(int E, int nblk, const double *__restrict__ part,
-                                                   double *__restrict__ stats)
+// stats[e] = sum over blocks of part[b][e], in a fixed order: workgroup w
+// takes entries 64 w .. 64 w + 63 (lane l entry 64 w + l, so every load of a
+// wave is 512 contiguous bytes), wave v of its 16 sums blocks
+// v, v + 16, v + 32, ..., and the 16 wave sums are added in wave order.
+constexpr int kRedWaves = 16;
+__global__ __launch_bounds__(64 * kRedWaves) void hyper_reduce(int E, int nblk,
+                                                               const double *__restrict__ part,
+                                                               double *__restrict__ stats)
 {
+    __shared__ double ws[kRedWaves][64];
     const int lane = threadIdx.x & 63;
-    const int e = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (e >= E) return;
+    const int v = threadIdx.x >> 6;
+    const int e = blockIdx.x * 64 + lane;
     double s = 0.0;
-    for (int b = lane; b < nblk; b += 64) s += part[(size_t)b * E + e];
+    if (e < E)
+#pragma unroll 4
+        for (int b = v; b < nblk; b += kRedWaves) s += part[(size_t)b * E + e];
+    ws[v][lane] = s;
+    __syncthreads();
+    if (v == 0 && e < E) {
+        double t = 0.0;
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-    if (lane == 0) stats[e] = s;
+        for (int q = 0; q < kRedWaves; ++q) t += ws[q][lane];
+        stats[e] = t;
+    }
 }
 
 // In-place Cholesky of a packed lower K x K matrix (K <= 128) by the whole
@@ -194,28 +220,25 @@ __device__ void chol_packed(int K, double *P, int *ok)
 {
     __shared__ double root[128];
     const int tid = threadIdx.x;
-    for (int k = 0; k < K; ++k) {
+    const int ti = tid & 31, tj = tid >> 5;  // a 32 x 32 tiling of the trailing triangle
+    for (int k = 0; k + 1 < K; ++k) {
         double d = P[pk(k, k)];
         if (!(d > 0.0)) d = 1.0;
         const double rd = 1.0 / d;
-        const int m = K - k - 1;
-        const int n = m * (m + 1) / 2;
-        for (int q = tid; q < n; q += kThreads) {
-            int ii, jj;
-            tri_index(q, ii, jj);
-            const int i = k + 1 + ii, j = k + 1 + jj;
-            P[pk(i, j)] -= P[pk(i, k)] * P[pk(j, k)] * rd;
+        for (int i = k + 1 + ti; i < K; i += 32) {
+            const double pik = P[pk(i, k)] * rd;
+            for (int j = k + 1 + tj; j <= i; j += 32) P[pk(i, j)] -= pik * P[pk(j, k)];
         }
         __syncthreads();
     }
-    for (int k = tid; k < K; k += kThreads) {
+    for (int k = tid; k < K; k += kDrawThreads) {
         const double d = P[pk(k, k)];
         if (!(d > 0.0)) *ok = 0;
         root[k] = sqrt(d > 0.0 ? d : 1.0);
     }
     __syncthreads();
     const int KK2 = K * (K + 1) / 2;
-    for (int e = tid; e < KK2; e += kThreads) {
+    for (int e = tid; e < KK2; e += kDrawThreads) {
         int i, j;
         tri_index(e, i, j);
         P[e] = i == j ? root[j] : P[e] / root[j];
@@ -231,23 +254,23 @@ __device__ void tri_inverse_packed(int K, const double *C, double *Xp)
 {
     const int tid = threadIdx.x;
     const int KK2 = K * (K + 1) / 2;
-    for (int e = tid; e < KK2; e += kThreads) {
+    for (int e = tid; e < KK2; e += kDrawThreads) {
         int i, j;
         tri_index(e, i, j);
         Xp[e] = i == j ? 1.0 : 0.0;
     }
     __syncthreads();
+    const int ti = tid & 31, tj = tid >> 5;  // a 32 x 32 tiling of rows i > k, columns j <= k
     for (int k = 0; k < K - 1; ++k) {
         const double rck = 1.0 / C[pk(k, k)];
         // rows i > k: X[i][j] -= C[i][k] X[k][j] / C[k][k], j <= k
-        const int rows = K - k - 1, cols = k + 1;
-        for (int q = tid; q < rows * cols; q += kThreads) {
-            const int i = k + 1 + q / cols, j = q - (q / cols) * cols;
-            Xp[pk(i, j)] -= C[pk(i, k)] * Xp[pk(k, j)] * rck;
+        for (int i = k + 1 + ti; i < K; i += 32) {
+            const double cik = C[pk(i, k)] * rck;
+            for (int j = tj; j <= k; j += 32) Xp[pk(i, j)] -= cik * Xp[pk(k, j)];
         }
         __syncthreads();
     }
-    for (int e = tid; e < KK2; e += kThreads) {
+    for (int e = tid; e < KK2; e += kDrawThreads) {
         int i, j;
         tri_index(e, i, j);
         Xp[e] /= C[pk(i, i)];
@@ -256,7 +279,7 @@ __device__ void tri_inverse_packed(int K, const double *C, double *Xp)
 }
 
 template <typename T>
-__global__ __launch_bounds__(kThreads) void hyper_draw(
+__global__ __launch_bounds__(kDrawThreads) void hyper_draw(
     int K, int64_t n, const double *__restrict__ stats, const double *__restrict__ mu0,
     const double *__restrict__ W0inv, double beta0, double nu0, uint64_t seed, uint32_t stream,
     const uint32_t *__restrict__ ctr, uint32_t t_off, double *__restrict__ gbuf, int n_lds_bufs,
@@ -281,13 +304,13 @@ __global__ __launch_bounds__(kThreads) void hyper_draw(
     const double nu_s = nu0 + dn;
     const double shrink = beta0 * dn / beta_s;
     if (tid == 0) ok = 1;
-    for (int k = tid; k < K; k += kThreads) {
+    for (int k = tid; k < K; k += kDrawThreads) {
         xbar[k] = stats[k] / dn;
         mus[k] = (beta0 * mu0[k] + dn * xbar[k]) / beta_s;
     }
     __syncthreads();
     // J W*^-1 J, packed: entry (i, j), i >= j, is W*^-1[K-1-j][K-1-i]
-    for (int e = tid; e < KK2; e += kThreads) {
+    for (int e = tid; e < KK2; e += kDrawThreads) {
         int a, b;
         tri_index(e, a, b);  // W*^-1 entry (a, b), a >= b
         const double S = stats[K + e] - dn * xbar[a] * xbar[b];
@@ -298,12 +321,12 @@ __global__ __launch_bounds__(kThreads) void hyper_draw(
     chol_packed(K, Cm, &ok);
     tri_inverse_packed(K, Cm, Ci);
     // Bartlett factor A (reuses Cm)
-    for (int e = tid; e < KK2; e += kThreads) Cm[e] = 0.0;
+    for (int e = tid; e < KK2; e += kDrawThreads) Cm[e] = 0.0;
     __syncthreads();
-    for (int k = tid; k < K; k += kThreads)
+    for (int k = tid; k < K; k += kDrawThreads)
         Cm[pk(k, k)] = sqrt(chi_square(seed, stream, t, (uint32_t)k, nu_s - (double)k, &ok));
     const int n_low = K * (K - 1) / 2;
-    for (int blk = tid; 4 * blk < n_low; blk += kThreads) {
+    for (int blk = tid; 4 * blk < n_low; blk += kDrawThreads) {
         double z[4];
         normals_block(seed, (uint32_t)blk, t, stream, 1u, 0u, z);
         for (int l = 0; l < 4 && 4 * blk + l < n_low; ++l) {
@@ -314,7 +337,7 @@ __global__ __launch_bounds__(kThreads) void hyper_draw(
     }
     __syncthreads();
     // B = L_W A, L_W[r][m] = C^-1[K-1-m][K-1-r]
-    for (int e = tid; e < KK2; e += kThreads) {
+    for (int e = tid; e < KK2; e += kDrawThreads) {
         int r, c;
         tri_index(e, r, c);
         double s = 0.0;
@@ -323,7 +346,7 @@ __global__ __launch_bounds__(kThreads) void hyper_draw(
     }
     __syncthreads();
     // Lambda = B B^T
-    for (int e = tid; e < KK2; e += kThreads) {
+    for (int e = tid; e < KK2; e += kDrawThreads) {
         int r, c;
         tri_index(e, r, c);
         double s = 0.0;
@@ -333,7 +356,7 @@ __global__ __launch_bounds__(kThreads) void hyper_draw(
         Lam_w[r * K + c] = (T)s;
         Lam_w[c * K + r] = (T)s;
     }
-    for (int blk = tid; 4 * blk < K; blk += kThreads) {
+    for (int blk = tid; 4 * blk < K; blk += kDrawThreads) {
         double z[4];
         normals_block(seed, (uint32_t)blk, t, stream, 2u, 0u, z);
         for (int l = 0; l < 4 && 4 * blk + l < K; ++l) zv[4 * blk + l] = z[l];
@@ -344,35 +367,35 @@ __global__ __launch_bounds__(kThreads) void hyper_draw(
     // the divisions are applied to zv at the end
     for (int i = K - 1; i > 0; --i) {
         const double xi = zv[i] / Bm[pk(i, i)];
-        for (int j = tid; j < i; j += kThreads) zv[j] -= Bm[pk(i, j)] * xi;
+        for (int j = tid; j < i; j += kDrawThreads) zv[j] -= Bm[pk(i, j)] * xi;
         __syncthreads();
     }
-    for (int i = tid; i < K; i += kThreads) zv[i] /= Bm[pk(i, i)];
+    for (int i = tid; i < K; i += kDrawThreads) zv[i] /= Bm[pk(i, i)];
     __syncthreads();
     const double rs = 1.0 / sqrt(beta_s);
-    for (int k = tid; k < K; k += kThreads) {
+    for (int k = tid; k < K; k += kDrawThreads) {
         mu[k] = mus[k] + zv[k] * rs;
         mu_out[k] = mu[k];
     }
     __syncthreads();
     // Lambda mu from the packed factor: Lambda mu = B (B^T mu)
-    for (int i = tid; i < K; i += kThreads) {
+    for (int i = tid; i < K; i += kDrawThreads) {
         double s = 0.0;
         for (int j = i; j < K; ++j) s += Bm[pk(j, i)] * mu[j];
         zv[i] = s;  // B^T mu
     }
     __syncthreads();
-    for (int i = tid; i < K; i += kThreads) {
+    for (int i = tid; i < K; i += kDrawThreads) {
         double s = 0.0;
         for (int j = 0; j <= i; ++j) s += Bm[pk(i, j)] * zv[j];
         Lmu_w[i] = (T)s;
     }
     if (Linv_w) {
         // for the rank-one row path: chol(Lambda)^-1 = B^-1 and B^T mu
-        for (int i = tid; i < K; i += kThreads) Ltmu_w[i] = (T)zv[i];
+        for (int i = tid; i < K; i += kDrawThreads) Ltmu_w[i] = (T)zv[i];
         __syncthreads();
         tri_inverse_packed(K, Bm, Ci);
-        for (int e = tid; e < K * K; e += kThreads) {
+        for (int e = tid; e < K * K; e += kDrawThreads) {
             const int r = e / K, cc = e - (e / K) * K;
             Linv_w[e] = cc <= r ? (T)Ci[pk(r, cc)] : (T)0;
         }
@@ -383,7 +406,7 @@ __global__ __launch_bounds__(kThreads) void hyper_draw(
 // For the rank-one row path after (mu, Lambda) were set by the host:
 // chol(Lambda)^-1 and chol(Lambda)^T mu, FP64 in one workgroup.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void prior_factor(int K, const double *__restrict__ mu,
+__global__ __launch_bounds__(kDrawThreads) void prior_factor(int K, const double *__restrict__ mu,
                                                          const double *__restrict__ Lam,
                                                          T *__restrict__ Linv_w, T *__restrict__ Ltmu_w,
                                                          int *__restrict__ status)
@@ -395,7 +418,7 @@ __global__ __launch_bounds__(kThreads) void prior_factor(int K, const double *__
     __shared__ int ok;
     const int tid = threadIdx.x;
     if (tid == 0) ok = 1;
-    for (int e = tid; e < KK2; e += kThreads) {
+    for (int e = tid; e < KK2; e += kDrawThreads) {
         int r, c;
         tri_index(e, r, c);
         P[e] = Lam[r * K + c];
@@ -403,11 +426,11 @@ __global__ __launch_bounds__(kThreads) void prior_factor(int K, const double *__
     __syncthreads();
     chol_packed(K, P, &ok);
     tri_inverse_packed(K, P, Ci);
-    for (int e = tid; e < K * K; e += kThreads) {
+    for (int e = tid; e < K * K; e += kDrawThreads) {
         const int r = e / K, cc = e - (e / K) * K;
         Linv_w[e] = cc <= r ? (T)Ci[pk(r, cc)] : (T)0;
     }
-    for (int i = tid; i < K; i += kThreads) {
+    for (int i = tid; i < K; i += kDrawThreads) {
         double s = 0.0;
         for (int j = i; j < K; ++j) s += P[pk(j, i)] * mu[j];
         Ltmu_w[i] = (T)s;
@@ -495,17 +518,17 @@ hipError_t launch_hyper(bpmf_ctx *c, int side_id, hipStream_t s, uint32_t t_off)
         else if (ne <= 21) launch_moments<21>(c, sd, part, used, chunk, s);
         else launch_moments<33>(c, sd, part, used, chunk, s);
     }
-    hipLaunchKernelGGL(hyper_reduce, dim3((E + 3) / 4), dim3(256), 0, s, E, used, part, stats);
+    hipLaunchKernelGGL(hyper_reduce, dim3((E + 63) / 64), dim3(64 * kRedWaves), 0, s, E, used, part, stats);
     const int nb = lds_buffers(K, c->hyp_lds_max);
     const size_t lds2 = draw_lds(K, nb);
     if (c->prec == 0)
-        hipLaunchKernelGGL((hyper_draw<double>), dim3(1), dim3(kThreads), lds2, s, K, rows,
+        hipLaunchKernelGGL((hyper_draw<double>), dim3(1), dim3(kDrawThreads), lds2, s, K, rows,
                            stats, c->d_mu0, c->d_W0inv, c->beta0, c->nu0, c->seed,
                            sd.stream_hyp, c->ctr, t_off, scratch, nb, sd.mu, sd.Lam,
                            (double *)sd.Lam_w, (double *)sd.Lmu_w, (double *)nullptr,
                            (double *)nullptr, c->hyp_status);
     else
-        hipLaunchKernelGGL((hyper_draw<float>), dim3(1), dim3(kThreads), lds2, s, K, rows,
+        hipLaunchKernelGGL((hyper_draw<float>), dim3(1), dim3(kDrawThreads), lds2, s, K, rows,
                            stats, c->d_mu0, c->d_W0inv, c->beta0, c->nu0, c->seed,
                            sd.stream_hyp, c->ctr, t_off, scratch, nb, sd.mu, sd.Lam,
                            (float *)sd.Lam_w, (float *)sd.Lmu_w,
@@ -540,7 +563,7 @@ hipError_t launch_prior_to_working(bpmf_ctx *c, int side_id, hipStream_t s)
     Side &sd = c->side[side_id];
     if (sd.n_low && c->prec == 1) {
         const size_t lds = sizeof(double) * (size_t)c->K * (c->K + 1);
-        hipLaunchKernelGGL((prior_factor<float>), dim3(1), dim3(kThreads), lds, s, c->K, sd.mu, sd.Lam,
+        hipLaunchKernelGGL((prior_factor<float>), dim3(1), dim3(kDrawThreads), lds, s, c->K, sd.mu, sd.Lam,
                            (float *)sd.Linv_w, (float *)sd.Ltmu_w, c->hyp_status);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;

@@ -12,17 +12,31 @@
 // of the 8 ratings 8*(l / 16) .. +7 of a 32-rating chunk; both accumulate in
 // FP32 and only the nb(nb+1)/2 lower 16x16 blocks of P are formed.
 //
-// Factorisation: blocked right-looking Cholesky with 16x16 blocks, the
-// trailing matrix kept in the MFMA accumulators.  For each block column kb:
-// the column goes to LDS; the diagonal block is factored column-per-lane
-// (16 lanes, pivot columns broadcast within each 16-lane row by DPP); every row below it,
-// and b's segment as one extra row, is solved against L_kk^T (one row per
-// lane; L_kk read by broadcast from LDS), which also yields y_kb = L_kk^-1 b_kb
-// and lets each row update b; the solved panel returns to the accumulators
-// (they end up holding L) and the trailing blocks are updated by
-// v_mfma_f32_16x16x4_f32 with the panel as both operands (negated A).
-// Back solve by block rows from the last, with the off-diagonal products
-// taken from the accumulators and reduced across lanes.
+// Storage: the accumulators hold the upper 16 x 16 blocks of the symmetric
+// matrix -- block (i, j), i >= j, keeps T[16 j + r][16 i + c] (block row j,
+// block column i) in the MFMA result layout, lane (g, c) rows r = 4g .. 4g+3
+// of column c -- which the Gram forms directly by taking the block-column
+// operand first.  In that storage both operands of every product the
+// factorisation needs come straight from the registers.
+//
+// Factorisation: blocked right-looking Cholesky P = L L^T with 16 x 16
+// blocks, by block rows of R = L^T.  For each block row kb:
+//   - the diagonal block: column c of it is copied to every 16-lane row of
+//     lanes (through LDS) and eliminated column by column without square
+//     roots (column c > k takes -f_c times column k, f_c = P[k][c] / P[k][k],
+//     column k's entry in the lane's own row coming from lane k of the row
+//     by a DPP broadcast); the same column operations on the identity give
+//     G = L_unit^-T (row r of G takes over row r's register once row r has
+//     served as pivot row), so X = L_kk^-1 = D^-1/2 G^T is at hand, each lane
+//     holding the A operand X[c][4g + v] of the products below; b's segment
+//     rides along as one more row and yields y_kb = L_kk^-1 b_kb;
+//   - the rest of the block row: R_kb,i = X T_kb,i on the matrix cores
+//     (v_mfma_f32_16x16x4_f32, T_kb,i as the B operand straight from the
+//     accumulators), and b_i -= L_i,kb y_kb;
+//   - the trailing blocks: T_j,i -= R_kb,j^T R_kb,i on the matrix cores, both
+//     operands straight from the accumulators (the first negated).
+// Back solve x = L^-T w by block rows from the last, as products with the
+// stored R and X and 16-lane reductions: no serial chain.
 //
 // Noise as in the other row kernels: Philox4x32-10 normal c of the row from
 // block c/4 of counter (row, t, stream<<24 | block, 0), Box-Muller in FP32.
@@ -49,13 +63,17 @@ constexpr int big_waves()
     return NB <= 3 ? 4 : (NB == 4 ? 3 : 2);
 }
 
+// Per-wave LDS (floats): X = L_kk^-1 of every block row in the A-operand
+// layout (one float4 per lane); a column-major copy of the current diagonal
+// block (column stride kDS); the rhs b (becomes y), w and x.
+constexpr int kDS = 20;
 template <int NB>
 struct BigLds {
-    static constexpr int PAN = NB * 16 * kPS;  // block column kb, rows of all blocks below
-    static constexpr int LDG = 256;            // L_kk, row-major 16 x 16
-    static constexpr int INVD = 16;            // 1 / L_kk[c][c]
-    static constexpr int VEC = 128;            // b (becomes y), w, x
-    static constexpr int TOTAL = PAN + LDG + INVD + 3 * VEC;
+    static constexpr int XS = NB * 256;
+    static constexpr int DG = 16 * kDS;
+    static constexpr int VEC = 16 * NB;
+    static constexpr int BV = XS + DG;  // offset of b
+    static constexpr int TOTAL = XS + DG + 3 * VEC;
 };
 
 __device__ __forceinline__ void wave_sync()
@@ -71,7 +89,8 @@ __device__ __forceinline__ uint32_t buf_u16(__amdgpu_buffer_rsrc_t r, uint32_t o
 }
 
 // Gram and rhs of one work item from BF16 rows (whole wave).  Chunks of 32
-// ratings; lane l takes ratings 8*(l/16) + e, e = 0..7, of each chunk.
+// ratings; lane l takes ratings 8*(l/16) + e, e = 0..7, of each chunk.  The
+// blocks are accumulated as upper blocks (block (bi, bj) holds (bj, bi)).
 template <int NB>
 __device__ __forceinline__ void gram_item_bf16(const RowItem &it, const int32_t *__restrict__ nbr,
                                                const float *__restrict__ rc,
@@ -115,7 +134,7 @@ __device__ __forceinline__ void gram_item_bf16(const RowItem &it, const int32_t 
         for (int bi = 0; bi < NB; ++bi) {
 #pragma unroll
             for (int bj = 0; bj <= bi; ++bj) {
-                acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(y[bi], y[bj], acc[q], 0, 0, 0);
+                acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(y[bj], y[bi], acc[q], 0, 0, 0);  // upper block (bj, bi)
                 ++q;
             }
             float s = 0.f;
@@ -126,12 +145,20 @@ __device__ __forceinline__ void gram_item_bf16(const RowItem &it, const int32_t 
     }
 }
 
+// Sum over the 16 lanes of each 16-lane row, left in lane 15 of the row
+// (inclusive prefix sums by DPP row shifts with zero fill).
+__device__ __forceinline__ float row_sum16(float x)
+{
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x111, 0xf, 0xf, true));
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x112, 0xf, 0xf, true));
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x114, 0xf, 0xf, true));
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x118, 0xf, 0xf, true));
+    return x;
+}
+
 // Blocked factorisation and draw for one row held in the accumulators (raw
-// Gram) and b in LDS (b = alpha * rhs + Lambda mu already).  Writes x_c.
-//
-// Register budget: the accumulators (nb(nb+1)/2 x 4) plus a few dozen
-// temporaries; every step works through LDS with a small working set so
-// that two waves fit per SIMD at K = 100.
+// Gram, upper blocks) and b in LDS (b = alpha * rhs + Lambda mu already).
+// Writes x_c.  A non-positive pivot of a real column clears *status.
 template <int NB>
 __device__ __forceinline__ void blocked_chol_sample(floatx4 (&acc)[NB * (NB + 1) / 2], float *lds,
                                                     int K, float alpha,
@@ -140,21 +167,19 @@ __device__ __forceinline__ void blocked_chol_sample(floatx4 (&acc)[NB * (NB + 1)
                                                     float *__restrict__ xrow, int *__restrict__ status)
 {
     using L = BigLds<NB>;
-    float *pan = lds;
-    float *ldg = pan + L::PAN;
-    float *invd = ldg + L::LDG;
-    float *bv = invd + L::INVD;
+    float *xs = lds;              // X of block row kb: float4 per lane at kb * 256 + 4 lane
+    float *dg = lds + L::XS;      // diagonal block, column-major
+    float *bv = lds + L::BV;      // b, overwritten by y block by block
     float *wv = bv + L::VEC;
     float *xv = wv + L::VEC;
     const int lane = threadIdx.x & 63;
     const int col = lane & 15;
     const int kq = lane >> 4;
 
-    // The accumulators hold the negated trailing matrix T = -(Lambda +
-    // alpha G - sum_k L_ik L_jk^T), so that the trailing updates
-    // T_ij += L_ik L_jk^T take the panel as both MFMA operands.  The prior
-    // comes from its image in the accumulator layout (identity on the
-    // padding), one float4 per block and lane.
+    // The accumulators hold the negated trailing matrix -(Lambda + alpha G -
+    // sum R^T R), so that every product below takes positive operands (the
+    // prior from its image in the same upper-block layout, identity on the
+    // padding)
 #pragma unroll
     for (int q = 0; q < NB * (NB + 1) / 2; ++q) {
         const floatx4 p = img[q * 64 + lane];
@@ -164,111 +189,95 @@ __device__ __forceinline__ void blocked_chol_sample(floatx4 (&acc)[NB * (NB + 1)
 
     static_for<0, NB>([&](auto kbc) {
         constexpr int kb = decltype(kbc)::value;
-        constexpr int R = 16 * (NB - 1 - kb);  // panel rows below the diagonal block
-        // (1) block column kb to LDS: pan row 16 (i - kb) + r holds row r of block i
+        constexpr int qd = kb * (kb + 1) / 2 + kb;
         __builtin_amdgcn_sched_barrier(0);
-        static_for<kb, NB>([&](auto ic) {
-            constexpr int i = decltype(ic)::value;
-            constexpr int q = i * (i + 1) / 2 + kb;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) pan[((i - kb) * 16 + 4 * kq + v) * kPS + col] = -acc[q][v];
-        });
+        // (1) column col of the diagonal block to every 16-lane row
+        *reinterpret_cast<float4 *>(dg + col * kDS + 4 * kq) =
+            float4{acc[qd][0], acc[qd][1], acc[qd][2], acc[qd][3]};
         wave_sync();
-        // (2) diagonal block column-per-lane (lane col holds column col; the
-        // four lane groups compute copies), with b's segment as an extra
-        // row so that the elimination also yields y_kb = L_kk^-1 b_kb
-        {
-            float d[16];
+        // u[r]: row r of column col of the block (d) until step r uses it as
+        // pivot row, then row r of column col of G (e; it is still the
+        // identity's until then)
+        float u[16];
 #pragma unroll
-            for (int r = 0; r < 16; ++r) d[r] = pan[r * kPS + col];
-            float db = bv[16 * kb + col];
-            float mydiag = 1.f;
-            static_for<0, 16>([&](auto kc) {
-                constexpr int k = decltype(kc)::value;
-                const float dk = bcast16<k>(d[k]);
+        for (int r4 = 0; r4 < 4; ++r4) {
+            const float4 v = *reinterpret_cast<const float4 *>(dg + col * kDS + 4 * r4);
+            u[4 * r4 + 0] = -v.x;
+            u[4 * r4 + 1] = -v.y;
+            u[4 * r4 + 2] = -v.z;
+            u[4 * r4 + 3] = -v.w;
+        }
+        float bc = bv[16 * kb + col];
+        // (2) eliminate columns k of the real part: column c > k takes -f_c
+        // times column k (rows > k of d, rows <= k of G -- the nonzero part
+        // of G's column k -- and b's row)
+        float mydiag = 1.f;
+        const int kreal = K - 16 * kb;
+        static_for<0, 16>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            if (k < kreal) {
+                const float dk = bcast16<k>(u[k]);
                 if (col == k) mydiag = dk;
-                // negated multiplier: each update is one v_fmac with a DPP operand
-                const float nf = col > k ? -d[k] * __builtin_amdgcn_rcpf(dk) : 0.f;
-                static_for<k + 1, 16>([&](auto rc) {
-                    constexpr int r = decltype(rc)::value;
-                    d[r] = __builtin_fmaf(bcast16<k>(d[r]), nf, d[r]);
-                });
-                db = __builtin_fmaf(bcast16<k>(db), nf, db);
-            });
-            if (kq == 0 && !(mydiag > 0.f)) *status = 0;  // P not positive definite in FP32
-            const float inv_s = __builtin_amdgcn_rsqf(mydiag);
-            if (kq == 0) {
-#pragma unroll
-                for (int r = 0; r < 16; ++r) ldg[r * 16 + col] = r >= col ? d[r] * inv_s : 0.f;
-                invd[col] = inv_s;
-                bv[16 * kb + col] = db * inv_s;  // y_kb
+                const float nf = col > k ? -u[k] * __builtin_amdgcn_rcpf(dk) : 0.f;
+                u[k] = col == k ? 1.f : 0.f;  // row k leaves d for G
+                fmac_bc_range<k, 0, 16>(u, nf);
+                fmac_bc1<k>(bc, nf);
             }
-        }
-        wave_sync();
-        // (3) rows below: solve x L_kk^T = a (one row per lane), store L_ik,
-        // and fold the row into b: b_r -= L_r,kb . y_kb
-        if constexpr (R > 0) {
-            for (int rr = lane; rr < R; rr += 64) {
-                float x[16];
-                const float *arow = pan + (16 + rr) * kPS;
-#pragma unroll
-                for (int cc = 0; cc < 16; ++cc) x[cc] = arow[cc];
-#pragma unroll
-                for (int cc = 0; cc < 16; ++cc) {
-                    const float4 *lrow = reinterpret_cast<const float4 *>(ldg + cc * 16);
-                    float sacc = x[cc];
-#pragma unroll
-                    for (int m4 = 0; m4 < (cc + 3) / 4; ++m4) {
-                        const float4 l4 = lrow[m4];
-                        if (4 * m4 + 0 < cc) sacc -= x[4 * m4 + 0] * l4.x;
-                        if (4 * m4 + 1 < cc) sacc -= x[4 * m4 + 1] * l4.y;
-                        if (4 * m4 + 2 < cc) sacc -= x[4 * m4 + 2] * l4.z;
-                        if (4 * m4 + 3 < cc) sacc -= x[4 * m4 + 3] * l4.w;
-                    }
-                    x[cc] = sacc * invd[cc];
-                }
-                float bd = 0.f;
-                const float4 *y4 = reinterpret_cast<const float4 *>(bv + 16 * kb);
-#pragma unroll
-                for (int m4 = 0; m4 < 4; ++m4) {
-                    const float4 yy = y4[m4];
-                    bd += x[4 * m4] * yy.x + x[4 * m4 + 1] * yy.y + x[4 * m4 + 2] * yy.z +
-                          x[4 * m4 + 3] * yy.w;
-                }
-                bv[16 * (kb + 1) + rr] -= bd;
-                float *wrow = pan + (16 + rr) * kPS;
-#pragma unroll
-                for (int cc = 0; cc < 16; ++cc) wrow[cc] = x[cc];
-            }
-        }
-        wave_sync();
-        // (4) L of block column kb back into its accumulators
-        static_for<kb, NB>([&](auto ic) {
-            constexpr int i = decltype(ic)::value;
-            constexpr int q = i * (i + 1) / 2 + kb;
-#pragma unroll
-            for (int v = 0; v < 4; ++v)
-                acc[q][v] = i == kb ? ldg[(4 * kq + v) * 16 + col]
-                                    : pan[((i - kb) * 16 + 4 * kq + v) * kPS + col];
         });
-        // (5) trailing update T_ij += L_i,kb L_j,kb^T on the matrix cores:
-        // lane (c, g) supplies L_i,kb[c][4s + g] for k-step s, which is the
-        // A operand of block row i and the B operand of block column i
-        if constexpr (R > 0) {
-            float op[NB][4];
-            static_for<kb + 1, NB>([&](auto ic) {
-                constexpr int i = decltype(ic)::value;
+        if (kreal < 16)  // rows of the padding: G is the identity there
 #pragma unroll
-                for (int s4 = 0; s4 < 4; ++s4) op[i][s4] = pan[((i - kb) * 16 + col) * kPS + 4 * s4 + kq];
-            });
+            for (int r = 0; r < 16; ++r)
+                if (r >= kreal) u[r] = col == r ? 1.f : 0.f;
+        // (3) pivots, y_kb, and X = L_kk^-1: lane (g, c) holds
+        // X[c][4g + v] = G[4g + v][c] / sqrt(pivot_c), the A operand of step v
+        if (kq == 0 && col < kreal && !(mydiag > 0.f)) *status = 0;  // P not positive definite in FP32
+        const float inv_s = __builtin_amdgcn_rsqf(mydiag);
+        float xa[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            float s = u[v];
+#pragma unroll
+            for (int g = 1; g < 4; ++g) s = kq == g ? u[4 * g + v] : s;
+            xa[v] = s * inv_s;
+        }
+        *reinterpret_cast<float4 *>(xs + kb * 256 + 4 * lane) = float4{xa[0], xa[1], xa[2], xa[3]};
+        if (kq == 0) bv[16 * kb + col] = bc * inv_s;  // y_kb
+        if constexpr (kb + 1 < NB) {
+            // (4) R_kb,i = X T_kb,i = (-X)(-T_kb,i) on the matrix cores
+            float nxa[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) nxa[v] = -xa[v];
             static_for<kb + 1, NB>([&](auto ic) {
                 constexpr int i = decltype(ic)::value;
+                constexpr int q = i * (i + 1) / 2 + kb;
+                floatx4 r = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int v = 0; v < 4; ++v) r = __builtin_amdgcn_mfma_f32_16x16x4f32(nxa[v], acc[q][v], r, 0, 0, 0);
+                acc[q] = r;
+            });
+            wave_sync();  // y_kb visible to every lane
+            // (5) b_i -= L_i,kb y_kb: (L_i,kb y)[c] = sum_m R_kb,i[m][c] y_m
+            const float4 y4 = *reinterpret_cast<const float4 *>(bv + 16 * kb + 4 * kq);
+            static_for<kb + 1, NB>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                constexpr int q = i * (i + 1) / 2 + kb;
+                float p = acc[q][0] * y4.x + acc[q][1] * y4.y + acc[q][2] * y4.z + acc[q][3] * y4.w;
+                p += __shfl_xor(p, 16);
+                p += __shfl_xor(p, 32);
+                if (kq == 0) bv[16 * i + col] -= p;
+            });
+            // (6) trailing blocks T_j,i -= R_kb,j^T R_kb,i, kb < j <= i (the
+            // negated T takes + R_kb,j^T R_kb,i)
+            static_for<kb + 1, NB>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                constexpr int qi = i * (i + 1) / 2 + kb;
                 static_for<kb + 1, i + 1>([&](auto jc) {
                     constexpr int j = decltype(jc)::value;
+                    constexpr int qj = j * (j + 1) / 2 + kb;
                     constexpr int q = i * (i + 1) / 2 + j;
 #pragma unroll
-                    for (int s4 = 0; s4 < 4; ++s4)
-                        acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(op[i][s4], op[j][s4], acc[q], 0, 0, 0);
+                    for (int v = 0; v < 4; ++v)
+                        acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(acc[qj][v], acc[qi][v], acc[q], 0, 0, 0);
                 });
             });
         }
@@ -290,36 +299,40 @@ __device__ __forceinline__ void blocked_chol_sample(floatx4 (&acc)[NB * (NB + 1)
         }
     }
     wave_sync();
-    // x = L^-T w by block rows from the last
+    // x = L^-T w by block rows from the last:
+    //   x_kb = X^T (w_kb - sum_{i > kb} R_kb,i x_i),
+    // (R_kb,i x_i)[m] = sum_c R_kb,i[m][c] x_i[c] and (X^T w')[m] =
+    // sum_c X[c][m] w'_c, both as 16-lane sums of per-lane products
     static_for<0, NB>([&](auto qc) {
         constexpr int kb = NB - 1 - decltype(qc)::value;
-        float part = 0.f;
+        float s[4] = {0.f, 0.f, 0.f, 0.f};
         static_for<kb + 1, NB>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
             constexpr int q = i * (i + 1) / 2 + kb;
+            const float xc = xv[16 * i + col];
 #pragma unroll
-            for (int v = 0; v < 4; ++v) part += acc[q][v] * xv[16 * i + 4 * kq + v];
+            for (int v = 0; v < 4; ++v) s[v] += acc[q][v] * xc;
         });
-        part += __shfl_xor(part, 16);
-        part += __shfl_xor(part, 32);
-        const float wc = wv[16 * kb + col] - part;
-        // L_kk column col from the accumulators via LDS
-        constexpr int qd = kb * (kb + 1) / 2 + kb;
+        if constexpr (kb + 1 < NB) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) ldg[(4 * kq + v) * 16 + col] = acc[qd][v];
-        wave_sync();
-        float d[16];
+            for (int v = 0; v < 4; ++v) s[v] = row_sum16(s[v]);
+            if (col == 15) {
+                float4 *p = reinterpret_cast<float4 *>(wv + 16 * kb + 4 * kq);
+                float4 o = *p;
+                o.x -= s[0];
+                o.y -= s[1];
+                o.z -= s[2];
+                o.w -= s[3];
+                *p = o;
+            }
+            wave_sync();
+        }
+        const float4 xa = *reinterpret_cast<const float4 *>(xs + kb * 256 + 4 * lane);
+        const float wc = wv[16 * kb + col];
+        float o[4] = {xa.x * wc, xa.y * wc, xa.z * wc, xa.w * wc};
 #pragma unroll
-        for (int r = 0; r < 16; ++r) d[r] = ldg[r * 16 + col];
-        const float inv = 1.0f / ldg[col * 16 + col];
-        float accx = 0.f, myx = 0.f;
-        static_for<0, 16>([&](auto rc) {
-            constexpr int r = 15 - decltype(rc)::value;
-            const float xr = bcast16<r>((wc - accx) * inv);
-            if (col == r) myx = xr;
-            if (col < r) accx += d[r] * xr;
-        });
-        if (lane < 16) xv[16 * kb + col] = myx;
+        for (int v = 0; v < 4; ++v) o[v] = row_sum16(o[v]);
+        if (col == 15) *reinterpret_cast<float4 *>(xv + 16 * kb + 4 * kq) = float4{o[0], o[1], o[2], o[3]};
         wave_sync();
     });
 #pragma unroll
@@ -388,7 +401,7 @@ __global__ __launch_bounds__(64 * kBigWPB, big_waves<NB>()) void row_big(
     if constexpr (BF16)
         gram_item_bf16<NB>(it, nbr, rc, ysrc, (uint32_t)ldy * 2u, lane_off, kq, acc, bacc);
     else
-        gram_item<NB>(it, nbr, rc, ysrc, (uint32_t)ldy * 4u, lane_off, kq, acc, bacc);
+        gram_item<NB, false, true>(it, nbr, rc, ysrc, (uint32_t)ldy * 4u, lane_off, kq, acc, bacc);
 #pragma unroll
     for (int bi = 0; bi < NB; ++bi) {
         bacc[bi] += __shfl_xor(bacc[bi], 16);
@@ -398,7 +411,7 @@ __global__ __launch_bounds__(64 * kBigWPB, big_waves<NB>()) void row_big(
         write_partial<NB>(acc, bacc, kq, col, part + (size_t)it.slot * big_slot_elems<NB>());
     } else {
         float *lds = smem_f + wave * BigLds<NB>::TOTAL;
-        float *bv = lds + BigLds<NB>::PAN + BigLds<NB>::LDG + BigLds<NB>::INVD;
+        float *bv = lds + BigLds<NB>::BV;
         if (kq == 0)
 #pragma unroll
             for (int bi = 0; bi < NB; ++bi) {
@@ -446,7 +459,7 @@ __global__ __launch_bounds__(64 * kBigWPB, big_waves<NB>()) void row_finish_big(
             if (c < 16 * NB) bs[h] += sq[NBLK * 256 + c];
         }
     }
-    float *bv = lds + BigLds<NB>::PAN + BigLds<NB>::LDG + BigLds<NB>::INVD;
+    float *bv = lds + BigLds<NB>::BV;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const int c = lane + 64 * h;
@@ -457,9 +470,9 @@ __global__ __launch_bounds__(64 * kBigWPB, big_waves<NB>()) void row_finish_big(
                             X + (size_t)f.row * ldx, status);
 }
 
-// The prior Lambda (identity on the padding) in the accumulator layout:
-// block q = i (i + 1) / 2 + j (i >= j), lane l, value v holds
-// Lambda[16 i + 4 (l / 16) + v][16 j + l % 16].
+// The prior Lambda (identity on the padding) in the accumulator layout of
+// the upper blocks: block q = i (i + 1) / 2 + j (i >= j), lane l, value v
+// holds Lambda[16 j + 4 (l / 16) + v][16 i + l % 16].
 template <int NB>
 __global__ __launch_bounds__(256) void prior_image(int K, const float *__restrict__ Lam, float *__restrict__ img)
 {
@@ -469,7 +482,7 @@ __global__ __launch_bounds__(256) void prior_image(int K, const float *__restric
     int i = 0;
     while ((i + 1) * (i + 2) / 2 <= q) ++i;
     const int j = q - i * (i + 1) / 2;
-    const int r = 16 * i + 4 * (l >> 4) + v, cc = 16 * j + (l & 15);
+    const int r = 16 * j + 4 * (l >> 4) + v, cc = 16 * i + (l & 15);
     img[e] = (r < K && cc < K) ? Lam[r * K + cc] : (r == cc ? 1.f : 0.f);
 }
 

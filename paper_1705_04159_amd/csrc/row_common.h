@@ -58,6 +58,54 @@ __device__ __forceinline__ float buf_f32(__amdgpu_buffer_rsrc_t r, uint32_t off)
     return __uint_as_float(buf_u32(r, off));
 }
 
+// x += f * (x of lane L of the same 16-lane row), one fused DPP multiply-add
+// per value (v_fmac_f32 with row_newbcast:L on its first source).  The
+// compiler does not fold its own DPP moves into v_fmac, so these are written
+// out; each group starts with two wait states, which covers the VALU-write
+// -> DPP-read hazard of a value written just before, and the values of a
+// group are distinct registers, so none is read through DPP right after
+// being written inside the group.
+#define BPMF_FMAC_BC(i) "v_fmac_f32_dpp %" #i ", %" #i ", %[f] row_newbcast:%[l] row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+template <int L>
+__device__ __forceinline__ void fmac_bc1(float &a, float f)
+{
+    asm("s_nop 1\n\t" BPMF_FMAC_BC(0) : "+v"(a) : [f] "v"(f), [l] "n"(L));
+}
+template <int L>
+__device__ __forceinline__ void fmac_bc2(float &a, float &b, float f)
+{
+    asm("s_nop 1\n\t" BPMF_FMAC_BC(0) BPMF_FMAC_BC(1) : "+v"(a), "+v"(b) : [f] "v"(f), [l] "n"(L));
+}
+template <int L>
+__device__ __forceinline__ void fmac_bc3(float &a, float &b, float &c, float f)
+{
+    asm("s_nop 1\n\t" BPMF_FMAC_BC(0) BPMF_FMAC_BC(1) BPMF_FMAC_BC(2)
+        : "+v"(a), "+v"(b), "+v"(c) : [f] "v"(f), [l] "n"(L));
+}
+template <int L>
+__device__ __forceinline__ void fmac_bc4(float &a, float &b, float &c, float &d, float f)
+{
+    asm("s_nop 1\n\t" BPMF_FMAC_BC(0) BPMF_FMAC_BC(1) BPMF_FMAC_BC(2) BPMF_FMAC_BC(3)
+        : "+v"(a), "+v"(b), "+v"(c), "+v"(d) : [f] "v"(f), [l] "n"(L));
+}
+#undef BPMF_FMAC_BC
+
+// fmac_bc over x[B], x[B+1], ..., x[E-1] in groups of four.
+template <int L, int B, int E, int N>
+__device__ __forceinline__ void fmac_bc_range(float (&x)[N], float f)
+{
+    if constexpr (E - B >= 4) {
+        fmac_bc4<L>(x[B], x[B + 1], x[B + 2], x[B + 3], f);
+        fmac_bc_range<L, B + 4, E>(x, f);
+    } else if constexpr (E - B == 3) {
+        fmac_bc3<L>(x[B], x[B + 1], x[B + 2], f);
+    } else if constexpr (E - B == 2) {
+        fmac_bc2<L>(x[B], x[B + 1], f);
+    } else if constexpr (E - B == 1) {
+        fmac_bc1<L>(x[B], f);
+    }
+}
+
 // Broadcast lane L of each 16-lane row to the whole row (DPP row_newbcast:
 // a VALU move, no scalar round trip).
 template <int L>
@@ -97,8 +145,10 @@ __device__ __forceinline__ float bm_normal_f32(uint32_t wr, uint32_t wa, bool si
 // PADOK the caller ignores every Gram and rhs entry outside the leading
 // K x K block, so all blocks load at immediate offsets from one address
 // (components >= K then hold whatever follows the row); otherwise
-// components >= K read as 0 through lane_off.
-template <int NB, int kUnroll, bool PADOK>
+// components >= K read as 0 through lane_off.  With TRANS the blocks are
+// accumulated transposed: block (bi, bj), bi >= bj, holds the upper block
+// (bj, bi) of the Gram in the MFMA result layout.
+template <int NB, int kUnroll, bool PADOK, bool TRANS = false>
 __device__ __forceinline__ void gram_item_pipe(const RowItem &it, const int32_t *__restrict__ nbr,
                                           const float *__restrict__ rc,
                                           __amdgpu_buffer_rsrc_t ysrc, uint32_t ldy4,
@@ -150,7 +200,10 @@ __device__ __forceinline__ void gram_item_pipe(const RowItem &it, const int32_t 
             for (int bi = 0; bi < NB; ++bi) {
 #pragma unroll
                 for (int bj = 0; bj <= bi; ++bj) {
-                    acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(yb[buf][g][bi], yb[buf][g][bj], acc[q], 0, 0, 0);
+                    if constexpr (TRANS)
+                        acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(yb[buf][g][bj], yb[buf][g][bi], acc[q], 0, 0, 0);
+                    else
+                        acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(yb[buf][g][bi], yb[buf][g][bj], acc[q], 0, 0, 0);
                     ++q;
                 }
                 bacc[bi] += rb[buf][g] * yb[buf][g][bi];
@@ -175,14 +228,14 @@ __device__ __forceinline__ void gram_item_pipe(const RowItem &it, const int32_t 
 // Gram and rhs of one work item into the accumulators (whole wave): the
 // pipelined per-group form, four groups (16 ratings) per stage for rows of
 // up to 32 components and two for wider rows (register budget).
-template <int NB, bool PADOK = false>
+template <int NB, bool PADOK = false, bool TRANS = false>
 __device__ __forceinline__ void gram_item(const RowItem &it, const int32_t *__restrict__ nbr,
                                           const float *__restrict__ rc,
                                           __amdgpu_buffer_rsrc_t ysrc, uint32_t ldy4,
                                           const uint32_t (&lane_off)[NB], int kq,
                                           floatx4 (&acc)[NB * (NB + 1) / 2], float (&bacc)[NB])
 {
-    gram_item_pipe<NB, (NB <= 2 ? 4 : 2), PADOK>(it, nbr, rc, ysrc, ldy4, lane_off, kq, acc, bacc);
+    gram_item_pipe<NB, (NB <= 2 ? 4 : 2), PADOK, TRANS>(it, nbr, rc, ysrc, ldy4, lane_off, kq, acc, bacc);
 }
 
 }  // namespace
