@@ -210,6 +210,36 @@ __global__ void to_bf16(const float *__restrict__ x, uint16_t *__restrict__ y, i
     y[i] = (uint16_t)(u >> 16);
 }
 
+// r = hi + mid + lo, each part a BF16 value (round to nearest even at each
+// step; exact: hi keeps the top 8 significant bits of r, mid the next 8 of
+// the remainder and lo the rest, which fits), stored as three planes of
+// n + 32 values, each ending in 32 zeros.
+__device__ __forceinline__ uint16_t bf16_rne_bits(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__global__ void split_ratings(const float *__restrict__ rc, uint16_t *__restrict__ rc3, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t plane = n + 32;
+    if (i >= plane) return;
+    if (i >= n) {
+        rc3[i] = rc3[plane + i] = rc3[2 * plane + i] = 0;
+        return;
+    }
+    float r = rc[i];
+    const uint16_t hi = bf16_rne_bits(r);
+    r -= __uint_as_float((uint32_t)hi << 16);
+    const uint16_t mid = bf16_rne_bits(r);
+    r -= __uint_as_float((uint32_t)mid << 16);
+    rc3[i] = hi;
+    rc3[plane + i] = mid;
+    rc3[2 * plane + i] = bf16_rne_bits(r);
+}
+
 }  // namespace
 
 hipError_t launch_init_factor(bpmf_ctx *c, int side_id, hipStream_t s)
@@ -310,6 +340,16 @@ hipError_t launch_to_bf16(bpmf_ctx *c, int side_id, hipStream_t s)
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(to_bf16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
                        (const float *)sd.X, sd.Xbf, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_split_ratings(bpmf_ctx *c, int side_id, hipStream_t s)
+{
+    Side &sd = c->side[side_id];
+    if (!sd.rc3) return hipSuccess;
+    const int64_t n = c->nnz;
+    hipLaunchKernelGGL(split_ratings, dim3((unsigned)((n + 32 + 255) / 256)), dim3(256), 0, s,
+                       (const float *)sd.rc, sd.rc3, n);
     return hipGetLastError();
 }
 

@@ -64,16 +64,13 @@ constexpr int big_waves()
 }
 
 // Per-wave LDS (floats): X = L_kk^-1 of every block row in the A-operand
-// layout (one float4 per lane); a column-major copy of the current diagonal
-// block (column stride kDS); the rhs b (becomes y), w and x.
-constexpr int kDS = 20;
+// layout (one float4 per lane); the rhs b (becomes y), w and x.
 template <int NB>
 struct BigLds {
     static constexpr int XS = NB * 256;
-    static constexpr int DG = 16 * kDS;
     static constexpr int VEC = 16 * NB;
-    static constexpr int BV = XS + DG;  // offset of b
-    static constexpr int TOTAL = XS + DG + 3 * VEC;
+    static constexpr int BV = XS;  // offset of b
+    static constexpr int TOTAL = XS + 3 * VEC;
 };
 
 __device__ __forceinline__ void wave_sync()
@@ -89,19 +86,37 @@ __device__ __forceinline__ uint32_t buf_u16(__amdgpu_buffer_rsrc_t r, uint32_t o
 }
 
 // Gram and rhs of one work item from BF16 rows (whole wave).  Chunks of 32
-// ratings; lane l takes ratings 8*(l/16) + e, e = 0..7, of each chunk.  The
-// blocks are accumulated as upper blocks (block (bi, bj) holds (bj, bi)).
-template <int NB>
+// ratings; lane l takes ratings 8*(l/16) + e, e = 0..7, of each chunk, and
+// loads component 16 bi + l % 16 of their rows for every block bi at
+// immediate offsets from one address (components >= K of the last block
+// then hold whatever follows the row and are replaced below).  The blocks
+// are accumulated as upper blocks (block (bi, bj) holds (bj, bi)).  With
+// AUG (kr = K - 16 (NB - 1) <= 13) lanes kr, kr + 1, kr + 2 of each row
+// take the three BF16 parts of the ratings (hi + mid + lo == r', exactly)
+// as components K, K + 1, K + 2, whose Gram rows then sum to the rhs
+// sum_j r'_j y_j -- BF16 x BF16 products are exact in the FP32
+// accumulation; the other components >= K are 0.  Without AUG they are
+// all 0 and the rhs is summed into bacc on the vector units.
+template <int NB, bool AUG>
 __device__ __forceinline__ void gram_item_bf16(const RowItem &it, const int32_t *__restrict__ nbr,
                                                const float *__restrict__ rc,
-                                               __amdgpu_buffer_rsrc_t ysrc, uint32_t ldy2,
-                                               const uint32_t (&lane_off)[NB], int kq,
+                                               const uint16_t *__restrict__ rc3, uint32_t plane, int kr,
+                                               __amdgpu_buffer_rsrc_t ysrc, uint32_t ldy2, int kq, int col,
                                                floatx4 (&acc)[NB * (NB + 1) / 2],
                                                float (&bacc)[NB])
 {
     const uint32_t cnt = (uint32_t)(it.end - it.beg);
     const __amdgpu_buffer_rsrc_t jsrc = make_rsrc(nbr + it.beg, cnt * 4u);
-    const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(rc + it.beg, cnt * 4u);
+    const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(rc + it.beg, AUG ? 0u : cnt * 4u);
+    // the three planes from this item on, one descriptor; lane part p reads
+    // plane p, the other lanes read nothing
+    const int p = col - kr;
+    const bool part_lane = p >= 0 && p < 3;
+    const __amdgpu_buffer_rsrc_t psrc =
+        make_rsrc(rc3 + it.beg, AUG ? (uint32_t)(3u * plane - (uint32_t)it.beg) * 2u : 0u);
+    const uint32_t poff = (AUG && part_lane) ? 2u * ((uint32_t)p * plane + 8u * kq) : kOOB;
+    const bool pad_lane = col >= kr;  // components >= K of the last block
+    const uint32_t coff = 2u * col;
     const uint32_t nchunk = (cnt + 31) / 32;
     for (uint32_t ch = 0; ch < nchunk; ++ch) {
         uint32_t base[8];
@@ -111,22 +126,27 @@ __device__ __forceinline__ void gram_item_bf16(const RowItem &it, const int32_t 
         for (int e = 0; e < 8; ++e) {
             const uint32_t t = ch * 32 + 8 * kq + e;
             const uint32_t j = buf_u32(jsrc, t * 4u);
-            r[e] = buf_f32(rsrc, t * 4u);
-            base[e] = __umul24(j, ldy2);  // fewer than 2^24 rows
+            if constexpr (!AUG) r[e] = buf_f32(rsrc, t * 4u);
+            base[e] = __umul24(j, ldy2) + coff;  // fewer than 2^24 rows
             if (last) base[e] = t < cnt ? base[e] : kOOB;
         }
+        u32x4 rp = u32x4{0u, 0u, 0u, 0u};
+        if constexpr (AUG) rp = __builtin_amdgcn_raw_buffer_load_b128(psrc, poff + ch * 64u, 0, 0);
         // raw BF16 bits; pairs packed into dwords form the MFMA operand
         uint32_t yr[NB][8];
 #pragma unroll
         for (int bi = 0; bi < NB; ++bi)
 #pragma unroll
-            for (int e = 0; e < 8; ++e) yr[bi][e] = buf_u16(ysrc, base[e] + lane_off[bi]) & 0xFFFFu;
+            for (int e = 0; e < 8; ++e) yr[bi][e] = buf_u16(ysrc, base[e] + 32u * bi) & 0xFFFFu;
         bf16x8 y[NB];
 #pragma unroll
         for (int bi = 0; bi < NB; ++bi) {
             u32x4 w;
 #pragma unroll
             for (int h = 0; h < 4; ++h) w[h] = yr[bi][2 * h] | (yr[bi][2 * h + 1] << 16);
+            if (bi == NB - 1)
+#pragma unroll
+                for (int h = 0; h < 4; ++h) w[h] = pad_lane ? rp[h] : w[h];
             y[bi] = __builtin_bit_cast(bf16x8, w);
         }
         int q = 0;
@@ -137,12 +157,53 @@ __device__ __forceinline__ void gram_item_bf16(const RowItem &it, const int32_t 
                 acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(y[bj], y[bi], acc[q], 0, 0, 0);  // upper block (bj, bi)
                 ++q;
             }
-            float s = 0.f;
+            if constexpr (!AUG) {
+                float s = 0.f;
 #pragma unroll
-            for (int e = 0; e < 8; ++e) s += r[e] * __uint_as_float(yr[bi][e] << 16);
-            bacc[bi] += s;
+                for (int e = 0; e < 8; ++e) s += r[e] * __uint_as_float(yr[bi][e] << 16);  // c >= K: ignored
+                bacc[bi] += s;
+            }
         }
     }
+}
+
+// The rhs of an AUG Gram: component 16 bj + 4 g + v of sum_j r'_j y_j is
+// value v of block (bj, NB - 1) summed over lanes kr .. kr + NP - 1 of row
+// g (NP parts of the rating); left in lane kr of each row.
+template <int NB, int NP>
+__device__ __forceinline__ void aug_rhs(const floatx4 (&acc)[NB * (NB + 1) / 2], floatx4 (&rh)[NB])
+{
+#pragma unroll
+    for (int bj = 0; bj < NB; ++bj) {
+        constexpr int q0 = (NB - 1) * NB / 2;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            float x = acc[q0 + bj][v];
+            if constexpr (NP == 3) {
+                // row_shl:1 and row_shl:2: lane i + 1 and i + 2 of the row
+                const float x1 = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x101, 0xf, 0xf, true));
+                const float x2 = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x102, 0xf, 0xf, true));
+                x += x1 + x2;
+            }
+            rh[bj][v] = x;
+        }
+    }
+}
+
+// Clear the Gram entries of components >= K (kr = K - 16 (NB - 1) < 16):
+// columns kr.. of the blocks (bj, NB - 1), and rows kr.. of the last
+// diagonal block.
+template <int NB>
+__device__ __forceinline__ void clear_padding(floatx4 (&acc)[NB * (NB + 1) / 2], int kr, int kq, int col)
+{
+    constexpr int q0 = (NB - 1) * NB / 2;
+#pragma unroll
+    for (int bj = 0; bj < NB; ++bj)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const bool pad = col >= kr || (bj == NB - 1 && 4 * kq + v >= kr);
+            acc[q0 + bj][v] = pad ? 0.f : acc[q0 + bj][v];
+        }
 }
 
 // Sum over the 16 lanes of each 16-lane row, left in lane 15 of the row
@@ -154,6 +215,21 @@ __device__ __forceinline__ float row_sum16(float x)
     x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x114, 0xf, 0xf, true));
     x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x118, 0xf, 0xf, true));
     return x;
+}
+
+// x from 16-lane row R of the wave, for every row (same lane within the
+// row): v_permlane16_swap of x with itself leaves the even rows in the
+// first result and the odd rows in the second (each twice), and
+// v_permlane32_swap of that with itself leaves rows 0 and 1 of it in the
+// first result and rows 2 and 3 in the second (each on all four rows).
+template <int R>
+__device__ __forceinline__ float bcast_row(float x)
+{
+    const uint32_t xi = __float_as_uint(x);
+    const auto p = __builtin_amdgcn_permlane16_swap(xi, xi, false, false);
+    const uint32_t y = (R & 1) ? p[1] : p[0];
+    const auto q = __builtin_amdgcn_permlane32_swap(y, y, false, false);
+    return __uint_as_float((R & 2) ? q[1] : q[0]);
 }
 
 // Blocked factorisation and draw for one row held in the accumulators (raw
@@ -168,7 +244,6 @@ __device__ __forceinline__ void blocked_chol_sample(floatx4 (&acc)[NB * (NB + 1)
 {
     using L = BigLds<NB>;
     float *xs = lds;              // X of block row kb: float4 per lane at kb * 256 + 4 lane
-    float *dg = lds + L::XS;      // diagonal block, column-major
     float *bv = lds + L::BV;      // b, overwritten by y block by block
     float *wv = bv + L::VEC;
     float *xv = wv + L::VEC;
@@ -191,55 +266,45 @@ __device__ __forceinline__ void blocked_chol_sample(floatx4 (&acc)[NB * (NB + 1)
         constexpr int kb = decltype(kbc)::value;
         constexpr int qd = kb * (kb + 1) / 2 + kb;
         __builtin_amdgcn_sched_barrier(0);
-        // (1) column col of the diagonal block to every 16-lane row
-        *reinterpret_cast<float4 *>(dg + col * kDS + 4 * kq) =
-            float4{acc[qd][0], acc[qd][1], acc[qd][2], acc[qd][3]};
-        wave_sync();
-        // u[r]: row r of column col of the block (d) until step r uses it as
-        // pivot row, then row r of column col of G (e; it is still the
-        // identity's until then)
-        float u[16];
+        // (1) lane (g, c) holds rows 4g .. 4g + 3 of column c of the
+        // diagonal block: the accumulator layout itself (the block is
+        // symmetric and stored whole)
+        float u[4];
 #pragma unroll
-        for (int r4 = 0; r4 < 4; ++r4) {
-            const float4 v = *reinterpret_cast<const float4 *>(dg + col * kDS + 4 * r4);
-            u[4 * r4 + 0] = -v.x;
-            u[4 * r4 + 1] = -v.y;
-            u[4 * r4 + 2] = -v.z;
-            u[4 * r4 + 3] = -v.w;
-        }
+        for (int v = 0; v < 4; ++v) u[v] = -acc[qd][v];
         float bc = bv[16 * kb + col];
         // (2) eliminate columns k of the real part: column c > k takes -f_c
         // times column k (rows > k of d, rows <= k of G -- the nonzero part
-        // of G's column k -- and b's row)
+        // of G's column k -- and b's row).  Each 16-lane group updates its
+        // own four rows; the pivot row comes from the group that holds it.
+        // Every block column but the last has 16 real columns (the kernel
+        // is instantiated with NB = ceil(K / 16)).
         float mydiag = 1.f;
         const int kreal = K - 16 * kb;
         static_for<0, 16>([&](auto kc) {
             constexpr int k = decltype(kc)::value;
-            if (k < kreal) {
-                const float dk = bcast16<k>(u[k]);
+            constexpr int gk = k >> 2, vk = k & 3;
+            if (kb + 1 < NB || k < kreal) {
+                const float pr = bcast_row<gk>(u[vk]);  // row k of column col
+                const float dk = bcast16<k>(pr);
                 if (col == k) mydiag = dk;
-                const float nf = col > k ? -u[k] * __builtin_amdgcn_rcpf(dk) : 0.f;
-                u[k] = col == k ? 1.f : 0.f;  // row k leaves d for G
-                fmac_bc_range<k, 0, 16>(u, nf);
+                const float nf = col > k ? -pr * __builtin_amdgcn_rcpf(dk) : 0.f;
+                if (kq == gk) u[vk] = col == k ? 1.f : 0.f;  // row k leaves d for G
+                fmac_bc4<k>(u[0], u[1], u[2], u[3], nf);
                 fmac_bc1<k>(bc, nf);
             }
         });
-        if (kreal < 16)  // rows of the padding: G is the identity there
+        if (kb + 1 == NB && kreal < 16)  // rows of the padding: G is the identity there
 #pragma unroll
-            for (int r = 0; r < 16; ++r)
-                if (r >= kreal) u[r] = col == r ? 1.f : 0.f;
+            for (int v = 0; v < 4; ++v)
+                if (4 * kq + v >= kreal) u[v] = col == 4 * kq + v ? 1.f : 0.f;
         // (3) pivots, y_kb, and X = L_kk^-1: lane (g, c) holds
         // X[c][4g + v] = G[4g + v][c] / sqrt(pivot_c), the A operand of step v
         if (kq == 0 && col < kreal && !(mydiag > 0.f)) *status = 0;  // P not positive definite in FP32
         const float inv_s = __builtin_amdgcn_rsqf(mydiag);
         float xa[4];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            float s = u[v];
-#pragma unroll
-            for (int g = 1; g < 4; ++g) s = kq == g ? u[4 * g + v] : s;
-            xa[v] = s * inv_s;
-        }
+        for (int v = 0; v < 4; ++v) xa[v] = u[v] * inv_s;
         *reinterpret_cast<float4 *>(xs + kb * 256 + 4 * lane) = float4{xa[0], xa[1], xa[2], xa[3]};
         if (kq == 0) bv[16 * kb + col] = bc * inv_s;  // y_kb
         if constexpr (kb + 1 < NB) {
@@ -352,31 +417,20 @@ constexpr int64_t big_slot_elems()
     return (int64_t)NB * (NB + 1) / 2 * 256 + 16 * NB;
 }
 
-template <int NB>
-__device__ __forceinline__ void write_partial(const floatx4 (&acc)[NB * (NB + 1) / 2],
-                                              const float (&bacc)[NB], int kq, int col,
-                                              float *__restrict__ dst)
-{
-    constexpr int NBLK = NB * (NB + 1) / 2;
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int q = 0; q < NBLK; ++q) reinterpret_cast<floatx4 *>(dst)[q * 64 + lane] = acc[q];
-    if (kq == 0)
-#pragma unroll
-        for (int bi = 0; bi < NB; ++bi) dst[NBLK * 256 + 16 * bi + col] = bacc[bi];
-}
 
 // SEG: the work items are segments of split rows and only their partial
 // sums are written; otherwise they are whole rows, factored and sampled.
 // (Two instantiations keep the partial path's registers out of the
-// factorisation's budget.)
-template <int NB, bool BF16, bool SEG>
+// factorisation's budget.)  AUG (BF16 rows with K - 16 (NB - 1) <= 13): the
+// rhs comes out of the Gram, the rating parts being padding components;
+// otherwise it is summed on the vector units.
+template <int NB, bool BF16, bool SEG, bool AUG>
 __global__ __launch_bounds__(64 * kBigWPB, big_waves<NB>()) void row_big(
     int K, float alpha, const RowItem *__restrict__ items, int64_t item0, int64_t n_items,
-    const int32_t *__restrict__ nbr, const float *__restrict__ rc, const void *__restrict__ Y,
-    int ldy, uint32_t y_bytes, const floatx4 *__restrict__ img, const float *__restrict__ Lmu,
-    float *__restrict__ X, int ldx, float *__restrict__ part, uint64_t seed, uint32_t stream,
-    const uint32_t *__restrict__ ctr, int *__restrict__ status)
+    const int32_t *__restrict__ nbr, const float *__restrict__ rc, const uint16_t *__restrict__ rc3,
+    uint32_t plane, const void *__restrict__ Y, int ldy, uint32_t y_bytes, const floatx4 *__restrict__ img,
+    const float *__restrict__ Lmu, float *__restrict__ X, int ldx, float *__restrict__ part, uint64_t seed,
+    uint32_t stream, const uint32_t *__restrict__ ctr, int *__restrict__ status)
 {
     constexpr int NBLK = NB * (NB + 1) / 2;
     extern __shared__ float smem_f[];
@@ -386,37 +440,56 @@ __global__ __launch_bounds__(64 * kBigWPB, big_waves<NB>()) void row_big(
     if (id >= n_items) return;
     const int col = lane & 15;
     const int kq = lane >> 4;
+    const int kr = K - 16 * (NB - 1);  // real components of the last block
     const RowItem it = items[id];
     const __amdgpu_buffer_rsrc_t ysrc = make_rsrc(Y, y_bytes);
-    const uint32_t esz = BF16 ? 2u : 4u;
-    uint32_t lane_off[NB];
-#pragma unroll
-    for (int bi = 0; bi < NB; ++bi) lane_off[bi] = 16 * bi + col < K ? (16 * bi + col) * esz : kOOB;
     floatx4 acc[NBLK];
 #pragma unroll
     for (int q = 0; q < NBLK; ++q) acc[q] = floatx4{0.f, 0.f, 0.f, 0.f};
     float bacc[NB];
 #pragma unroll
     for (int bi = 0; bi < NB; ++bi) bacc[bi] = 0.f;
-    if constexpr (BF16)
-        gram_item_bf16<NB>(it, nbr, rc, ysrc, (uint32_t)ldy * 2u, lane_off, kq, acc, bacc);
-    else
-        gram_item<NB, false, true>(it, nbr, rc, ysrc, (uint32_t)ldy * 4u, lane_off, kq, acc, bacc);
+    if constexpr (BF16) {
+        gram_item_bf16<NB, AUG>(it, nbr, rc, rc3, plane, kr, ysrc, (uint32_t)ldy * 2u, kq, col, acc, bacc);
+    } else {
+        uint32_t lane_off[NB];
 #pragma unroll
-    for (int bi = 0; bi < NB; ++bi) {
-        bacc[bi] += __shfl_xor(bacc[bi], 16);
-        bacc[bi] += __shfl_xor(bacc[bi], 32);
+        for (int bi = 0; bi < NB; ++bi) lane_off[bi] = (16 * bi + col) * 4u;
+        gram_item<NB, true, true>(it, nbr, rc, ysrc, (uint32_t)ldy * 4u, lane_off, kq, acc, bacc);
+    }
+    float *lds = smem_f + wave * BigLds<NB>::TOTAL;
+    float *bv = lds + BigLds<NB>::BV;
+    float *rdst = SEG ? part + (size_t)it.slot * big_slot_elems<NB>() + NBLK * 256 : bv;
+    static_assert(BF16 || !AUG, "the rating parts are BF16");
+    if constexpr (AUG) {
+        floatx4 rh[NB];
+        aug_rhs<NB, 3>(acc, rh);
+        clear_padding<NB>(acc, kr, kq, col);
+        if (col == kr)
+#pragma unroll
+            for (int bj = 0; bj < NB; ++bj) *reinterpret_cast<floatx4 *>(rdst + 16 * bj + 4 * kq) = rh[bj];
+    } else {
+        clear_padding<NB>(acc, kr, kq, col);  // rows loaded past K (none if kr == 16)
+#pragma unroll
+        for (int bi = 0; bi < NB; ++bi) {
+            bacc[bi] += __shfl_xor(bacc[bi], 16);
+            bacc[bi] += __shfl_xor(bacc[bi], 32);
+        }
+        if (kq == 0)
+#pragma unroll
+            for (int bi = 0; bi < NB; ++bi) rdst[16 * bi + col] = bacc[bi];
     }
     if constexpr (SEG) {
-        write_partial<NB>(acc, bacc, kq, col, part + (size_t)it.slot * big_slot_elems<NB>());
+        float *dst = part + (size_t)it.slot * big_slot_elems<NB>();
+#pragma unroll
+        for (int q = 0; q < NBLK; ++q) reinterpret_cast<floatx4 *>(dst)[q * 64 + lane] = acc[q];
     } else {
-        float *lds = smem_f + wave * BigLds<NB>::TOTAL;
-        float *bv = lds + BigLds<NB>::BV;
+        wave_sync();  // the rhs in bv
         if (kq == 0)
 #pragma unroll
             for (int bi = 0; bi < NB; ++bi) {
                 const int c = 16 * bi + col;
-                bv[c] = c < K ? alpha * bacc[bi] + Lmu[c] : 0.f;
+                bv[c] = c < K ? alpha * bv[c] + Lmu[c] : 0.f;
             }
         wave_sync();
         blocked_chol_sample<NB>(acc, lds, K, alpha, img, (uint32_t)it.row, ctr[0], seed, stream,
@@ -512,26 +585,35 @@ hipError_t launch_big(bpmf_ctx *c, Side &sd, Side &ot, hipStream_t s, int stage)
     const bool bf = c->prec == 2;
     const void *ysrc = bf ? (const void *)ot.Xbf : (const void *)ot.X;
     const uint32_t y_bytes = (uint32_t)(ot.rows * c->ld * (bf ? 2 : 4));
+    // the rhs from the Gram where the padding has room for the rating
+    const int kr = c->K - 16 * (NB - 1);
+    const bool aug = bf && kr <= 13 && sd.rc3 != nullptr;
     auto go = [&](auto kern, int64_t item0, int64_t count, size_t lds_bytes) {
         if (count <= 0) return;
         const unsigned grid = (unsigned)((count + kBigWPB - 1) / kBigWPB);
         hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * kBigWPB), lds_bytes, s, c->K,
                            (float)c->alpha, sd.items, item0, item0 + count, sd.nbr,
-                           (const float *)sd.rc, ysrc, c->ld, y_bytes, img,
-                           (const float *)sd.Lmu_w, (float *)sd.X, c->ld, (float *)c->part,
-                           c->seed, sd.stream_row, c->ctr, c->hyp_status + 1);
+                           (const float *)sd.rc, (const uint16_t *)sd.rc3, (uint32_t)(c->nnz + 32), ysrc,
+                           c->ld, y_bytes, img, (const float *)sd.Lmu_w, (float *)sd.X, c->ld,
+                           (float *)c->part, c->seed, sd.stream_row, c->ctr, c->hyp_status + 1);
     };
-    if (stage == kStageSegments) {
-        if (bf)
-            go(row_big<NB, true, true>, 0, n_seg, 0);
-        else
-            go(row_big<NB, false, true>, 0, n_seg, 0);
-    } else {
-        if (bf)
-            go(row_big<NB, true, false>, n_seg, n_rows, lds);
-        else
-            go(row_big<NB, false, false>, n_seg, n_rows, lds);
-    }
+    auto pick = [&](auto segc) {
+        constexpr bool SEG = decltype(segc)::value;
+        const int64_t item0 = SEG ? 0 : n_seg, count = SEG ? n_seg : n_rows;
+        const size_t bytes = SEG ? 0 : lds;
+        if (bf) {
+            if (aug)
+                go(row_big<NB, true, SEG, true>, item0, count, bytes);
+            else
+                go(row_big<NB, true, SEG, false>, item0, count, bytes);
+        } else {
+            go(row_big<NB, false, SEG, false>, item0, count, bytes);
+        }
+    };
+    if (stage == kStageSegments)
+        pick(std::integral_constant<bool, true>{});
+    else
+        pick(std::integral_constant<bool, false>{});
     return hipGetLastError();
 }
 
