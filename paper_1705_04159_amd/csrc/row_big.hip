@@ -96,7 +96,8 @@ __device__ __forceinline__ uint32_t buf_u16(__amdgpu_buffer_rsrc_t r, uint32_t o
 // as components K, K + 1, K + 2, whose Gram rows then sum to the rhs
 // sum_j r'_j y_j -- BF16 x BF16 products are exact in the FP32
 // accumulation; the other components >= K are 0.  Without AUG they are
-// all 0 and the rhs is summed into bacc on the vector units.
+// all 0 and the rhs is summed into bacc on the vector units.  acc and bacc
+// are written, not accumulated into.
 template <int NB, bool AUG>
 __device__ __forceinline__ void gram_item_bf16(const RowItem &it, const int32_t *__restrict__ nbr,
                                                const float *__restrict__ rc,
@@ -118,10 +119,12 @@ __device__ __forceinline__ void gram_item_bf16(const RowItem &it, const int32_t 
     const bool pad_lane = col >= kr;  // components >= K of the last block
     const uint32_t coff = 2u * col;
     const uint32_t nchunk = (cnt + 31) / 32;
-    for (uint32_t ch = 0; ch < nchunk; ++ch) {
+    // the first chunk starts the accumulators from zero (no separate clear)
+    auto chunk = [&](uint32_t ch, auto firstc) {
+        constexpr bool FIRST = decltype(firstc)::value;
         uint32_t base[8];
         float r[8];
-        const bool last = ch + 1 == nchunk;  // only the last chunk can run past the end
+        const bool last = ch + 1 >= nchunk;  // only the last chunk (or chunk 0 of an empty item) runs past the end
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const uint32_t t = ch * 32 + 8 * kq + e;
@@ -149,22 +152,27 @@ __device__ __forceinline__ void gram_item_bf16(const RowItem &it, const int32_t 
                 for (int h = 0; h < 4; ++h) w[h] = pad_lane ? rp[h] : w[h];
             y[bi] = __builtin_bit_cast(bf16x8, w);
         }
+        const floatx4 zero = floatx4{0.f, 0.f, 0.f, 0.f};
         int q = 0;
 #pragma unroll
         for (int bi = 0; bi < NB; ++bi) {
 #pragma unroll
             for (int bj = 0; bj <= bi; ++bj) {
-                acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(y[bj], y[bi], acc[q], 0, 0, 0);  // upper block (bj, bi)
+                // upper block (bj, bi)
+                acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(y[bj], y[bi], FIRST ? zero : acc[q], 0, 0, 0);
                 ++q;
             }
             if constexpr (!AUG) {
                 float s = 0.f;
 #pragma unroll
                 for (int e = 0; e < 8; ++e) s += r[e] * __uint_as_float(yr[bi][e] << 16);  // c >= K: ignored
-                bacc[bi] += s;
+                bacc[bi] = FIRST ? s : bacc[bi] + s;
             }
         }
-    }
+    };
+    // chunk 0 even for an empty item: every row it loads is 0 (out of range)
+    chunk(0u, std::integral_constant<bool, true>{});
+    for (uint32_t ch = 1; ch < nchunk; ++ch) chunk(ch, std::integral_constant<bool, false>{});
 }
 
 // The rhs of an AUG Gram: component 16 bj + 4 g + v of sum_j r'_j y_j is
@@ -349,18 +357,22 @@ __device__ __forceinline__ void blocked_chol_sample(floatx4 (&acc)[NB * (NB + 1)
         wave_sync();
     });
 
-    // w = y + z for components lane and lane + 64
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int cc = lane + 64 * h;
-        if (cc < 16 * NB) {
-            float w = bv[cc];
-            if (cc < K) {
-                const Block4 bl = philox4x32_10(row, t, (stream << 24) | (uint32_t)(cc >> 2), 0u, seed);
-                const int m = cc & 3;
-                w += bm_normal_f32(m < 2 ? bl.w0 : bl.w2, m < 2 ? bl.w1 : bl.w3, (m & 1) != 0);
+    // w = y + z: lanes l and l + 32 (l < 4 NB) take components 4l, 4l + 1
+    // and 4l + 2, 4l + 3, whose normals are the Box-Muller pairs (w0, w1) and
+    // (w2, w3) of Philox block l
+    {
+        const int blk = lane & 31, hf = lane >> 5;
+        const int c0 = 4 * blk + 2 * hf;
+        if (blk < 4 * NB) {
+            float2 w = *reinterpret_cast<const float2 *>(bv + c0);
+            if (c0 < K) {
+                const Block4 bl = philox4x32_10(row, t, (stream << 24) | (uint32_t)blk, 0u, seed);
+                float zc, zs;
+                bm_pair_f32(hf ? bl.w2 : bl.w0, hf ? bl.w3 : bl.w1, zc, zs);
+                w.x += zc;
+                if (c0 + 1 < K) w.y += zs;
             }
-            wv[cc] = w;
+            *reinterpret_cast<float2 *>(wv + c0) = w;
         }
     }
     wave_sync();
@@ -444,14 +456,14 @@ __global__ __launch_bounds__(64 * kBigWPB, big_waves<NB>()) void row_big(
     const RowItem it = items[id];
     const __amdgpu_buffer_rsrc_t ysrc = make_rsrc(Y, y_bytes);
     floatx4 acc[NBLK];
-#pragma unroll
-    for (int q = 0; q < NBLK; ++q) acc[q] = floatx4{0.f, 0.f, 0.f, 0.f};
     float bacc[NB];
-#pragma unroll
-    for (int bi = 0; bi < NB; ++bi) bacc[bi] = 0.f;
     if constexpr (BF16) {
         gram_item_bf16<NB, AUG>(it, nbr, rc, rc3, plane, kr, ysrc, (uint32_t)ldy * 2u, kq, col, acc, bacc);
     } else {
+#pragma unroll
+        for (int q = 0; q < NBLK; ++q) acc[q] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int bi = 0; bi < NB; ++bi) bacc[bi] = 0.f;
         uint32_t lane_off[NB];
 #pragma unroll
         for (int bi = 0; bi < NB; ++bi) lane_off[bi] = (16 * bi + col) * 4u;

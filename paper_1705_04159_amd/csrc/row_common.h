@@ -6,6 +6,7 @@
 
 
 #include "internal.h"
+#include "rng_device.h"
 
 namespace bpmf {
 namespace {
@@ -114,9 +115,9 @@ __device__ __forceinline__ float bcast16(float x)
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x150 + L, 0xf, 0xf, true));
 }
 
-// Standard normal from Philox words: the pair (wr, wa) gives radius and
-// angle; `sine` picks the sine branch.  FP32 evaluation.
-__device__ __forceinline__ float bm_normal_f32(uint32_t wr, uint32_t wa, bool sine)
+// Box-Muller on Philox words: the pair (wr, wa) gives radius and angle, and
+// both normals of the pair (cosine and sine branch).  FP32 evaluation.
+__device__ __forceinline__ void bm_pair_f32(uint32_t wr, uint32_t wa, float &zc, float &zs)
 {
     float lnu;
     if (wr < 0x80000000u) {
@@ -130,7 +131,25 @@ __device__ __forceinline__ float bm_normal_f32(uint32_t wr, uint32_t wa, bool si
     const float ua = ((float)wa + 0.5f) * 2.3283064365386963e-10f;
     float sv, cv;
     sincospif(2.0f * ua, &sv, &cv);
-    return rho * (sine ? sv : cv);
+    zc = rho * cv;
+    zs = rho * sv;
+}
+
+// One standard normal: `sine` picks the branch.
+__device__ __forceinline__ float bm_normal_f32(uint32_t wr, uint32_t wa, bool sine)
+{
+    float zc, zs;
+    bm_pair_f32(wr, wa, zc, zs);
+    return sine ? zs : zc;
+}
+
+// The four normals of one Philox block: components 4 blk + m take the
+// cosine (m even) and sine (m odd) of the pairs (w0, w1) for m < 2 and
+// (w2, w3) otherwise -- the same values as bm_normal_f32 per component.
+__device__ __forceinline__ void bm_normal4_f32(const Block4 &bl, float (&z)[4])
+{
+    bm_pair_f32(bl.w0, bl.w1, z[0], z[1]);
+    bm_pair_f32(bl.w2, bl.w3, z[2], z[3]);
 }
 
 // Gram and rhs of one work item (whole wave), FP32 rows on

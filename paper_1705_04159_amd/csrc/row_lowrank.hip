@@ -215,13 +215,35 @@ __global__ __launch_bounds__(64 * kLowWPB) void row_lowrank(
         if (i < dw) solve_fwd<C>(F[i], vb);
     });
     const uint32_t row = live ? (uint32_t)it.row : 0u;
+    if constexpr (C == 4) {
+        // components 4 l16 .. 4 l16 + 3: the four normals of Philox block l16
+        if (4 * l16 < K) {
+            const Block4 bl = philox4x32_10(row, ctr[0], (stream << 24) | (uint32_t)l16, 0u, seed);
+            float z[4];
+            bm_normal4_f32(bl, z);
 #pragma unroll
-    for (int e = 0; e < C; ++e) {
-        const int c = C * l16 + e;
-        if (c < K) {
-            const Block4 bl = philox4x32_10(row, ctr[0], (stream << 24) | (uint32_t)(c >> 2), 0u, seed);
-            const int m = c & 3;
-            vb[e] += bm_normal_f32(m < 2 ? bl.w0 : bl.w2, m < 2 ? bl.w1 : bl.w3, (m & 1) != 0);
+            for (int e = 0; e < 4; ++e)
+                if (4 * l16 + e < K) vb[e] += z[e];
+        }
+    } else if constexpr (C == 2) {
+        // components 2 l16, 2 l16 + 1: one Box-Muller pair of block l16 / 2
+        if (2 * l16 < K) {
+            const Block4 bl = philox4x32_10(row, ctr[0], (stream << 24) | (uint32_t)(l16 >> 1), 0u, seed);
+            const bool hi = (l16 & 1) != 0;
+            float zc, zs;
+            bm_pair_f32(hi ? bl.w2 : bl.w0, hi ? bl.w3 : bl.w1, zc, zs);
+            vb[0] += zc;
+            if (2 * l16 + 1 < K) vb[1] += zs;
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < C; ++e) {
+            const int c = C * l16 + e;
+            if (c < K) {
+                const Block4 bl = philox4x32_10(row, ctr[0], (stream << 24) | (uint32_t)(c >> 2), 0u, seed);
+                const int m = c & 3;
+                vb[e] += bm_normal_f32(m < 2 ? bl.w0 : bl.w2, m < 2 ? bl.w1 : bl.w3, (m & 1) != 0);
+            }
         }
     }
     // R_d^-T ... R_1^-T
