@@ -270,23 +270,25 @@ __device__ __forceinline__ void blocked_chol_sample(floatx4 (&acc)[NB * (NB + 1)
         for (int v = 0; v < 4; ++v) acc[q][v] = -alpha * acc[q][v] - p[v];
     }
 
-    static_for<0, NB>([&](auto kbc) {
+    // Diagonal block kb (already brought up to date): (1) lane (g, c) holds
+    // rows 4g .. 4g + 3 of column c -- the accumulator layout itself (the
+    // block is symmetric and stored whole); (2) eliminate columns k of the
+    // real part: column c > k takes -f_c times column k (rows > k of d,
+    // rows <= k of G -- the nonzero part of G's column k -- and b's row).
+    // Each 16-lane group updates its own four rows; the pivot row comes from
+    // the group that holds it.  Every block column but the last has 16 real
+    // columns (the kernel is instantiated with NB = ceil(K / 16)).  (3)
+    // pivots, y_kb, and X = L_kk^-1: lane (g, c) holds X[c][4g + v] =
+    // G[4g + v][c] / sqrt(pivot_c), the A operand of step v, also kept in
+    // LDS for the back solve.
+    float xa[4];
+    auto eliminate = [&](auto kbc) {
         constexpr int kb = decltype(kbc)::value;
         constexpr int qd = kb * (kb + 1) / 2 + kb;
-        __builtin_amdgcn_sched_barrier(0);
-        // (1) lane (g, c) holds rows 4g .. 4g + 3 of column c of the
-        // diagonal block: the accumulator layout itself (the block is
-        // symmetric and stored whole)
         float u[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) u[v] = -acc[qd][v];
         float bc = bv[16 * kb + col];
-        // (2) eliminate columns k of the real part: column c > k takes -f_c
-        // times column k (rows > k of d, rows <= k of G -- the nonzero part
-        // of G's column k -- and b's row).  Each 16-lane group updates its
-        // own four rows; the pivot row comes from the group that holds it.
-        // Every block column but the last has 16 real columns (the kernel
-        // is instantiated with NB = ceil(K / 16)).
         float mydiag = 1.f;
         const int kreal = K - 16 * kb;
         static_for<0, 16>([&](auto kc) {
@@ -306,56 +308,65 @@ __device__ __forceinline__ void blocked_chol_sample(floatx4 (&acc)[NB * (NB + 1)
 #pragma unroll
             for (int v = 0; v < 4; ++v)
                 if (4 * kq + v >= kreal) u[v] = col == 4 * kq + v ? 1.f : 0.f;
-        // (3) pivots, y_kb, and X = L_kk^-1: lane (g, c) holds
-        // X[c][4g + v] = G[4g + v][c] / sqrt(pivot_c), the A operand of step v
         if (kq == 0 && col < kreal && !(mydiag > 0.f)) *status = 0;  // P not positive definite in FP32
         const float inv_s = __builtin_amdgcn_rsqf(mydiag);
-        float xa[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) xa[v] = u[v] * inv_s;
         *reinterpret_cast<float4 *>(xs + kb * 256 + 4 * lane) = float4{xa[0], xa[1], xa[2], xa[3]};
         if (kq == 0) bv[16 * kb + col] = bc * inv_s;  // y_kb
-        if constexpr (kb + 1 < NB) {
-            // (4) R_kb,i = X T_kb,i = (-X)(-T_kb,i) on the matrix cores
-            float nxa[4];
+    };
+
+    eliminate(std::integral_constant<int, 0>{});
+    static_for<0, NB - 1>([&](auto kbc) {
+        constexpr int kb = decltype(kbc)::value;
+        constexpr int kn = kb + 1;
+        __builtin_amdgcn_sched_barrier(0);
+        // (4) R_kb,i = X T_kb,i = (-X)(-T_kb,i) on the matrix cores
+        float nxa[4];
 #pragma unroll
-            for (int v = 0; v < 4; ++v) nxa[v] = -xa[v];
-            static_for<kb + 1, NB>([&](auto ic) {
-                constexpr int i = decltype(ic)::value;
-                constexpr int q = i * (i + 1) / 2 + kb;
-                floatx4 r = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int v = 0; v < 4; ++v) nxa[v] = -xa[v];
+        static_for<kb + 1, NB>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            constexpr int q = i * (i + 1) / 2 + kb;
+            floatx4 r = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                for (int v = 0; v < 4; ++v) r = __builtin_amdgcn_mfma_f32_16x16x4f32(nxa[v], acc[q][v], r, 0, 0, 0);
-                acc[q] = r;
-            });
-            wave_sync();  // y_kb visible to every lane
-            // (5) b_i -= L_i,kb y_kb: (L_i,kb y)[c] = sum_m R_kb,i[m][c] y_m
-            const float4 y4 = *reinterpret_cast<const float4 *>(bv + 16 * kb + 4 * kq);
-            static_for<kb + 1, NB>([&](auto ic) {
-                constexpr int i = decltype(ic)::value;
-                constexpr int q = i * (i + 1) / 2 + kb;
-                float p = acc[q][0] * y4.x + acc[q][1] * y4.y + acc[q][2] * y4.z + acc[q][3] * y4.w;
-                p += __shfl_xor(p, 16);
-                p += __shfl_xor(p, 32);
-                if (kq == 0) bv[16 * i + col] -= p;
-            });
-            // (6) trailing blocks T_j,i -= R_kb,j^T R_kb,i, kb < j <= i (the
-            // negated T takes + R_kb,j^T R_kb,i)
-            static_for<kb + 1, NB>([&](auto ic) {
-                constexpr int i = decltype(ic)::value;
-                constexpr int qi = i * (i + 1) / 2 + kb;
-                static_for<kb + 1, i + 1>([&](auto jc) {
-                    constexpr int j = decltype(jc)::value;
-                    constexpr int qj = j * (j + 1) / 2 + kb;
-                    constexpr int q = i * (i + 1) / 2 + j;
+            for (int v = 0; v < 4; ++v) r = __builtin_amdgcn_mfma_f32_16x16x4f32(nxa[v], acc[q][v], r, 0, 0, 0);
+            acc[q] = r;
+        });
+        wave_sync();  // y_kb visible to every lane
+        // (5) b_i -= L_i,kb y_kb: (L_i,kb y)[c] = sum_m R_kb,i[m][c] y_m
+        const float4 y4 = *reinterpret_cast<const float4 *>(bv + 16 * kb + 4 * kq);
+        static_for<kb + 1, NB>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            constexpr int q = i * (i + 1) / 2 + kb;
+            float p = acc[q][0] * y4.x + acc[q][1] * y4.y + acc[q][2] * y4.z + acc[q][3] * y4.w;
+            p += __shfl_xor(p, 16);
+            p += __shfl_xor(p, 32);
+            if (kq == 0) bv[16 * i + col] -= p;
+        });
+        wave_sync();  // b_kn visible to every lane
+        // (6) trailing blocks T_j,i -= R_kb,j^T R_kb,i, kb < j <= i (the
+        // negated T takes + R_kb,j^T R_kb,i): the next diagonal block first,
+        // whose elimination then overlaps the other blocks' products
+        auto trail = [&](auto jc, auto ic) {
+            constexpr int j = decltype(jc)::value, i = decltype(ic)::value;
+            constexpr int qi = i * (i + 1) / 2 + kb, qj = j * (j + 1) / 2 + kb;
+            constexpr int q = i * (i + 1) / 2 + j;
 #pragma unroll
-                    for (int v = 0; v < 4; ++v)
-                        acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(acc[qj][v], acc[qi][v], acc[q], 0, 0, 0);
-                });
+            for (int v = 0; v < 4; ++v)
+                acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(acc[qj][v], acc[qi][v], acc[q], 0, 0, 0);
+        };
+        trail(std::integral_constant<int, kn>{}, std::integral_constant<int, kn>{});
+        static_for<kn, NB>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            static_for<kn, i + 1>([&](auto jc) {
+                constexpr int j = decltype(jc)::value;
+                if constexpr (!(i == kn && j == kn)) trail(jc, ic);
             });
-        }
-        wave_sync();
+        });
+        eliminate(std::integral_constant<int, kn>{});
     });
+    wave_sync();
 
     // w = y + z: lanes l and l + 32 (l < 4 NB) take components 4l, 4l + 1
     // and 4l + 2, 4l + 3, whose normals are the Box-Muller pairs (w0, w1) and
