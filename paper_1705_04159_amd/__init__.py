@@ -365,6 +365,22 @@ class Sampler:
                                              int(top_n), ctypes.byref(rid)))
         return rid.value
 
+    def foldin_prepare(self, movie, rating):
+        """A request's arrays converted once for foldin_submit_prepared (for
+        load generators that submit faster than per-call conversion allows)."""
+        movie = _c(movie, np.int32)
+        rating = _c(rating, np.float32)
+        return (movie, rating, len(movie), _ptr(movie), _ptr(rating))
+
+    def foldin_submit_prepared(self, prepared, top_n=100):
+        """foldin_submit on foldin_prepare's result."""
+        rid = ctypes.c_uint64()
+        rc = lib().bpmf_foldin_submit(self._ctx, prepared[2], prepared[3], prepared[4], top_n,
+                                      ctypes.byref(rid))
+        if rc:
+            self._check(rc)
+        return rid.value
+
     def foldin_poll(self, req_id, top_n=100):
         """None while pending, else (movie ids, mean, var, latency seconds)."""
         ids = np.zeros(top_n, np.int32)

@@ -431,12 +431,28 @@ int bpmf_foldin_submit(bpmf_ctx *c, int32_t n, const int32_t *movie, const float
     r->movie.assign(movie, movie + n);
     r->rc.resize(n);
     {
-        std::vector<int32_t> sorted(r->movie);
-        std::sort(sorted.begin(), sorted.end());
-        for (int32_t i = 0; i < n; ++i) {
-            if (sorted[i] < 0 || sorted[i] >= c->N) return BPMF_E_RANGE;
-            if (i > 0 && sorted[i] == sorted[i - 1]) return BPMF_E_FORMAT;
+        // range and duplicate check in O(n): one bit per movie, per calling
+        // thread, cleared again before returning
+        thread_local std::vector<uint64_t> seen;
+        if (seen.size() < (size_t)(c->N + 63) / 64) seen.assign((size_t)(c->N + 63) / 64, 0);
+        int rc = BPMF_OK;
+        int32_t i = 0;
+        for (; i < n; ++i) {
+            const int32_t m = movie[i];
+            if (m < 0 || m >= c->N) {
+                rc = BPMF_E_RANGE;
+                break;
+            }
+            uint64_t &w = seen[(size_t)m >> 6];
+            const uint64_t bit = 1ull << (m & 63);
+            if (w & bit) {
+                rc = BPMF_E_FORMAT;
+                break;
+            }
+            w |= bit;
         }
+        for (int32_t j = 0; j < i; ++j) seen[(size_t)movie[j] >> 6] &= ~(1ull << (movie[j] & 63));
+        if (rc != BPMF_OK) return rc;
     }
     for (int32_t i = 0; i < n; ++i) {
         if (!(rating[i] == rating[i]) || rating[i] > 3.4e38f || rating[i] < -3.4e38f) return BPMF_E_FORMAT;

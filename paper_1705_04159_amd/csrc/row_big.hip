@@ -128,8 +128,8 @@ __device__ __forceinline__ void gram_item_bf16(const RowItem &it, const int32_t 
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const uint32_t t = ch * 32 + 8 * kq + e;
-            const uint32_t j = buf_u32(jsrc, t * 4u);
-            if constexpr (!AUG) r[e] = buf_f32(rsrc, t * 4u);
+            const uint32_t j = buf_u32_stream(jsrc, t * 4u);
+            if constexpr (!AUG) r[e] = buf_f32_stream(rsrc, t * 4u);
             base[e] = __umul24(j, ldy2) + coff;  // fewer than 2^24 rows
             if (last) base[e] = t < cnt ? base[e] : kOOB;
         }

@@ -59,6 +59,20 @@ __device__ __forceinline__ float buf_f32(__amdgpu_buffer_rsrc_t r, uint32_t off)
     return __uint_as_float(buf_u32(r, off));
 }
 
+// Loads of data read once per sweep (neighbour ids, ratings), marked
+// non-temporal (cache policy NT) so that they do not push the gathered
+// factor rows, which every row re-reads, out of the L2.
+constexpr int kStreamPolicy = 2;
+__device__ __forceinline__ uint32_t buf_u32_stream(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    return __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, kStreamPolicy);
+}
+
+__device__ __forceinline__ float buf_f32_stream(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    return __uint_as_float(buf_u32_stream(r, off));
+}
+
 // x += f * (x of lane L of the same 16-lane row), one fused DPP multiply-add
 // per value (v_fmac_f32 with row_newbcast:L on its first source).  The
 // compiler does not fold its own DPP moves into v_fmac, so these are written
@@ -184,14 +198,14 @@ __device__ __forceinline__ void gram_item_pipe(const RowItem &it, const int32_t 
     float rb[2][kUnroll];
     auto load_ids = [&](int buf, uint32_t ch) {
 #pragma unroll
-        for (int g = 0; g < kUnroll; ++g) jb[buf][g] = buf_u32(jsrc, (ch * kChunk + 4 * g + kq) * 4u);
+        for (int g = 0; g < kUnroll; ++g) jb[buf][g] = buf_u32_stream(jsrc, (ch * kChunk + 4 * g + kq) * 4u);
     };
     auto load_rows_t = [&](int buf, uint32_t ch, auto checkc) {
         constexpr bool CHECK = decltype(checkc)::value;
 #pragma unroll
         for (int g = 0; g < kUnroll; ++g) {
             const uint32_t t = ch * kChunk + 4 * g + kq;
-            rb[buf][g] = buf_f32(rsrc, t * 4u);  // 0 past the end
+            rb[buf][g] = buf_f32_stream(rsrc, t * 4u);  // 0 past the end
             uint32_t base = __umul24(jb[buf][g], ldy4);
             if constexpr (CHECK) base = t < cnt ? base : kOOB;
             if constexpr (PADOK) {

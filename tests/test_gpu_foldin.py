@@ -116,6 +116,25 @@ def test_foldin_ring_keeps_last_S(bp, orc):
     s.close()
 
 
+def test_foldin_prepared_submit_matches(bp):
+    """The prepared form of submit (arrays converted once) queues the same
+    request: identical results to the plain form on a second context."""
+    r = synth.random_small(22, 300, 200, 6000, 6)
+    movie = np.array([3, 10, 50, 77], np.int32)
+    rating = np.array([1.0, -0.5, 2.0, 0.25], np.float32)
+    out = []
+    for prepared in (False, True):
+        s, _ = _chain_with_samples(bp, r, 6, 5, n_samples=3, S=3)
+        if prepared:
+            rid = s.foldin_submit_prepared(s.foldin_prepare(movie, rating), 20)
+        else:
+            rid = s.foldin_submit(movie, rating, 20)
+        out.append(_wait(s, rid, 20)[:3])
+        s.close()
+    for a, b in zip(*out):
+        assert np.array_equal(a, b)
+
+
 def test_foldin_alone_equals_mixed(bp):
     """121 requests (0 to 399 ratings, every size class but the largest; top-n
     between 1 and 100) run one at a time in context A -- each submitted only
