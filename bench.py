@@ -545,6 +545,9 @@ def main():
                     help="skip the micro-benchmarks of the measured peaks")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the library's default split threshold and kernel family")
+    ap.add_argument("--plan", default=None, metavar="SPLIT,KMAX,LOWD",
+                    help="fix the plan (split threshold, fast-kernel K cut-off, rank-one degree "
+                         "cut-off) instead of autotuning, e.g. to profile the plan a timed run chose")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (torch), the "
                          "reference kernel for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE")
@@ -588,7 +591,12 @@ def main():
     log("created context in %.1fs" % (time.perf_counter() - t))
     steps, warm = args.steps, args.warmup
     tuned = None
-    if not args.no_autotune:
+    if args.plan:
+        split, kmax, low = (int(x) for x in args.plan.split(","))
+        s.set_plan(split, kmax, low)
+        tuned = {"split_threshold": split, "fast_kmax": kmax, "lowrank_dmax": low, "tried": "fixed"}
+        log("plan fixed: split %d, kmax %d, low %d" % (split, kmax, low))
+    elif not args.no_autotune:
         t = time.perf_counter()
         split, kmax, low, tried = s.autotune(5)
         tuned = {"split_threshold": split, "fast_kmax": kmax, "lowrank_dmax": low,
