@@ -183,31 +183,35 @@ __global__ __launch_bounds__(64) void hyper_moments_mfma(int K, const XT *__rest
         }
 }
 
-// stats[e] = sum over blocks of part[b][e], in a fixed order: workgroup w
-// takes entries 64 w .. 64 w + 63 (lane l entry 64 w + l, so every load of a
-// wave is 512 contiguous bytes), wave v of its 16 sums blocks
-// v, v + 16, v + 32, ..., and the 16 wave sums are added in wave order.
-constexpr int kRedWaves = 16;
-__global__ __launch_bounds__(64 * kRedWaves) void hyper_reduce(int E, int nblk,
-                                                               const double *__restrict__ part,
-                                                               double *__restrict__ stats)
+// stats[e] = sum over blocks of part[b][e], in a fixed order, in two passes
+// of one-wave workgroups (which fit beside the row kernels of the other
+// side): wave (w, g) of the first pass takes entries 64 w .. 64 w + 63 (lane
+// l entry 64 w + l, so every load of a wave is 512 contiguous bytes) and
+// sums blocks g, g + 16, g + 32, ...; the second pass adds the 16 sums of
+// each entry in order of g.
+constexpr int kRedGroups = 16;
+__global__ __launch_bounds__(64) void hyper_reduce_groups(int E, int nblk, const double *__restrict__ part,
+                                                         double *__restrict__ red)
 {
-    __shared__ double ws[kRedWaves][64];
-    const int lane = threadIdx.x & 63;
-    const int v = threadIdx.x >> 6;
+    const int lane = threadIdx.x;
     const int e = blockIdx.x * 64 + lane;
+    const int g = blockIdx.y;
+    if (e >= E) return;
     double s = 0.0;
-    if (e < E)
-#pragma unroll 4
-        for (int b = v; b < nblk; b += kRedWaves) s += part[(size_t)b * E + e];
-    ws[v][lane] = s;
-    __syncthreads();
-    if (v == 0 && e < E) {
-        double t = 0.0;
+#pragma unroll 8
+    for (int b = g; b < nblk; b += kRedGroups) s += part[(size_t)b * E + e];
+    red[(size_t)g * E + e] = s;
+}
+
+__global__ __launch_bounds__(64) void hyper_reduce(int E, const double *__restrict__ red,
+                                                   double *__restrict__ stats)
+{
+    const int e = blockIdx.x * 64 + threadIdx.x;
+    if (e >= E) return;
+    double t = 0.0;
 #pragma unroll
-        for (int q = 0; q < kRedWaves; ++q) t += ws[q][lane];
-        stats[e] = t;
-    }
+    for (int g = 0; g < kRedGroups; ++g) t += red[(size_t)g * E + e];
+    stats[e] = t;
 }
 
 // In-place Cholesky of a packed lower K x K matrix (K <= 128) by the whole
@@ -216,29 +220,30 @@ __global__ __launch_bounds__(64 * kRedWaves) void hyper_reduce(int E, int nblk,
 // the trailing entries (i >= j > k), reading column k unscaled; at the end
 // column k is divided by sqrt(P[k][k]) and the pivot replaced by the root.
 // Clears *ok on a non-positive pivot (which is then taken as 1).
+template <int NT>
 __device__ void chol_packed(int K, double *P, int *ok)
 {
     __shared__ double root[128];
     const int tid = threadIdx.x;
-    const int ti = tid & 31, tj = tid >> 5;  // a 32 x 32 tiling of the trailing triangle
+    const int ti = tid & 31, tj = tid >> 5;  // a 32 x (NT / 32) tiling of the trailing triangle
     for (int k = 0; k + 1 < K; ++k) {
         double d = P[pk(k, k)];
         if (!(d > 0.0)) d = 1.0;
         const double rd = 1.0 / d;
         for (int i = k + 1 + ti; i < K; i += 32) {
             const double pik = P[pk(i, k)] * rd;
-            for (int j = k + 1 + tj; j <= i; j += 32) P[pk(i, j)] -= pik * P[pk(j, k)];
+            for (int j = k + 1 + tj; j <= i; j += NT / 32) P[pk(i, j)] -= pik * P[pk(j, k)];
         }
         __syncthreads();
     }
-    for (int k = tid; k < K; k += kDrawThreads) {
+    for (int k = tid; k < K; k += NT) {
         const double d = P[pk(k, k)];
         if (!(d > 0.0)) *ok = 0;
         root[k] = sqrt(d > 0.0 ? d : 1.0);
     }
     __syncthreads();
     const int KK2 = K * (K + 1) / 2;
-    for (int e = tid; e < KK2; e += kDrawThreads) {
+    for (int e = tid; e < KK2; e += NT) {
         int i, j;
         tri_index(e, i, j);
         P[e] = i == j ? root[j] : P[e] / root[j];
@@ -250,27 +255,28 @@ __device__ void chol_packed(int K, double *P, int *ok)
 // substitution on the identity with the row scaling deferred (one barrier
 // per pivot row): step k subtracts C[i][k] X[k][j] / C[k][k] from the rows
 // i > k, X[k] still unscaled; every row i is divided by C[i][i] at the end.
+template <int NT>
 __device__ void tri_inverse_packed(int K, const double *C, double *Xp)
 {
     const int tid = threadIdx.x;
     const int KK2 = K * (K + 1) / 2;
-    for (int e = tid; e < KK2; e += kDrawThreads) {
+    for (int e = tid; e < KK2; e += NT) {
         int i, j;
         tri_index(e, i, j);
         Xp[e] = i == j ? 1.0 : 0.0;
     }
     __syncthreads();
-    const int ti = tid & 31, tj = tid >> 5;  // a 32 x 32 tiling of rows i > k, columns j <= k
+    const int ti = tid & 31, tj = tid >> 5;  // a 32 x (NT / 32) tiling of rows i > k, columns j <= k
     for (int k = 0; k < K - 1; ++k) {
         const double rck = 1.0 / C[pk(k, k)];
         // rows i > k: X[i][j] -= C[i][k] X[k][j] / C[k][k], j <= k
         for (int i = k + 1 + ti; i < K; i += 32) {
             const double cik = C[pk(i, k)] * rck;
-            for (int j = tj; j <= k; j += 32) Xp[pk(i, j)] -= cik * Xp[pk(k, j)];
+            for (int j = tj; j <= k; j += NT / 32) Xp[pk(i, j)] -= cik * Xp[pk(k, j)];
         }
         __syncthreads();
     }
-    for (int e = tid; e < KK2; e += kDrawThreads) {
+    for (int e = tid; e < KK2; e += NT) {
         int i, j;
         tri_index(e, i, j);
         Xp[e] /= C[pk(i, i)];
@@ -278,8 +284,8 @@ __device__ void tri_inverse_packed(int K, const double *C, double *Xp)
     __syncthreads();
 }
 
-template <typename T>
-__global__ __launch_bounds__(kDrawThreads) void hyper_draw(
+template <int NT, typename T>
+__global__ __launch_bounds__(NT) void hyper_draw(
     int K, int64_t n, const double *__restrict__ stats, const double *__restrict__ mu0,
     const double *__restrict__ W0inv, double beta0, double nu0, uint64_t seed, uint32_t stream,
     const uint32_t *__restrict__ ctr, uint32_t t_off, double *__restrict__ gbuf, int n_lds_bufs,
@@ -304,13 +310,13 @@ __global__ __launch_bounds__(kDrawThreads) void hyper_draw(
     const double nu_s = nu0 + dn;
     const double shrink = beta0 * dn / beta_s;
     if (tid == 0) ok = 1;
-    for (int k = tid; k < K; k += kDrawThreads) {
+    for (int k = tid; k < K; k += NT) {
         xbar[k] = stats[k] / dn;
         mus[k] = (beta0 * mu0[k] + dn * xbar[k]) / beta_s;
     }
     __syncthreads();
     // J W*^-1 J, packed: entry (i, j), i >= j, is W*^-1[K-1-j][K-1-i]
-    for (int e = tid; e < KK2; e += kDrawThreads) {
+    for (int e = tid; e < KK2; e += NT) {
         int a, b;
         tri_index(e, a, b);  // W*^-1 entry (a, b), a >= b
         const double S = stats[K + e] - dn * xbar[a] * xbar[b];
@@ -318,15 +324,15 @@ __global__ __launch_bounds__(kDrawThreads) void hyper_draw(
         Cm[pk(K - 1 - b, K - 1 - a)] = w;
     }
     __syncthreads();
-    chol_packed(K, Cm, &ok);
-    tri_inverse_packed(K, Cm, Ci);
+    chol_packed<NT>(K, Cm, &ok);
+    tri_inverse_packed<NT>(K, Cm, Ci);
     // Bartlett factor A (reuses Cm)
-    for (int e = tid; e < KK2; e += kDrawThreads) Cm[e] = 0.0;
+    for (int e = tid; e < KK2; e += NT) Cm[e] = 0.0;
     __syncthreads();
-    for (int k = tid; k < K; k += kDrawThreads)
+    for (int k = tid; k < K; k += NT)
         Cm[pk(k, k)] = sqrt(chi_square(seed, stream, t, (uint32_t)k, nu_s - (double)k, &ok));
     const int n_low = K * (K - 1) / 2;
-    for (int blk = tid; 4 * blk < n_low; blk += kDrawThreads) {
+    for (int blk = tid; 4 * blk < n_low; blk += NT) {
         double z[4];
         normals_block(seed, (uint32_t)blk, t, stream, 1u, 0u, z);
         for (int l = 0; l < 4 && 4 * blk + l < n_low; ++l) {
@@ -337,7 +343,7 @@ __global__ __launch_bounds__(kDrawThreads) void hyper_draw(
     }
     __syncthreads();
     // B = L_W A, L_W[r][m] = C^-1[K-1-m][K-1-r]
-    for (int e = tid; e < KK2; e += kDrawThreads) {
+    for (int e = tid; e < KK2; e += NT) {
         int r, c;
         tri_index(e, r, c);
         double s = 0.0;
@@ -346,7 +352,7 @@ __global__ __launch_bounds__(kDrawThreads) void hyper_draw(
     }
     __syncthreads();
     // Lambda = B B^T
-    for (int e = tid; e < KK2; e += kDrawThreads) {
+    for (int e = tid; e < KK2; e += NT) {
         int r, c;
         tri_index(e, r, c);
         double s = 0.0;
@@ -356,7 +362,7 @@ __global__ __launch_bounds__(kDrawThreads) void hyper_draw(
         Lam_w[r * K + c] = (T)s;
         Lam_w[c * K + r] = (T)s;
     }
-    for (int blk = tid; 4 * blk < K; blk += kDrawThreads) {
+    for (int blk = tid; 4 * blk < K; blk += NT) {
         double z[4];
         normals_block(seed, (uint32_t)blk, t, stream, 2u, 0u, z);
         for (int l = 0; l < 4 && 4 * blk + l < K; ++l) zv[4 * blk + l] = z[l];
@@ -367,35 +373,35 @@ __global__ __launch_bounds__(kDrawThreads) void hyper_draw(
     // the divisions are applied to zv at the end
     for (int i = K - 1; i > 0; --i) {
         const double xi = zv[i] / Bm[pk(i, i)];
-        for (int j = tid; j < i; j += kDrawThreads) zv[j] -= Bm[pk(i, j)] * xi;
+        for (int j = tid; j < i; j += NT) zv[j] -= Bm[pk(i, j)] * xi;
         __syncthreads();
     }
-    for (int i = tid; i < K; i += kDrawThreads) zv[i] /= Bm[pk(i, i)];
+    for (int i = tid; i < K; i += NT) zv[i] /= Bm[pk(i, i)];
     __syncthreads();
     const double rs = 1.0 / sqrt(beta_s);
-    for (int k = tid; k < K; k += kDrawThreads) {
+    for (int k = tid; k < K; k += NT) {
         mu[k] = mus[k] + zv[k] * rs;
         mu_out[k] = mu[k];
     }
     __syncthreads();
     // Lambda mu from the packed factor: Lambda mu = B (B^T mu)
-    for (int i = tid; i < K; i += kDrawThreads) {
+    for (int i = tid; i < K; i += NT) {
         double s = 0.0;
         for (int j = i; j < K; ++j) s += Bm[pk(j, i)] * mu[j];
         zv[i] = s;  // B^T mu
     }
     __syncthreads();
-    for (int i = tid; i < K; i += kDrawThreads) {
+    for (int i = tid; i < K; i += NT) {
         double s = 0.0;
         for (int j = 0; j <= i; ++j) s += Bm[pk(i, j)] * zv[j];
         Lmu_w[i] = (T)s;
     }
     if (Linv_w) {
         // for the rank-one row path: chol(Lambda)^-1 = B^-1 and B^T mu
-        for (int i = tid; i < K; i += kDrawThreads) Ltmu_w[i] = (T)zv[i];
+        for (int i = tid; i < K; i += NT) Ltmu_w[i] = (T)zv[i];
         __syncthreads();
-        tri_inverse_packed(K, Bm, Ci);
-        for (int e = tid; e < K * K; e += kDrawThreads) {
+        tri_inverse_packed<NT>(K, Bm, Ci);
+        for (int e = tid; e < K * K; e += NT) {
             const int r = e / K, cc = e - (e / K) * K;
             Linv_w[e] = cc <= r ? (T)Ci[pk(r, cc)] : (T)0;
         }
@@ -424,8 +430,8 @@ __global__ __launch_bounds__(kDrawThreads) void prior_factor(int K, const double
         P[e] = Lam[r * K + c];
     }
     __syncthreads();
-    chol_packed(K, P, &ok);
-    tri_inverse_packed(K, P, Ci);
+    chol_packed<kDrawThreads>(K, P, &ok);
+    tri_inverse_packed<kDrawThreads>(K, P, Ci);
     for (int e = tid; e < K * K; e += kDrawThreads) {
         const int r = e / K, cc = e - (e / K) * K;
         Linv_w[e] = cc <= r ? (T)Ci[pk(r, cc)] : (T)0;
@@ -518,22 +524,33 @@ hipError_t launch_hyper(bpmf_ctx *c, int side_id, hipStream_t s, uint32_t t_off)
         else if (ne <= 21) launch_moments<21>(c, sd, part, used, chunk, s);
         else launch_moments<33>(c, sd, part, used, chunk, s);
     }
-    hipLaunchKernelGGL(hyper_reduce, dim3((E + 63) / 64), dim3(64 * kRedWaves), 0, s, E, used, part, stats);
+    double *red = c->hyp_red[side_id];
+    hipLaunchKernelGGL(hyper_reduce_groups, dim3((E + 63) / 64, kRedGroups), dim3(64), 0, s, E, used, part, red);
+    hipLaunchKernelGGL(hyper_reduce, dim3((E + 63) / 64), dim3(64), 0, s, E, (const double *)red, stats);
     const int nb = lds_buffers(K, c->hyp_lds_max);
     const size_t lds2 = draw_lds(K, nb);
-    if (c->prec == 0)
-        hipLaunchKernelGGL((hyper_draw<double>), dim3(1), dim3(kDrawThreads), lds2, s, K, rows,
-                           stats, c->d_mu0, c->d_W0inv, c->beta0, c->nu0, c->seed,
-                           sd.stream_hyp, c->ctr, t_off, scratch, nb, sd.mu, sd.Lam,
-                           (double *)sd.Lam_w, (double *)sd.Lmu_w, (double *)nullptr,
-                           (double *)nullptr, c->hyp_status);
+    // K <= 64: 256 threads (four waves find room beside the other side's row
+    // kernels, where a 1024-thread workgroup waits for a whole free CU; one
+    // wave is slower again: the steps' work outweighs their barriers);
+    // above, 1024 threads
+    auto draw = [&](auto ntc) {
+        constexpr int NT = decltype(ntc)::value;
+        if (c->prec == 0)
+            hipLaunchKernelGGL((hyper_draw<NT, double>), dim3(1), dim3(NT), lds2, s, K, rows, stats, c->d_mu0,
+                               c->d_W0inv, c->beta0, c->nu0, c->seed, sd.stream_hyp, c->ctr, t_off, scratch, nb,
+                               sd.mu, sd.Lam, (double *)sd.Lam_w, (double *)sd.Lmu_w, (double *)nullptr,
+                               (double *)nullptr, c->hyp_status);
+        else
+            hipLaunchKernelGGL((hyper_draw<NT, float>), dim3(1), dim3(NT), lds2, s, K, rows, stats, c->d_mu0,
+                               c->d_W0inv, c->beta0, c->nu0, c->seed, sd.stream_hyp, c->ctr, t_off, scratch, nb,
+                               sd.mu, sd.Lam, (float *)sd.Lam_w, (float *)sd.Lmu_w,
+                               sd.n_low ? (float *)sd.Linv_w : (float *)nullptr,
+                               sd.n_low ? (float *)sd.Ltmu_w : (float *)nullptr, c->hyp_status);
+    };
+    if (K <= 64)
+        draw(std::integral_constant<int, 256>{});
     else
-        hipLaunchKernelGGL((hyper_draw<float>), dim3(1), dim3(kDrawThreads), lds2, s, K, rows,
-                           stats, c->d_mu0, c->d_W0inv, c->beta0, c->nu0, c->seed,
-                           sd.stream_hyp, c->ctr, t_off, scratch, nb, sd.mu, sd.Lam,
-                           (float *)sd.Lam_w, (float *)sd.Lmu_w,
-                           sd.n_low ? (float *)sd.Linv_w : (float *)nullptr,
-                           sd.n_low ? (float *)sd.Ltmu_w : (float *)nullptr, c->hyp_status);
+        draw(std::integral_constant<int, kDrawThreads>{});
     return hipGetLastError();
 }
 
@@ -544,11 +561,11 @@ hipError_t prepare_hyper(bpmf_ctx *c)
     if (e != hipSuccess) return e;
     c->hyp_lds_max = dev_max;
     const size_t need = draw_lds(c->K, lds_buffers(c->K, dev_max));
-    if (need > 65536) {
-        e = hipFuncSetAttribute((const void *)hyper_draw<double>,
+    if (need > 65536) {  // only above K = 64, where the draw has 1024 threads
+        e = hipFuncSetAttribute((const void *)hyper_draw<kDrawThreads, double>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)need);
         if (e == hipSuccess)
-            e = hipFuncSetAttribute((const void *)hyper_draw<float>,
+            e = hipFuncSetAttribute((const void *)hyper_draw<kDrawThreads, float>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)need);
         if (e != hipSuccess) {  // keep the draw within the default limit
             (void)hipGetLastError();

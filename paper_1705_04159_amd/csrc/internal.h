@@ -117,6 +117,7 @@ struct bpmf_ctx {
     int64_t hist_cap = 0;
     // hyper workspace, one set per side so that the two draws may overlap
     double *hyp_part[2] = {};     // [hyp_blocks * (K + K(K+1)/2)]
+    double *hyp_red[2] = {};      // [kHypRedGroups * (K + K(K+1)/2)] sums of the reduction's first pass
     int hyp_blocks = 0;
     double *hyp_stats[2] = {};    // [K + K(K+1)/2]
     double *hyp_scratch[2] = {};  // [4 * K * K + 8 * K]

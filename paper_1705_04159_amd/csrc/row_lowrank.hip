@@ -186,12 +186,37 @@ __global__ __launch_bounds__(64 * kLowWPB) void row_lowrank(
         vb[e] = c < K ? Ltmu[c] : 0.f;
     }
     Factor<C> F[DMAX];
+    // Up to 8 factors: every neighbour's id, rating and transformed row are
+    // loaded before the factors are built (two round trips to memory in
+    // all, not two per neighbour); the 16-factor instance has no registers
+    // to spare and loads them as it goes.
+    constexpr bool kPrefetch = DMAX <= 8;
+    float pa[kPrefetch ? DMAX : 1][C], pr[kPrefetch ? DMAX : 1];
+    if constexpr (kPrefetch) {
+        int pc[DMAX];
+#pragma unroll
+        for (int j = 0; j < DMAX; ++j) {
+            pc[j] = j < d ? nbr[it.beg + j] : -1;
+            pr[j] = j < d ? rc[it.beg + j] : 0.f;
+        }
+#pragma unroll
+        for (int j = 0; j < DMAX; ++j)
+#pragma unroll
+            for (int e = 0; e < C; ++e) {
+                const int c = C * l16 + e;
+                pa[j][e] = (pc[j] >= 0 && c < K) ? sa * Yt[(size_t)pc[j] * ld + c] : 0.f;  // 0: identity factor
+            }
+    }
     static_for<0, DMAX>([&](auto jc) {
         constexpr int j = decltype(jc)::value;
         if (j >= dw) return;  // uniform
         float a[C];
         float r = 0.f;
-        if (j < d) {
+        if constexpr (kPrefetch) {
+            r = pr[j];
+#pragma unroll
+            for (int e = 0; e < C; ++e) a[e] = pa[j][e];
+        } else if (j < d) {
             const int col = nbr[it.beg + j];
             r = rc[it.beg + j];
 #pragma unroll

@@ -541,6 +541,7 @@ int bpmf_create(int64_t M, int64_t N, const int64_t *csr_ptr, const int32_t *csr
         c->hyp_blocks = K <= 64 ? 2048 : 1024;  // row blocks of the moment sums (one wave each on the matrix-core path)
         for (int sid = 0; sid < 2; ++sid) {
             CK(dalloc(&c->hyp_part[sid], (size_t)c->hyp_blocks * (K + KK2)));
+            CK(dalloc(&c->hyp_red[sid], (size_t)16 * (K + KK2)));
             CK(dalloc(&c->hyp_stats[sid], (size_t)(K + KK2)));
             CK(dalloc(&c->hyp_scratch[sid], (size_t)4 * K * K + 8 * K));
         }
@@ -615,8 +616,8 @@ void bpmf_destroy(bpmf_ctx *c)
     for (auto &ev : c->tpool) (void)hipEventDestroy(ev);
     for (auto &s : c->side) free_side(s);
     void *ps[] = {c->d_mu0, c->d_W0inv, c->test_row, c->test_col, c->test_val, c->pred_sum,
-                  c->rmse_part, c->rmse_hist, c->hyp_part[0], c->hyp_stats[0], c->hyp_scratch[0],
-                  c->hyp_part[1], c->hyp_stats[1], c->hyp_scratch[1],
+                  c->rmse_part, c->rmse_hist, c->hyp_part[0], c->hyp_red[0], c->hyp_stats[0], c->hyp_scratch[0],
+                  c->hyp_part[1], c->hyp_red[1], c->hyp_stats[1], c->hyp_scratch[1],
                   c->hyp_status, c->part, c->ctr, c->q_row, c->q_col, c->q_out};
     for (void *p : ps) (void)hipFree(p);
     for (auto &ev : c->fork_ev)
