@@ -216,14 +216,19 @@ int bpmf_last_time_ms(bpmf_ctx *c, double *ms);
  * serial method (Sec. III, Fig. 2, Sec. IV-B); here three cut-offs are chosen
  * by timing n_sweeps (1..64) graph sweeps per candidate:
  *   - the degree above which a row is split into segments across
- *     wavefronts: 512, 1024, ... up to the first power of two at or above the
- *     largest degree, and the current one;
+ *     wavefronts: of 512, 1024, ... up to the first power of two at or above
+ *     the largest degree, those within a factor of four of the workload
+ *     model's threshold (or the one nearest it), and the current one.  The
+ *     model: a row costs r + d rating-equivalents, r = 3K, and with W the sum
+ *     over a side's rows and P the rows in flight on the GPU a row alone on
+ *     its wave must not take more than half of the side's stage, so
+ *     d* = W / (2P) - r, the smaller of the two sides';
  *   - for FP32 with 32 < K <= 64, whether rows take the column-per-lane
  *     (kmax 64) or the blocked (kmax 32) kernel;
  *   - for FP32 with K <= 64, the degree up to which rows take the rank-one
  *     update path (0 = off, 8, 16; a side uses it only where the saved
  *     factorisations outweigh transforming the gathered factor).
- * A candidate replaces the current plan only if it is at least 2% faster.
+ * A candidate replaces the current plan only if it is at least 1% faster.
  * The chain state (factors, hyperparameters, running predictions, sweep
  * counter) is restored afterwards, so the chain continues as if no trial had
  * run; only the plan changes, and the sweep graph of the chosen plan is

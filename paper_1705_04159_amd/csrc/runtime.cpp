@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -818,21 +819,60 @@ static int refresh_lowrank(bpmf_ctx *c)
     return BPMF_OK;
 }
 
+// Split threshold from the workload model of Sec. IV-B (measured as Fig. 2
+// on gfx950: a row costs a fixed amount plus an amount per rating, the
+// fixed part worth about 3K ratings in the factorising kernels at K = 32 and
+// K = 100).  With W = sum over a side's rows of (r + d_i), r = 3K, and P rows
+// in flight on the GPU, a row of degree d alone on its wave takes the share
+// (r + d) P / W of the side's stage; it does not prolong the stage while
+// that share is at most one half, so d* = W / (2P) - r.  The smaller d* of the
+// two sides (the threshold is shared).
+static double model_split(const bpmf_ctx *c)
+{
+    const int K = c->K;
+    const double r = 3.0 * K;
+    double P;  // rows in flight: SIMDs x waves per SIMD x rows per wave of the kernel family
+    if (c->prec == BPMF_FP64) P = 512.0;  // one 256-thread workgroup per row
+    else if (K <= 16) P = 1024.0 * 8 * 4;
+    else if (K <= 32) P = 1024.0 * 7 * 2;
+    else if (K <= 48) P = 1024.0 * 4;
+    else if (K <= 64) P = 1024.0 * 3;
+    else P = 1024.0 * 2;
+    double dstar = 1e300;
+    for (auto &sd : c->side) {
+        double W = 0.0;
+        for (int64_t i = 0; i < sd.rows; ++i) W += r + (double)(sd.hptr[i + 1] - sd.hptr[i]);
+        dstar = std::min(dstar, W / (2.0 * P) - r);
+    }
+    return std::max(1.0, dstar);
+}
+
 int bpmf_autotune(bpmf_ctx *c, uint32_t n_sweeps, int32_t *chosen_split, int32_t *chosen_kmax,
                   int32_t *chosen_low, int32_t *n_tried, int32_t *tried_split, int32_t *tried_kmax,
                   int32_t *tried_low, double *tried_ms)
 {
     STICKY(c);
     if (n_sweeps == 0 || n_sweeps > 64) return fail(c, BPMF_E_INVAL, "n_sweeps must be 1..64");
-    // candidate cut-offs: powers of two from 512 up to the first at or above
-    // the largest degree (no split), and the kernel families for FP32 K in (32, 64]
+    // candidate cut-offs: the powers of two from 512 up to the first at or
+    // above the largest degree (no split) that lie within a factor of four
+    // of the workload model's threshold (the one nearest it if none does),
+    // plus the current one; and the kernel families for FP32 K in (32, 64]
     int64_t max_deg = 0;
     for (auto &sd : c->side)
         for (int64_t r = 0; r < sd.rows; ++r) max_deg = std::max(max_deg, sd.hptr[r + 1] - sd.hptr[r]);
-    std::vector<int> splits;
+    const double dstar = model_split(c);
+    std::vector<int> all, splits;
     for (int64_t s = 512; s <= (1 << 24); s *= 2) {
-        splits.push_back((int)s);
+        all.push_back((int)s);
         if (s >= max_deg) break;
+    }
+    for (int s : all)
+        if (s >= dstar / 4 && s <= dstar * 4) splits.push_back(s);
+    if (splits.empty()) {
+        int near = all.front();
+        for (int s : all)
+            if (std::fabs(std::log((double)s / dstar)) < std::fabs(std::log((double)near / dstar))) near = s;
+        splits.push_back(near);
     }
     if (std::find(splits.begin(), splits.end(), c->split_threshold) == splits.end())
         splits.push_back(c->split_threshold);
@@ -874,7 +914,7 @@ int bpmf_autotune(bpmf_ctx *c, uint32_t n_sweeps, int32_t *chosen_split, int32_t
             }
         }
     // keep the current plan unless a candidate is clearly faster (timing noise)
-    if (best > 0.98 * incumbent) {
+    if (best > 0.99 * incumbent) {
         best_split = old_split;
         best_kmax = old_kmax;
         best_low = old_low;
