@@ -368,15 +368,27 @@ __global__ __launch_bounds__(NT) void hyper_draw(
         for (int l = 0; l < 4 && 4 * blk + l < K; ++l) zv[4 * blk + l] = z[l];
     }
     __syncthreads();
-    // x = B^-T z (column oriented, one barrier per step), in zv: step i
-    // takes x_i = zv[i] / B[i][i] (zv[i] final) and updates zv[j], j < i;
-    // the divisions are applied to zv at the end
-    for (int i = K - 1; i > 0; --i) {
-        const double xi = zv[i] / Bm[pk(i, i)];
-        for (int j = tid; j < i; j += NT) zv[j] -= Bm[pk(i, j)] * xi;
+    if (Linv_w) {
+        // the rank-one row path needs B^-1 anyway: x = B^-T z as a product
+        tri_inverse_packed<NT>(K, Bm, Ci);
+        for (int i = tid; i < K; i += NT) {
+            double s = 0.0;
+            for (int j = i; j < K; ++j) s += Ci[pk(j, i)] * zv[j];
+            mu[i] = s;  // staged: zv is still being read
+        }
         __syncthreads();
+        for (int i = tid; i < K; i += NT) zv[i] = mu[i];
+    } else {
+        // x = B^-T z (column oriented, one barrier per step), in zv: step i
+        // takes x_i = zv[i] / B[i][i] (zv[i] final) and updates zv[j], j < i;
+        // the divisions are applied to zv at the end
+        for (int i = K - 1; i > 0; --i) {
+            const double xi = zv[i] / Bm[pk(i, i)];
+            for (int j = tid; j < i; j += NT) zv[j] -= Bm[pk(i, j)] * xi;
+            __syncthreads();
+        }
+        for (int i = tid; i < K; i += NT) zv[i] /= Bm[pk(i, i)];
     }
-    for (int i = tid; i < K; i += NT) zv[i] /= Bm[pk(i, i)];
     __syncthreads();
     const double rs = 1.0 / sqrt(beta_s);
     for (int k = tid; k < K; k += NT) {
@@ -397,10 +409,9 @@ __global__ __launch_bounds__(NT) void hyper_draw(
         Lmu_w[i] = (T)s;
     }
     if (Linv_w) {
-        // for the rank-one row path: chol(Lambda)^-1 = B^-1 and B^T mu
+        // for the rank-one row path: chol(Lambda)^-1 = B^-1 (in Ci since the
+        // solve for mu) and B^T mu
         for (int i = tid; i < K; i += NT) Ltmu_w[i] = (T)zv[i];
-        __syncthreads();
-        tri_inverse_packed<NT>(K, Bm, Ci);
         for (int e = tid; e < K * K; e += NT) {
             const int r = e / K, cc = e - (e / K) * K;
             Linv_w[e] = cc <= r ? (T)Ci[pk(r, cc)] : (T)0;
