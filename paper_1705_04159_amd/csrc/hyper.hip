@@ -215,31 +215,64 @@ __global__ __launch_bounds__(64) void hyper_reduce(int E, const double *__restri
 }
 
 // In-place Cholesky of a packed lower K x K matrix (K <= 128) by the whole
-// workgroup, right-looking with the column scaling deferred so that each
-// pivot costs one barrier: step k subtracts P[i][k] P[j][k] / P[k][k] from
-// the trailing entries (i >= j > k), reading column k unscaled; at the end
-// column k is divided by sqrt(P[k][k]) and the pivot replaced by the root.
-// Clears *ok on a non-positive pivot (which is then taken as 1).
+// workgroup, right-looking with the column scaling deferred: step k
+// subtracts P[i][k] P[j][k] / P[k][k] from the trailing entries (i >= j > k),
+// reading column k unscaled; at the end column k is divided by
+// sqrt(P[k][k]) and the pivot replaced by the root.  Steps go in pairs, one
+// barrier per pair: every thread forms column k + 1 after step k from
+// columns k and k + 1 as they were (the same operations in the same order
+// as one step after the other), applies both steps to its trailing entries
+// (j >= k + 2), and the pair's own update of column k + 1 is written in the
+// next phase, when nothing reads that column.  Clears *ok on a
+// non-positive pivot (which is then taken as 1).
 template <int NT>
 __device__ void chol_packed(int K, double *P, int *ok)
 {
     __shared__ double root[128];
     const int tid = threadIdx.x;
     const int ti = tid & 31, tj = tid >> 5;  // a 32 x (NT / 32) tiling of the trailing triangle
-    for (int k = 0; k + 1 < K; ++k) {
-        double d = P[pk(k, k)];
-        if (!(d > 0.0)) d = 1.0;
-        const double rd = 1.0 / d;
-        for (int i = k + 1 + ti; i < K; i += 32) {
-            const double pik = P[pk(i, k)] * rd;
-            for (int j = k + 1 + tj; j <= i; j += NT / 32) P[pk(i, j)] -= pik * P[pk(j, k)];
+    auto inv_pivot = [&](int k) {
+        const double d = P[pk(k, k)];
+        return 1.0 / (d > 0.0 ? d : 1.0);
+    };
+    // column c's update by step c - 1 (the second column of the pair before)
+    auto pending = [&](int c) {
+        const double rd = inv_pivot(c - 1), p = P[pk(c, c - 1)];
+        for (int i = c + tid; i < K; i += NT) P[pk(i, c)] -= (P[pk(i, c - 1)] * rd) * p;
+    };
+    int k = 0;
+    for (; k + 2 <= K - 1; k += 2) {
+        if (k >= 2) pending(k - 1);
+        const double rd0 = inv_pivot(k);
+        const double p10 = P[pk(k + 1, k)];
+        double d1 = P[pk(k + 1, k + 1)] - (p10 * rd0) * p10;
+        const double rd1 = 1.0 / (d1 > 0.0 ? d1 : 1.0);
+        for (int i = k + 2 + ti; i < K; i += 32) {
+            const double pi0 = P[pk(i, k)] * rd0;
+            const double pi1 = (P[pk(i, k + 1)] - pi0 * p10) * rd1;
+            for (int j = k + 2 + tj; j <= i; j += NT / 32) {
+                const double aj = P[pk(j, k)];
+                const double qj = P[pk(j, k + 1)] - (aj * rd0) * p10;
+                double v = P[pk(i, j)];
+                v -= pi0 * aj;
+                v -= pi1 * qj;
+                P[pk(i, j)] = v;
+            }
         }
         __syncthreads();
     }
-    for (int k = tid; k < K; k += NT) {
-        const double d = P[pk(k, k)];
+    if (k >= 2) pending(k - 1);
+    if (k == K - 2) {  // one step left: column K - 2 onto the last pivot
+        if (tid == 0) {
+            const double pik = P[pk(K - 1, k)] * inv_pivot(k);
+            P[pk(K - 1, K - 1)] -= pik * P[pk(K - 1, k)];
+        }
+    }
+    __syncthreads();
+    for (int kk = tid; kk < K; kk += NT) {
+        const double d = P[pk(kk, kk)];
         if (!(d > 0.0)) *ok = 0;
-        root[k] = sqrt(d > 0.0 ? d : 1.0);
+        root[kk] = sqrt(d > 0.0 ? d : 1.0);
     }
     __syncthreads();
     const int KK2 = K * (K + 1) / 2;
@@ -252,9 +285,11 @@ __device__ void chol_packed(int K, double *P, int *ok)
 }
 
 // X = C^-1 for a packed lower C (X packed lower, distinct storage): forward
-// substitution on the identity with the row scaling deferred (one barrier
-// per pivot row): step k subtracts C[i][k] X[k][j] / C[k][k] from the rows
-// i > k, X[k] still unscaled; every row i is divided by C[i][i] at the end.
+// substitution on the identity with the row scaling deferred: step k
+// subtracts C[i][k] X[k][j] / C[k][k] from the rows i > k, X[k] still
+// unscaled; every row i is divided by C[i][i] at the end.  Steps go in
+// pairs, one barrier per pair, as in chol_packed: row k + 1 after step k is
+// formed by every thread that needs it and written in the next phase.
 template <int NT>
 __device__ void tri_inverse_packed(int K, const double *C, double *Xp)
 {
@@ -267,15 +302,35 @@ __device__ void tri_inverse_packed(int K, const double *C, double *Xp)
     }
     __syncthreads();
     const int ti = tid & 31, tj = tid >> 5;  // a 32 x (NT / 32) tiling of rows i > k, columns j <= k
-    for (int k = 0; k < K - 1; ++k) {
-        const double rck = 1.0 / C[pk(k, k)];
-        // rows i > k: X[i][j] -= C[i][k] X[k][j] / C[k][k], j <= k
-        for (int i = k + 1 + ti; i < K; i += 32) {
-            const double cik = C[pk(i, k)] * rck;
-            for (int j = tj; j <= k; j += NT / 32) Xp[pk(i, j)] -= cik * Xp[pk(k, j)];
+    // row r's update by step r - 1 (the second row of the pair before)
+    auto pending = [&](int r) {
+        const double c = C[pk(r, r - 1)] * (1.0 / C[pk(r - 1, r - 1)]);  // as in the pair
+        for (int j = tid; j <= r - 1; j += NT) Xp[pk(r, j)] -= c * Xp[pk(r - 1, j)];
+    };
+    int k = 0;
+    for (; k + 2 <= K - 1; k += 2) {
+        if (k >= 2) pending(k - 1);
+        const double rck0 = 1.0 / C[pk(k, k)], rck1 = 1.0 / C[pk(k + 1, k + 1)];
+        const double c10 = C[pk(k + 1, k)] * rck0;
+        for (int i = k + 2 + ti; i < K; i += 32) {
+            const double ci0 = C[pk(i, k)] * rck0, ci1 = C[pk(i, k + 1)] * rck1;
+            for (int j = tj; j <= k + 1; j += NT / 32) {
+                const double xk = j <= k ? Xp[pk(k, j)] : 0.0;
+                const double xk1 = j <= k ? Xp[pk(k + 1, j)] - c10 * xk : Xp[pk(k + 1, j)];
+                double v = Xp[pk(i, j)];
+                if (j <= k) v -= ci0 * xk;
+                v -= ci1 * xk1;
+                Xp[pk(i, j)] = v;
+            }
         }
         __syncthreads();
     }
+    if (k >= 2) pending(k - 1);
+    if (k == K - 2) {  // one step left: row K - 1 from row K - 2
+        const double c = C[pk(K - 1, k)] * (1.0 / C[pk(k, k)]);
+        for (int j = tid; j <= k; j += NT) Xp[pk(K - 1, j)] -= c * Xp[pk(k, j)];
+    }
+    __syncthreads();
     for (int e = tid; e < KK2; e += NT) {
         int i, j;
         tri_index(e, i, j);
