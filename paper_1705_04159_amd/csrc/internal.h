@@ -58,7 +58,7 @@ struct Side {
     uint16_t *Xbf = nullptr; // device [rows * ld] BF16 copy of the factor (BF16 mode)
     uint16_t *rc3 = nullptr; // device [3 * (nnz + 32)] the centred ratings as three BF16 parts,
                              // hi, mid and lo, each a plane in rc's order ending in 32 zeros
-                             // (BF16 mode; hi + mid + lo == rc exactly)
+                             // (BF16 mode, and FP32 with K <= 32; hi + mid + lo == rc exactly)
     double *mu = nullptr;    // device [K]
     double *Lam = nullptr;   // device [K * K]
     void *Lam_w = nullptr;   // device [K * K] Lambda in working precision
@@ -179,6 +179,9 @@ hipError_t launch_prior_to_working(bpmf_ctx *c, int side_id, hipStream_t s);
 hipError_t launch_to_bf16(bpmf_ctx *c, int side_id, hipStream_t s);
 // The centred ratings of a side as three BF16 parts (rc3).
 hipError_t launch_split_ratings(bpmf_ctx *c, int side_id, hipStream_t s);
+// FP32 contexts whose column-per-lane kernel forms its Gram from three-part
+// BF16 splits (they keep the rating planes rc3).
+bool parts_gram_wanted(const bpmf_ctx *c);
 // Largest dynamic LDS a generic row kernel needs for K (bytes).
 size_t row_generic_lds_bytes(int K, int prec);
 // Fold-in kernels (FP32 factors, K <= 64).

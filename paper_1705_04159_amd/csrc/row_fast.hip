@@ -46,6 +46,162 @@ hipError_t prepare_hyper(bpmf_ctx *c);
 
 namespace {
 
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float floatx2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// Two FP32 values as three BF16 parts each, x = h + m + l exactly (round to
+// nearest even at every step: h keeps the top 8 significant bits, m the
+// next 8 of the remainder, and the remainder after that has at most 8, so
+// l holds it exactly): |m| <= 2^-8 |x| (1 + 2^-8), |l| <= 2^-15 |x|.  The
+// parts of the pair come back packed as the two halves of h, m and l.
+__device__ __forceinline__ void split3(float x0, float x1, uint32_t &h, uint32_t &m, uint32_t &l)
+{
+    const floatx2 x = floatx2{x0, x1};
+    const bf16x2 hb = __builtin_convertvector(x, bf16x2);
+    const floatx2 r = x - __builtin_convertvector(hb, floatx2);
+    const bf16x2 mb = __builtin_convertvector(r, bf16x2);
+    const floatx2 t = r - __builtin_convertvector(mb, floatx2);
+    const bf16x2 lb = __builtin_convertvector(t, bf16x2);
+    h = __builtin_bit_cast(uint32_t, hb);
+    m = __builtin_bit_cast(uint32_t, mb);
+    l = __builtin_bit_cast(uint32_t, lb);
+}
+
+// FP32 Gram and rhs of one work item (whole wave) on the BF16 matrix cores
+// (v_mfma_f32_16x16x32_bf16).  Each gathered FP32 entry y is split into
+// three BF16 parts y = h + m + l (split3).  Block (bi, bj) of sum y y^T
+// takes the six part products hh, hm, mh, hl, lh, mm, each exact, summed in
+// FP32 by the matrix cores; the three left out (ml, lm, ll) are below
+// 2^-22 |y_i y_j| together (FP32 rounding of the product itself: 2^-24).
+// The rhs sum_j r'_j y_j uses the same instruction with the rating parts as
+// the A operand: rows 0, 1, 2 of that tile hold the hi, mid and lo parts of
+// r' (three planes, rc3), the other rows zero, and B runs over the three
+// parts of y, so rows 0..2 of the result are sum_k part_p(r'_k) y_k and
+// their sum is the rhs with all nine products.  Lane l holds, for the
+// ratings 8 (l / 16) + e, e = 0..7, of a chunk of 32, the parts of
+// component 16 bi + (l % 16): the A operand of block row bi and the B
+// operand of block column bj at once.  Components >= K read whatever
+// follows in the row (the caller ignores those entries); ratings past the
+// end of the item read 0 (buffer range check on the last chunk).
+template <int NB>
+__device__ __forceinline__ void gram_item_p3(const RowItem &it, const int32_t *__restrict__ nbr,
+                                             const uint16_t *__restrict__ rc3, uint32_t plane,
+                                             __amdgpu_buffer_rsrc_t ysrc, uint32_t ldy4, int kq, int col,
+                                             floatx4 (&acc)[NB * (NB + 1) / 2], floatx4 (&racc)[NB])
+{
+    const uint32_t cnt = (uint32_t)(it.end - it.beg);
+    const __amdgpu_buffer_rsrc_t jsrc = make_rsrc(nbr + it.beg, cnt * 4u);
+    const __amdgpu_buffer_rsrc_t psrc = make_rsrc(rc3 + it.beg, (uint32_t)(3u * plane - (uint32_t)it.beg) * 2u);
+    const uint32_t poff = col < 3 ? 2u * ((uint32_t)col * plane + 8u * kq) : kOOB;
+    const uint32_t coff = 4u * col;
+    const uint32_t nchunk = (cnt + 31) / 32;
+    // software pipeline: the next chunk's rows and rating parts, and the ids
+    // of the chunk after it, are in flight during a chunk's products
+    uint32_t jb[8];
+    float yv[NB][8];
+    u32x4 rp;
+    auto load_ids = [&](uint32_t ch) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) jb[e] = buf_u32_stream(jsrc, (ch * 32 + 8 * kq + e) * 4u);
+    };
+    auto load_rows_t = [&](uint32_t ch, auto checkc) {
+        constexpr bool CHECK = decltype(checkc)::value;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const uint32_t t = ch * 32 + 8 * kq + e;
+            uint32_t base = __umul24(jb[e], ldy4) + coff;  // fewer than 2^24 rows
+            if constexpr (CHECK) base = t < cnt ? base : kOOB;
+#pragma unroll
+            for (int bi = 0; bi < NB; ++bi) yv[bi][e] = buf_f32(ysrc, base + 64u * bi);
+        }
+        rp = __builtin_amdgcn_raw_buffer_load_b128(psrc, poff + ch * 64u, 0, kStreamPolicy);
+    };
+    // only the last chunk (or chunk 0 of an empty item) runs past the end
+    auto load_rows = [&](uint32_t ch) {
+        if (ch + 1 < nchunk)
+            load_rows_t(ch, std::integral_constant<bool, false>{});
+        else
+            load_rows_t(ch, std::integral_constant<bool, true>{});
+    };
+    bf16x8 H[NB], Md[NB], L[NB], R;
+    auto convert = [&]() {
+#pragma unroll
+        for (int bi = 0; bi < NB; ++bi) {
+            u32x4 h, m, l;
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                uint32_t a, b, c;
+                split3(yv[bi][2 * p], yv[bi][2 * p + 1], a, b, c);
+                h[p] = a;
+                m[p] = b;
+                l[p] = c;
+            }
+            H[bi] = __builtin_bit_cast(bf16x8, h);
+            Md[bi] = __builtin_bit_cast(bf16x8, m);
+            L[bi] = __builtin_bit_cast(bf16x8, l);
+        }
+        R = __builtin_bit_cast(bf16x8, rp);
+    };
+    auto products = [&](auto firstc) {
+        constexpr bool FIRST = decltype(firstc)::value;
+        const floatx4 zero = floatx4{0.f, 0.f, 0.f, 0.f};
+        // the small products first, block by block interleaved
+        int q = 0;
+#pragma unroll
+        for (int bi = 0; bi < NB; ++bi)
+#pragma unroll
+            for (int bj = 0; bj <= bi; ++bj, ++q)
+                acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Md[bi], Md[bj], FIRST ? zero : acc[q], 0, 0, 0);
+#pragma unroll
+        for (int bj = 0; bj < NB; ++bj)
+            racc[bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(R, L[bj], FIRST ? zero : racc[bj], 0, 0, 0);
+        q = 0;
+#pragma unroll
+        for (int bi = 0; bi < NB; ++bi)
+#pragma unroll
+            for (int bj = 0; bj <= bi; ++bj, ++q) {
+                acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(L[bi], H[bj], acc[q], 0, 0, 0);
+                acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(H[bi], L[bj], acc[q], 0, 0, 0);
+            }
+#pragma unroll
+        for (int bj = 0; bj < NB; ++bj)
+            racc[bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(R, Md[bj], racc[bj], 0, 0, 0);
+        q = 0;
+#pragma unroll
+        for (int bi = 0; bi < NB; ++bi)
+#pragma unroll
+            for (int bj = 0; bj <= bi; ++bj, ++q) {
+                acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Md[bi], H[bj], acc[q], 0, 0, 0);
+                acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(H[bi], Md[bj], acc[q], 0, 0, 0);
+            }
+#pragma unroll
+        for (int bj = 0; bj < NB; ++bj)
+            racc[bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(R, H[bj], racc[bj], 0, 0, 0);
+        q = 0;
+#pragma unroll
+        for (int bi = 0; bi < NB; ++bi)
+#pragma unroll
+            for (int bj = 0; bj <= bi; ++bj, ++q)
+                acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(H[bi], H[bj], acc[q], 0, 0, 0);
+    };
+    // chunk ch: its rows are in registers, the ids of chunk ch + 1 in jb;
+    // the next chunk's rows are issued before this chunk's products, then
+    // the ids of the chunk after it
+    auto step = [&](uint32_t ch, auto firstc) {
+        convert();
+        if (ch + 1 < nchunk) load_rows(ch + 1);
+        if (ch + 2 < nchunk) load_ids(ch + 2);
+        products(firstc);
+    };
+    // chunk 0 even for an empty item: every row it loads is 0 (out of range)
+    load_ids(0);
+    load_rows(0);
+    if (nchunk > 1) load_ids(1);
+    step(0u, std::integral_constant<bool, true>{});
+    for (uint32_t ch = 1; ch < nchunk; ++ch) step(ch, std::integral_constant<bool, false>{});
+}
 
 // Factor and sample one row held column-per-lane: lane c of the group has
 // v[r] = P[r][c] for r < KP (identity outside the leading K x K block) and
@@ -117,11 +273,14 @@ __global__ __launch_bounds__(256) void prior_packed(int K, int KP, const float *
 
 // At least six waves per SIMD asked of the register allocator (K = 32: 71
 // registers, so seven fit), which hides more of the gather latency than
-// the unrestricted allocation's extra unrolling.
-template <int NB, int RPW, int WPB>
-__global__ __launch_bounds__(64 * WPB, 6) void row_fast_f32(
+// the unrestricted allocation's extra unrolling.  With P3 the Gram runs on
+// the BF16 matrix cores from three-part splits of the FP32 rows and the
+// rating planes rc3 (gram_item_p3); otherwise on the FP32 ones.
+template <int NB, int RPW, int WPB, bool P3>
+__global__ __launch_bounds__(64 * WPB, P3 ? 5 : 6) void row_fast_f32(
     int K, float alpha, const RowItem *__restrict__ items, int64_t item0, int64_t n_items,
-    const int32_t *__restrict__ nbr, const float *__restrict__ rc, const float *__restrict__ Y,
+    const int32_t *__restrict__ nbr, const float *__restrict__ rc, const uint16_t *__restrict__ rc3,
+    uint32_t plane, const void *__restrict__ Y,
     int ldy, uint32_t y_bytes, const float *__restrict__ LamPk, const float *__restrict__ Lmu,
     float *__restrict__ X, int ldx, float *__restrict__ part, uint64_t seed, uint32_t stream,
     const uint32_t *__restrict__ ctr, int *__restrict__ status)
@@ -173,14 +332,22 @@ __global__ __launch_bounds__(64 * WPB, 6) void row_fast_f32(
 #pragma unroll
         for (int q = 0; q < NBLK; ++q) acc[q] = floatx4{0.f, 0.f, 0.f, 0.f};
         float bacc[NB];
+        if constexpr (P3) {
+            floatx4 racc[NB];
+            gram_item_p3<NB>(it, nbr, rc3, plane, ysrc, ldy4, kq, col, acc, racc);
+            // rows 0..2 of the rhs tile (lanes 0..15: kq = 0), the three rating parts
 #pragma unroll
-        for (int bi = 0; bi < NB; ++bi) bacc[bi] = 0.f;
-        gram_item<NB, true>(it, nbr, rc, ysrc, ldy4, lane_off, kq, acc, bacc);
-        // sum the rhs over the four rating slots of each 16-lane column
+            for (int bi = 0; bi < NB; ++bi) bacc[bi] = (racc[bi][0] + racc[bi][1]) + racc[bi][2];
+        } else {
 #pragma unroll
-        for (int bi = 0; bi < NB; ++bi) {
-            bacc[bi] += __shfl_xor(bacc[bi], 16);
-            bacc[bi] += __shfl_xor(bacc[bi], 32);
+            for (int bi = 0; bi < NB; ++bi) bacc[bi] = 0.f;
+            gram_item<NB, true>(it, nbr, rc, ysrc, ldy4, lane_off, kq, acc, bacc);
+            // sum the rhs over the four rating slots of each 16-lane column
+#pragma unroll
+            for (int bi = 0; bi < NB; ++bi) {
+                bacc[bi] += __shfl_xor(bacc[bi], 16);
+                bacc[bi] += __shfl_xor(bacc[bi], 32);
+            }
         }
         if (it.slot >= 0) {  // segment of a split row: raw partial sums
             float *dst = part + (size_t)it.slot * (KK2 + K);
@@ -408,13 +575,22 @@ hipError_t launch_f32(bpmf_ctx *c, Side &sd, Side &ot, hipStream_t s, int64_t it
     const int64_t count = item_end - item0;
     const int64_t per_block = (int64_t)WPB * RPW;
     const unsigned grid = (unsigned)((count + per_block - 1) / per_block);
-    const uint32_t y_bytes = (uint32_t)(ot.rows * c->ld * sizeof(float));
     if (count <= 0) return hipSuccess;
-    hipLaunchKernelGGL((row_fast_f32<NB, RPW, WPB>), dim3(grid), dim3(64 * WPB), lds, s, c->K,
-                       (float)c->alpha, sd.items, item0, item_end, sd.nbr, (const float *)sd.rc,
-                       (const float *)ot.X, c->ld, y_bytes, (const float *)sd.Lam_pk,
-                       (const float *)sd.Lmu_w, (float *)sd.X, c->ld, (float *)c->part, c->seed,
-                       sd.stream_row, c->ctr, c->hyp_status + 1);
+    auto go = [&](auto kern, const void *Y, uint32_t y_bytes) {
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * WPB), lds, s, c->K, (float)c->alpha, sd.items, item0,
+                           item_end, sd.nbr, (const float *)sd.rc, (const uint16_t *)sd.rc3,
+                           (uint32_t)(c->nnz + 32), Y, c->ld, y_bytes, (const float *)sd.Lam_pk,
+                           (const float *)sd.Lmu_w, (float *)sd.X, c->ld, (float *)c->part, c->seed,
+                           sd.stream_row, c->ctr, c->hyp_status + 1);
+    };
+    const uint32_t y_bytes = (uint32_t)(ot.rows * c->ld * sizeof(float));
+    if constexpr (NB <= 2) {
+        if (sd.rc3) {
+            go(row_fast_f32<NB, RPW, WPB, true>, ot.X, y_bytes);
+            return hipGetLastError();
+        }
+    }
+    go(row_fast_f32<NB, RPW, WPB, false>, ot.X, y_bytes);
     return hipGetLastError();
 }
 
@@ -471,6 +647,14 @@ bool fast_path_available(const bpmf_ctx *c)
         if ((uint64_t)c->side[s].rows * c->ld * sizeof(float) >= kOOB || c->side[s].rows >= (1 << 24))
             return false;  // 32-bit buffer offsets, 24-bit row ids in the gather
     return (uint64_t)c->split_threshold * 4u < kOOB;
+}
+
+// FP32 factors with K <= 32: the column-per-lane kernel's Gram on the BF16
+// matrix cores from three-part splits (needs the rating planes, read at
+// 32-bit buffer offsets).
+bool parts_gram_wanted(const bpmf_ctx *c)
+{
+    return c->prec == 1 && c->K <= 32 && 6u * ((uint64_t)c->nnz + 32u) < kOOB;
 }
 
 hipError_t launch_row_fast(bpmf_ctx *c, int side_id, hipStream_t s, int stage, bool *handled)

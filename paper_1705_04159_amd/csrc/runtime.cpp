@@ -476,10 +476,12 @@ int bpmf_create(int64_t M, int64_t N, const int64_t *csr_ptr, const int32_t *csr
             CK(hipMalloc(&sd.rc, std::max<size_t>(1, nnz) * es));
             CK(hipMalloc(&sd.X, std::max<size_t>(1, (size_t)sd.rows * c->ld) * es));
             if (c->prec == BPMF_BF16_GRAM) CK(dalloc(&sd.Xbf, (size_t)sd.rows * c->ld));
-            // rating parts for the matrix-core rhs of the blocked kernel (read
-            // at byte offsets below 2^30 across all three planes; beyond that
-            // the kernel sums the rhs on the vector units)
-            if (c->prec == BPMF_BF16_GRAM && 6 * ((uint64_t)nnz + 32) < (1ull << 30))
+            // rating parts for the matrix-core rhs of the blocked kernel and of
+            // the FP32 K <= 32 kernel's three-part Gram (read at byte offsets
+            // below 2^30 across all three planes; beyond that the blocked
+            // kernel sums the rhs on the vector units and the K <= 32 one
+            // keeps its FP32 Gram)
+            if ((c->prec == BPMF_BF16_GRAM || parts_gram_wanted(c)) && 6 * ((uint64_t)nnz + 32) < (1ull << 30))
                 CK(dalloc(&sd.rc3, 3 * ((size_t)nnz + 32)));
             CK(dalloc(&sd.mu, K));
             CK(dalloc(&sd.Lam, (size_t)K * K));
@@ -590,10 +592,8 @@ int bpmf_create(int64_t M, int64_t N, const int64_t *csr_ptr, const int32_t *csr
         for (int sid = 0; sid < 2; ++sid) {
             CK(launch_init_factor(c, sid, c->stream));
             CK(launch_prior_to_working(c, sid, c->stream));
-            if (c->prec == BPMF_BF16_GRAM) {
-                CK(launch_to_bf16(c, sid, c->stream));
-                CK(launch_split_ratings(c, sid, c->stream));
-            }
+            if (c->prec == BPMF_BF16_GRAM) CK(launch_to_bf16(c, sid, c->stream));
+            CK(launch_split_ratings(c, sid, c->stream));  // if the side has rating parts
         }
         CK(hipStreamSynchronize(c->stream));
     }
