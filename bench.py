@@ -74,6 +74,34 @@ def side_degrees(r):
 
 
 PEAK_FP64_TFLOPS = 78.6  # MI355X dense FP64 (matrix cores), TFLOP/s
+# The FP32 Gram of the K <= 32 kernel runs on the BF16 matrix cores as six
+# products of three-part BF16 splits per FP32 product.
+P3_PRODUCTS = 6
+P3_KMAX = 32
+
+
+def split_work(K, prec):
+    """Whether the Gram and the factorisation are priced apart: the BF16-Gram
+    form, and FP32 at K <= 32 (Gram on the BF16 matrix cores); the divisor
+    of the BF16 rate for the Gram (products per algorithmic product)."""
+    if prec == "bf16":
+        return True, 1
+    if prec == "fp32" and K <= P3_KMAX:
+        return True, P3_PRODUCTS
+    return False, 1
+
+
+def gram_arith(K, prec):
+    """How the row kernels form the Gram for this precision and K."""
+    if prec == "fp64":
+        return "fp64"
+    if prec == "bf16":
+        return "bf16 products, fp32 accumulation"
+    if K <= P3_KMAX:
+        return "fp32 as three bf16 parts, six products, fp32 accumulation"
+    return "fp32"
+
+
 GATHER_SOURCES_MB = (3.4, 18.0, 96.0, 192.0)  # one L2, Infinity Cache, HBM-sized sources
 
 
@@ -107,7 +135,8 @@ def sweep_roofline(K, prec, r, ms_per_step, peaks, n_low=None):
     updates, with the algorithmic work of `algorithmic` for every row and
     rating.  Against the spec sheet (FP32 work at 157.3 TFLOP/s; in the
     BF16-Gram form the Gram at 2.5 PFLOP/s and the factorisation at
-    157.3; bytes at 8 TB/s, the gather counted only when its source exceeds
+    157.3, and the same split for FP32 at K <= 32 with the Gram at 2.5 / 6
+    PFLOP/s; bytes at 8 TB/s, the gather counted only when its source exceeds
     one L2) and against the measured peaks (the same split of the work;
     compulsory bytes at the triad rate plus every gathered row at the
     measured gather rate for a source of that factor's size).  The fraction
@@ -123,10 +152,11 @@ def sweep_roofline(K, prec, r, ms_per_step, peaks, n_low=None):
         gram, fact, byts = algorithmic(K, degs[name], n_low.get(name, 0), other, ld * esize, src)
         gathered = ld * esize * r.nnz
         compulsory = byts - (gathered if src > L2_BYTES else 0)
+        split, nprod = split_work(K, prec)
         if prec == "fp64":
             spec = {"mfma": (gram + fact) / (PEAK_FP64_TFLOPS * 1e12), "valu": 0.0}
-        elif prec == "bf16":
-            spec = {"mfma": gram / (PEAK_BF16_TFLOPS * 1e12), "valu": fact / (PEAK_FP32_TFLOPS * 1e12)}
+        elif split:
+            spec = {"mfma": gram * nprod / (PEAK_BF16_TFLOPS * 1e12), "valu": fact / (PEAK_FP32_TFLOPS * 1e12)}
         else:
             spec = {"mfma": (gram + fact) / (PEAK_FP32_TFLOPS * 1e12), "valu": 0.0}
         spec["hbm"] = byts / (PEAK_HBM_GBS * 1e9)
@@ -137,8 +167,8 @@ def sweep_roofline(K, prec, r, ms_per_step, peaks, n_low=None):
             p32 = max(peaks["fp32_mfma_tflops"], peaks["fp32_valu_tflops"]) * 1e12
             if prec == "fp64":
                 meas = {"mfma": (gram + fact) / (peaks["fp64_mfma_tflops"] * 1e12), "valu": 0.0}
-            elif prec == "bf16":
-                meas = {"mfma": gram / (peaks["bf16_mfma_tflops"] * 1e12), "valu": fact / p32}
+            elif split:
+                meas = {"mfma": gram * nprod / (peaks["bf16_mfma_tflops"] * 1e12), "valu": fact / p32}
             else:
                 meas = {"mfma": (gram + fact) / (peaks["fp32_mfma_tflops"] * 1e12), "valu": 0.0}
             g = peaks["gather_gbs"][str(int(src))]
@@ -260,7 +290,8 @@ def kernel_roofline(K, prec, r, k_ms, peaks, n_low, steps):
     timed sweeps), with its algorithmic FLOP and bytes per launch against
     the peak of its own arithmetic (FP32 matrix cores; in the BF16-Gram form
     the Gram at the BF16 peak and the factorisation at the FP32 one,
-    time-weighted) or HBM, whichever bound is higher; also against the peaks
+    time-weighted; for FP32 at K <= 32 the same with the Gram at a sixth of
+    the BF16 peak) or HBM, whichever bound is higher; also against the peaks
     measured on this GPU, and the HBM traffic of the committed counter
     summary for this workload and side (None if there is none or the
     kernel's sources changed since)."""
@@ -276,8 +307,9 @@ def kernel_roofline(K, prec, r, k_ms, peaks, n_low, steps):
     flops = gram + fact
     sec = k_ms[dom] / 1000.0
     peak = PEAK_FP64_TFLOPS if prec == "fp64" else PEAK_FP32_TFLOPS
-    if prec == "bf16":
-        peak = flops / (gram / PEAK_BF16_TFLOPS + fact / PEAK_FP32_TFLOPS)
+    split, nprod = split_work(K, prec)
+    if split:
+        peak = flops / (gram * nprod / PEAK_BF16_TFLOPS + fact / PEAK_FP32_TFLOPS)
     t_mfma = flops / (peak * 1e12)
     t_hbm = byts / (PEAK_HBM_GBS * 1e9)
     if t_hbm > t_mfma:
@@ -297,8 +329,8 @@ def kernel_roofline(K, prec, r, k_ms, peaks, n_low, steps):
         else:
             p32 = peaks["fp32_mfma_tflops"]
             pm = p32
-            if prec == "bf16":
-                pm = flops / (gram / peaks["bf16_mfma_tflops"]
+            if split:
+                pm = flops / (gram * nprod / peaks["bf16_mfma_tflops"]
                               + fact / max(p32, peaks["fp32_valu_tflops"]))
             elif prec == "fp64":
                 pm = peaks["fp64_mfma_tflops"]
@@ -648,7 +680,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": r.name, "M": r.M, "N": r.N, "nnz_train": r.nnz,
                    "n_test": int(len(r.test_row)), "K": K, "precision": prec,
-                   "parallelism": "single-gpu"},
+                   "gram": gram_arith(K, prec), "parallelism": "single-gpu"},
         "ratings_per_s": round(2 * r.nnz / (ms_per_step / 1000.0), 1),
         "rmse_avg": round(float(avg[-1]), 5),
         "rmse_last": round(float(last[-1]), 5),
