@@ -80,7 +80,9 @@ __global__ __launch_bounds__(256) void predict_test(
     const int grp = threadIdx.x / G;
     const int64_t groups_total = (int64_t)gridDim.x * GPB;
     double sa = 0.0, sl = 0.0;
-    for (int64_t e0 = (int64_t)blockIdx.x * GPB + grp; e0 < n; e0 += P * groups_total) {
+    // a group takes P consecutive pairs: the pairs are in user order, so
+    // they mostly share the user's row (cache hits after the first)
+    for (int64_t e0 = ((int64_t)blockIdx.x * GPB + grp) * P; e0 < n; e0 += P * groups_total) {
         int64_t e[P];
         bool ok[P];
         int32_t ri[P], ci[P];
@@ -88,7 +90,7 @@ __global__ __launch_bounds__(256) void predict_test(
         double prev[P];
 #pragma unroll
         for (int q = 0; q < P; ++q) {
-            e[q] = e0 + q * groups_total;
+            e[q] = e0 + q;
             ok[q] = e[q] < n;
             ri[q] = ok[q] ? row[e[q]] : 0;
             ci[q] = ok[q] ? col[e[q]] : 0;

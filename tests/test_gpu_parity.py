@@ -219,6 +219,23 @@ def test_row_update_single_step(bp, orc, prec, K, side):
     assert err.max() <= TOL[prec], (err.max(), np.argmax(err))
 
 
+@pytest.mark.parametrize("K", [10, 32])
+@pytest.mark.parametrize("side", [0, 1])
+def test_fp32_three_part_gram_accuracy(bp, orc, K, side):
+    """FP32 at K <= 32 sums the Gram from six products of exact three-part
+    BF16 splits of the FP32 rows (each term within 2^-22 of y_i y_j); its
+    error against the FP64 oracle stays at the level of the blocked
+    kernel's Gram of FP32 matrix products on the same rows and state."""
+    r = synth.random_small(40 + K, 700, 300, 20000, min(K, 16), empty_rows=5)
+    e3, g3, _ = single_step(bp, orc, r, K, "fp32", side, plan=(2048, 32, 0))
+    e1, g1, _ = single_step(bp, orc, r, K, "fp32", side, plan=(2048, 0, 0))
+    _say("  K=%d side=%d: three-part max %.2e median %.2e; FP32 products max %.2e median %.2e" % (
+        K, side, e3.max(), np.median(e3), e1.max(), np.median(e1)))
+    assert np.isfinite(g3).all() and np.isfinite(g1).all()
+    assert e3.max() <= 2e-5
+    assert np.median(e3) <= 3 * np.median(e1) + 1e-7
+
+
 @pytest.mark.parametrize("K", [10, 32, 64, 100])
 @pytest.mark.parametrize("side", [0, 1])
 def test_bf16_gram_against_unrounded_oracle(bp, orc, K, side):
