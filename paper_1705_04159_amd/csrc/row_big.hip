@@ -527,7 +527,7 @@ __global__ __launch_bounds__(64 * kBigWPB, big_waves<NB>()) void row_finish_big(
     int K, float alpha, const FinishItem *__restrict__ fin, int64_t n_fin,
     const float *__restrict__ part, const floatx4 *__restrict__ img, const float *__restrict__ Lmu,
     float *__restrict__ X, int ldx, uint64_t seed, uint32_t stream,
-    const uint32_t *__restrict__ ctr, int *__restrict__ status)
+    const uint32_t *__restrict__ ctr, int *__restrict__ status, int summed)
 {
     constexpr int NBLK = NB * (NB + 1) / 2;
     extern __shared__ float smem_f[];
@@ -539,13 +539,15 @@ __global__ __launch_bounds__(64 * kBigWPB, big_waves<NB>()) void row_finish_big(
     const int col = lane & 15;
     const int kq = lane >> 4;
     const FinishItem f = fin[fid];
-    // the row's partial slots summed in slot order
+    // the row's partial slots summed in slot order (with `summed`, already
+    // summed into the first by part_reduce, in the same order)
     const float *src = part + (size_t)f.first * big_slot_elems<NB>();
+    const int count = summed ? 1 : f.count;
     floatx4 acc[NBLK];
 #pragma unroll
     for (int q = 0; q < NBLK; ++q) acc[q] = floatx4{0.f, 0.f, 0.f, 0.f};
     float bs[2] = {0.f, 0.f};
-    for (int sl = 0; sl < f.count; ++sl) {
+    for (int sl = 0; sl < count; ++sl) {
         const float *sq = src + (size_t)sl * big_slot_elems<NB>();
 #pragma unroll
         for (int q = 0; q < NBLK; ++q) acc[q] += reinterpret_cast<const floatx4 *>(sq)[q * 64 + lane];
@@ -595,11 +597,20 @@ hipError_t launch_big(bpmf_ctx *c, Side &sd, Side &ot, hipStream_t s, int stage)
     }
     if (stage == kStageFinish) {
         if (sd.n_fin == 0) return hipSuccess;
+        // up to K = 64 the slots are summed first by one thread per entry and
+        // row (the same order as the finishing's own sum), so that a row with
+        // many segments does not leave one wavefront streaming all its slots;
+        // above, the finishing's own float4 sum measured faster
+        constexpr bool summed = NB <= 4;
+        if constexpr (summed) {
+            const hipError_t e = launch_part_reduce(c, sd, s, big_slot_elems<NB>());
+            if (e != hipSuccess) return e;
+        }
         const unsigned grid = (unsigned)((sd.n_fin + kBigWPB - 1) / kBigWPB);
         hipLaunchKernelGGL((row_finish_big<NB>), dim3(grid), dim3(64 * kBigWPB), lds, s, c->K,
                            (float)c->alpha, sd.fin, sd.n_fin, (const float *)c->part, img,
                            (const float *)sd.Lmu_w, (float *)sd.X, c->ld, c->seed, sd.stream_row,
-                           c->ctr, c->hyp_status + 1);
+                           c->ctr, c->hyp_status + 1, summed ? 1 : 0);
         return hipGetLastError();
     }
     if (stage != kStageSegments && stage != kStageRows) return hipSuccess;

@@ -509,7 +509,8 @@ __global__ __launch_bounds__(64 * WPB) void foldin_draw_f32(
 }
 
 // Sum the partial slots of every split row into its first slot, in slot
-// order (one thread per (row, entry)).
+// order (one thread per (row, entry)); eight slots' loads in flight at a
+// time, added in order.
 __global__ __launch_bounds__(256) void part_reduce(const FinishItem *__restrict__ fin, int E,
                                                    float *__restrict__ part)
 {
@@ -518,7 +519,15 @@ __global__ __launch_bounds__(256) void part_reduce(const FinishItem *__restrict_
     if (e >= E || f.count <= 1) return;
     float *base = part + (size_t)f.first * E + e;
     float s = 0.f;
-    for (int q = 0; q < f.count; ++q) s += base[(size_t)q * E];
+    int q = 0;
+    for (; q + 8 <= f.count; q += 8) {
+        float x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) x[u] = base[(size_t)(q + u) * E];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += x[u];
+    }
+    for (; q < f.count; ++q) s += base[(size_t)q * E];
     base[0] = s;
 }
 
