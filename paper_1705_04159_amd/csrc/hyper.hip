@@ -339,6 +339,39 @@ __device__ void tri_inverse_packed(int K, const double *C, double *Xp)
     __syncthreads();
 }
 
+// The lower 16 x 16 blocks of a K x K product D = X Y on the FP64 matrix
+// cores (v_mfma_f64_16x16x4_f64), the workgroup's waves taking the blocks
+// in turn: block (bi, bj), bi >= bj, sums k over [k0, k1) = krange(bi, bj)
+// in steps of four, lane l feeding X[16 bi + l % 16][k + l / 16] as the A
+// operand and Y[k + l / 16][16 bj + l % 16] as the B operand (xf and yf
+// return 0 outside their matrices' triangles and past K); out(i, j, d)
+// receives every D[i][j] with j <= i < K (value v of lane l is
+// D[4 v + l / 16][l % 16] of the block).  Every wave runs uniform loops.
+template <int NT, typename XF, typename YF, typename KR, typename OUT>
+__device__ __forceinline__ void lower_product_mfma(int K, XF xf, YF yf, KR krange, OUT out)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = lane & 15, kq = lane >> 4;
+    const int nb = (K + 15) / 16;
+    for (int q = wave; q < nb * (nb + 1) / 2; q += NT / 64) {
+        int bi, bj;
+        tri_index(q, bi, bj);
+        int k0, k1;
+        krange(bi, bj, k0, k1);
+        doublex4 acc = doublex4{0.0, 0.0, 0.0, 0.0};
+        for (int kk = k0; kk < k1; kk += 4) {
+            const double a = xf(16 * bi + col, kk + kq);
+            const double b = yf(kk + kq, 16 * bj + col);
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = 16 * bi + 4 * v + kq, j = 16 * bj + col;
+            if (i < K && j <= i) out(i, j, acc[v]);
+        }
+    }
+}
+
 template <int NT, typename T>
 __global__ __launch_bounds__(NT) void hyper_draw(
     int K, int64_t n, const double *__restrict__ stats, const double *__restrict__ mu0,
@@ -397,26 +430,31 @@ __global__ __launch_bounds__(NT) void hyper_draw(
         }
     }
     __syncthreads();
-    // B = L_W A, L_W[r][m] = C^-1[K-1-m][K-1-r]
-    for (int e = tid; e < KK2; e += NT) {
-        int r, c;
-        tri_index(e, r, c);
-        double s = 0.0;
-        for (int m = c; m <= r; ++m) s += Ci[pk(K - 1 - m, K - 1 - r)] * Cm[pk(m, c)];
-        Bm[e] = s;
-    }
+    // B = L_W A, L_W[r][m] = C^-1[K-1-m][K-1-r] (lower), A lower: block
+    // (bi, bj) sums m over blocks bj .. bi
+    lower_product_mfma<NT>(
+        K, [&](int r, int m) { return (r < K && m <= r) ? Ci[pk(K - 1 - m, K - 1 - r)] : 0.0; },
+        [&](int m, int c) { return (m < K && c <= m) ? Cm[pk(m, c)] : 0.0; },
+        [](int bi, int bj, int &k0, int &k1) {
+            k0 = 16 * bj;
+            k1 = 16 * bi + 16;
+        },
+        [&](int r, int c, double d) { Bm[pk(r, c)] = d; });
     __syncthreads();
-    // Lambda = B B^T
-    for (int e = tid; e < KK2; e += NT) {
-        int r, c;
-        tri_index(e, r, c);
-        double s = 0.0;
-        for (int m = 0; m <= c; ++m) s += Bm[pk(r, m)] * Bm[pk(c, m)];
-        Lam_out[r * K + c] = s;
-        Lam_out[c * K + r] = s;
-        Lam_w[r * K + c] = (T)s;
-        Lam_w[c * K + r] = (T)s;
-    }
+    // Lambda = B B^T: block (bi, bj) sums m over blocks 0 .. bj
+    lower_product_mfma<NT>(
+        K, [&](int r, int m) { return (r < K && m <= r) ? Bm[pk(r, m)] : 0.0; },
+        [&](int m, int c) { return (c < K && m <= c) ? Bm[pk(c, m)] : 0.0; },
+        [](int bi, int bj, int &k0, int &k1) {
+            k0 = 0;
+            k1 = 16 * bj + 16;
+        },
+        [&](int r, int c, double d) {
+            Lam_out[r * K + c] = d;
+            Lam_out[c * K + r] = d;
+            Lam_w[r * K + c] = (T)d;
+            Lam_w[c * K + r] = (T)d;
+        });
     for (int blk = tid; 4 * blk < K; blk += NT) {
         double z[4];
         normals_block(seed, (uint32_t)blk, t, stream, 2u, 0u, z);
