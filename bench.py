@@ -74,15 +74,15 @@ def side_degrees(r):
 
 
 PEAK_FP64_TFLOPS = 78.6  # MI355X dense FP64 (matrix cores), TFLOP/s
-# The FP32 Gram of the K <= 32 kernel runs on the BF16 matrix cores as six
-# products of three-part BF16 splits per FP32 product.
+# The FP32 Gram of the matrix-core kernels (K <= 128) runs on the BF16
+# matrix cores as six products of three-part BF16 splits per FP32 product.
 P3_PRODUCTS = 6
-P3_KMAX = 32
+P3_KMAX = 128
 
 
 def split_work(K, prec):
     """Whether the Gram and the factorisation are priced apart: the BF16-Gram
-    form, and FP32 at K <= 32 (Gram on the BF16 matrix cores); the divisor
+    form, and FP32 at K <= 128 (Gram on the BF16 matrix cores); the divisor
     of the BF16 rate for the Gram (products per algorithmic product)."""
     if prec == "bf16":
         return True, 1
@@ -135,7 +135,7 @@ def sweep_roofline(K, prec, r, ms_per_step, peaks, n_low=None):
     updates, with the algorithmic work of `algorithmic` for every row and
     rating.  Against the spec sheet (FP32 work at 157.3 TFLOP/s; in the
     BF16-Gram form the Gram at 2.5 PFLOP/s and the factorisation at
-    157.3, and the same split for FP32 at K <= 32 with the Gram at 2.5 / 6
+    157.3, and the same split for FP32 at K <= 128 with the Gram at 2.5 / 6
     PFLOP/s; bytes at 8 TB/s, the gather counted only when its source exceeds
     one L2) and against the measured peaks (the same split of the work;
     compulsory bytes at the triad rate plus every gathered row at the
@@ -290,7 +290,7 @@ def kernel_roofline(K, prec, r, k_ms, peaks, n_low, steps):
     timed sweeps), with its algorithmic FLOP and bytes per launch against
     the peak of its own arithmetic (FP32 matrix cores; in the BF16-Gram form
     the Gram at the BF16 peak and the factorisation at the FP32 one,
-    time-weighted; for FP32 at K <= 32 the same with the Gram at a sixth of
+    time-weighted; for FP32 at K <= 128 the same with the Gram at a sixth of
     the BF16 peak) or HBM, whichever bound is higher; also against the peaks
     measured on this GPU, and the HBM traffic of the committed counter
     summary for this workload and side (None if there is none or the

@@ -179,8 +179,8 @@ hipError_t launch_prior_to_working(bpmf_ctx *c, int side_id, hipStream_t s);
 hipError_t launch_to_bf16(bpmf_ctx *c, int side_id, hipStream_t s);
 // The centred ratings of a side as three BF16 parts (rc3).
 hipError_t launch_split_ratings(bpmf_ctx *c, int side_id, hipStream_t s);
-// FP32 contexts whose column-per-lane kernel forms its Gram from three-part
-// BF16 splits (they keep the rating planes rc3).
+// FP32 contexts whose matrix-core kernels take the rating planes rc3 for
+// the rhs of their three-part BF16 Gram.
 bool parts_gram_wanted(const bpmf_ctx *c);
 // Largest dynamic LDS a generic row kernel needs for K (bytes).
 size_t row_generic_lds_bytes(int K, int prec);

@@ -49,8 +49,6 @@ namespace bpmf {
 
 namespace {
 
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kBigWPB = 1;     // waves per workgroup (independent; one-wave groups measured best)
 constexpr int kPS = 17;        // panel row stride (floats)
@@ -169,6 +167,106 @@ __device__ __forceinline__ void gram_item_bf16(const RowItem &it, const int32_t 
                 bacc[bi] = FIRST ? s : bacc[bi] + s;
             }
         }
+    };
+    // chunk 0 even for an empty item: every row it loads is 0 (out of range)
+    chunk(0u, std::integral_constant<bool, true>{});
+    for (uint32_t ch = 1; ch < nchunk; ++ch) chunk(ch, std::integral_constant<bool, false>{});
+}
+
+// The FP32 Gram and rhs of one work item (whole wave) on the BF16 matrix
+// cores, from three-part splits of the gathered FP32 rows (split3: y = h +
+// m + l exactly; each block takes the six part products hh, hm, mh, hl, lh,
+// mm, FP32 accumulation; the three left out are below 2^-22 |y_i y_j|),
+// accumulated transposed like gram_item_bf16: block (bi, bj), bi >= bj,
+// holds the upper block (bj, bi) in the MFMA result layout.  Chunks of 32
+// ratings; lane l holds the parts of component 16 bi + l % 16 of the
+// neighbour rows of ratings 8 (l / 16) + e, e = 0..7.  With AUG the last
+// block's padding components kr, kr + 1, kr + 2 carry the centred rating's
+// three BF16 parts (exact; the planes rc3) as their high part and zero mid
+// and low parts, so that the Gram rows of those components hold the rhs
+// with every part product (aug_rhs); otherwise the rhs is summed on the
+// vector units from the FP32 rows.  Components >= K read whatever follows
+// in the row (clear_padding drops them); ratings past the end of the item
+// read 0 (buffer range check on the last chunk).
+template <int NB, bool AUG>
+__device__ __forceinline__ void gram_item_p3t(const RowItem &it, const int32_t *__restrict__ nbr,
+                                              const float *__restrict__ rc,
+                                              const uint16_t *__restrict__ rc3, uint32_t plane, int kr,
+                                              __amdgpu_buffer_rsrc_t ysrc, uint32_t ldy4, int kq, int col,
+                                              floatx4 (&acc)[NB * (NB + 1) / 2], float (&bacc)[NB])
+{
+    const uint32_t cnt = (uint32_t)(it.end - it.beg);
+    const __amdgpu_buffer_rsrc_t jsrc = make_rsrc(nbr + it.beg, cnt * 4u);
+    const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(rc + it.beg, AUG ? 0u : cnt * 4u);
+    const int p = col - kr;
+    const bool part_lane = p >= 0 && p < 3;
+    const __amdgpu_buffer_rsrc_t psrc =
+        make_rsrc(rc3 + it.beg, AUG ? (uint32_t)(3u * plane - (uint32_t)it.beg) * 2u : 0u);
+    const uint32_t poff = (AUG && part_lane) ? 2u * ((uint32_t)p * plane + 8u * kq) : kOOB;
+    const bool pad_lane = col >= kr;  // components >= K of the last block
+    const uint32_t coff = 4u * col;
+    const uint32_t nchunk = (cnt + 31) / 32;
+    auto chunk = [&](uint32_t ch, auto firstc) {
+        constexpr bool FIRST = decltype(firstc)::value;
+        uint32_t base[8];
+        float r[8];
+        const bool last = ch + 1 >= nchunk;  // only the last chunk (or chunk 0 of an empty item) runs past the end
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const uint32_t t = ch * 32 + 8 * kq + e;
+            const uint32_t j = buf_u32_stream(jsrc, t * 4u);
+            if constexpr (!AUG) r[e] = buf_f32_stream(rsrc, t * 4u);
+            base[e] = __umul24(j, ldy4) + coff;  // fewer than 2^24 rows
+            if (last) base[e] = t < cnt ? base[e] : kOOB;
+        }
+        u32x4 rp = u32x4{0u, 0u, 0u, 0u};
+        if constexpr (AUG) rp = __builtin_amdgcn_raw_buffer_load_b128(psrc, poff + ch * 64u, 0, kStreamPolicy);
+        bf16x8 H[NB], M[NB], L[NB];
+#pragma unroll
+        for (int bi = 0; bi < NB; ++bi) {
+            float yv[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) yv[e] = buf_f32(ysrc, base[e] + 64u * bi);
+            if constexpr (!AUG) {
+                float s = 0.f;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) s += r[e] * yv[e];  // c >= K: dropped with the padding
+                bacc[bi] = FIRST ? s : bacc[bi] + s;
+            }
+            u32x4 h, m, l;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                uint32_t a, b, c;
+                split3(yv[2 * q], yv[2 * q + 1], a, b, c);
+                h[q] = a;
+                m[q] = b;
+                l[q] = c;
+            }
+            if (AUG && bi == NB - 1)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    h[q] = pad_lane ? rp[q] : h[q];
+                    m[q] = pad_lane ? 0u : m[q];
+                    l[q] = pad_lane ? 0u : l[q];
+                }
+            H[bi] = __builtin_bit_cast(bf16x8, h);
+            M[bi] = __builtin_bit_cast(bf16x8, m);
+            L[bi] = __builtin_bit_cast(bf16x8, l);
+        }
+        const floatx4 zero = floatx4{0.f, 0.f, 0.f, 0.f};
+        // upper block (bj, bi): the small products first
+        int q = 0;
+#pragma unroll
+        for (int bi = 0; bi < NB; ++bi)
+#pragma unroll
+            for (int bj = 0; bj <= bi; ++bj, ++q) {
+                floatx4 a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(M[bj], M[bi], FIRST ? zero : acc[q], 0, 0, 0);
+                a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(L[bj], H[bi], a, 0, 0, 0);
+                a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(H[bj], L[bi], a, 0, 0, 0);
+                a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(M[bj], H[bi], a, 0, 0, 0);
+                a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(H[bj], M[bi], a, 0, 0, 0);
+                acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(H[bj], H[bi], a, 0, 0, 0);
+            }
     };
     // chunk 0 even for an empty item: every row it loads is 0 (out of range)
     chunk(0u, std::integral_constant<bool, true>{});
@@ -468,22 +566,13 @@ __global__ __launch_bounds__(64 * kBigWPB, big_waves<NB>()) void row_big(
     const __amdgpu_buffer_rsrc_t ysrc = make_rsrc(Y, y_bytes);
     floatx4 acc[NBLK];
     float bacc[NB];
-    if constexpr (BF16) {
+    if constexpr (BF16)
         gram_item_bf16<NB, AUG>(it, nbr, rc, rc3, plane, kr, ysrc, (uint32_t)ldy * 2u, kq, col, acc, bacc);
-    } else {
-#pragma unroll
-        for (int q = 0; q < NBLK; ++q) acc[q] = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int bi = 0; bi < NB; ++bi) bacc[bi] = 0.f;
-        uint32_t lane_off[NB];
-#pragma unroll
-        for (int bi = 0; bi < NB; ++bi) lane_off[bi] = (16 * bi + col) * 4u;
-        gram_item<NB, true, true>(it, nbr, rc, ysrc, (uint32_t)ldy * 4u, lane_off, kq, acc, bacc);
-    }
+    else  // FP32 rows: the Gram from their three-part BF16 splits
+        gram_item_p3t<NB, AUG>(it, nbr, rc, rc3, plane, kr, ysrc, (uint32_t)ldy * 4u, kq, col, acc, bacc);
     float *lds = smem_f + wave * BigLds<NB>::TOTAL;
     float *bv = lds + BigLds<NB>::BV;
     float *rdst = SEG ? part + (size_t)it.slot * big_slot_elems<NB>() + NBLK * 256 : bv;
-    static_assert(BF16 || !AUG, "the rating parts are BF16");
     if constexpr (AUG) {
         floatx4 rh[NB];
         aug_rhs<NB, 3>(acc, rh);
@@ -621,7 +710,7 @@ hipError_t launch_big(bpmf_ctx *c, Side &sd, Side &ot, hipStream_t s, int stage)
     const uint32_t y_bytes = (uint32_t)(ot.rows * c->ld * (bf ? 2 : 4));
     // the rhs from the Gram where the padding has room for the rating
     const int kr = c->K - 16 * (NB - 1);
-    const bool aug = bf && kr <= 13 && sd.rc3 != nullptr;
+    const bool aug = kr <= 13 && sd.rc3 != nullptr;
     auto go = [&](auto kern, int64_t item0, int64_t count, size_t lds_bytes) {
         if (count <= 0) return;
         const unsigned grid = (unsigned)((count + kBigWPB - 1) / kBigWPB);
@@ -641,7 +730,10 @@ hipError_t launch_big(bpmf_ctx *c, Side &sd, Side &ot, hipStream_t s, int stage)
             else
                 go(row_big<NB, true, SEG, false>, item0, count, bytes);
         } else {
-            go(row_big<NB, false, SEG, false>, item0, count, bytes);
+            if (aug)
+                go(row_big<NB, false, SEG, true>, item0, count, bytes);
+            else
+                go(row_big<NB, false, SEG, false>, item0, count, bytes);
         }
     };
     if (stage == kStageSegments)

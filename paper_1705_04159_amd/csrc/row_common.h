@@ -15,6 +15,30 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr uint32_t kOOB = 0x40000000u;  // offset beyond every buffer read here
 
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float floatx2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// Two FP32 values as three BF16 parts each, x = h + m + l exactly (round to
+// nearest even at every step: h keeps the top 8 significant bits, m the
+// next 8 of the remainder, and the remainder after that has at most 8, so
+// l holds it exactly): |m| <= 2^-8 |x| (1 + 2^-8), |l| <= 2^-15 |x|.  The
+// parts of the pair come back packed as the two halves of h, m and l.
+__device__ __forceinline__ void split3(float x0, float x1, uint32_t &h, uint32_t &m, uint32_t &l)
+{
+    const floatx2 x = floatx2{x0, x1};
+    const bf16x2 hb = __builtin_convertvector(x, bf16x2);
+    const floatx2 r = x - __builtin_convertvector(hb, floatx2);
+    const bf16x2 mb = __builtin_convertvector(r, bf16x2);
+    const floatx2 t = r - __builtin_convertvector(mb, floatx2);
+    const bf16x2 lb = __builtin_convertvector(t, bf16x2);
+    h = __builtin_bit_cast(uint32_t, hb);
+    m = __builtin_bit_cast(uint32_t, mb);
+    l = __builtin_bit_cast(uint32_t, lb);
+}
+
+
 template <int I, int N, typename F>
 __device__ __forceinline__ void static_for(F &&f)
 {

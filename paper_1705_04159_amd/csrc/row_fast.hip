@@ -46,29 +46,6 @@ hipError_t prepare_hyper(bpmf_ctx *c);
 
 namespace {
 
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
-typedef float floatx2 __attribute__((ext_vector_type(2)));
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-
-// Two FP32 values as three BF16 parts each, x = h + m + l exactly (round to
-// nearest even at every step: h keeps the top 8 significant bits, m the
-// next 8 of the remainder, and the remainder after that has at most 8, so
-// l holds it exactly): |m| <= 2^-8 |x| (1 + 2^-8), |l| <= 2^-15 |x|.  The
-// parts of the pair come back packed as the two halves of h, m and l.
-__device__ __forceinline__ void split3(float x0, float x1, uint32_t &h, uint32_t &m, uint32_t &l)
-{
-    const floatx2 x = floatx2{x0, x1};
-    const bf16x2 hb = __builtin_convertvector(x, bf16x2);
-    const floatx2 r = x - __builtin_convertvector(hb, floatx2);
-    const bf16x2 mb = __builtin_convertvector(r, bf16x2);
-    const floatx2 t = r - __builtin_convertvector(mb, floatx2);
-    const bf16x2 lb = __builtin_convertvector(t, bf16x2);
-    h = __builtin_bit_cast(uint32_t, hb);
-    m = __builtin_bit_cast(uint32_t, mb);
-    l = __builtin_bit_cast(uint32_t, lb);
-}
-
 // FP32 Gram and rhs of one work item (whole wave) on the BF16 matrix cores
 // (v_mfma_f32_16x16x32_bf16).  Each gathered FP32 entry y is split into
 // three BF16 parts y = h + m + l (split3).  Block (bi, bj) of sum y y^T
@@ -658,12 +635,13 @@ bool fast_path_available(const bpmf_ctx *c)
     return (uint64_t)c->split_threshold * 4u < kOOB;
 }
 
-// FP32 factors with K <= 32: the column-per-lane kernel's Gram on the BF16
-// matrix cores from three-part splits (needs the rating planes, read at
-// 32-bit buffer offsets).
+// FP32 factors with K <= 128: the matrix-core kernels form the Gram from
+// three-part BF16 splits and take the rhs from the rating planes (the
+// column-per-lane kernel always, the blocked one when its last block has
+// room for the parts), read at 32-bit buffer offsets.
 bool parts_gram_wanted(const bpmf_ctx *c)
 {
-    return c->prec == 1 && c->K <= 32 && 6u * ((uint64_t)c->nnz + 32u) < kOOB;
+    return c->prec == 1 && c->K <= 128 && 6u * ((uint64_t)c->nnz + 32u) < kOOB;
 }
 
 hipError_t launch_row_fast(bpmf_ctx *c, int side_id, hipStream_t s, int stage, bool *handled)

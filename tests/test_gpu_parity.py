@@ -221,21 +221,23 @@ def test_row_update_single_step(bp, orc, prec, K, side):
     assert err.max() <= TOL[prec], (err.max(), np.argmax(err))
 
 
-@pytest.mark.parametrize("K", [10, 32])
+@pytest.mark.parametrize("K,kmax", [(10, 32), (32, 32), (32, 0), (64, 32), (100, 32)])
 @pytest.mark.parametrize("side", [0, 1])
-def test_fp32_three_part_gram_accuracy(bp, orc, K, side):
-    """FP32 at K <= 32 sums the Gram from six products of exact three-part
-    BF16 splits of the FP32 rows (each term within 2^-22 of y_i y_j); its
-    error against the FP64 oracle stays at the level of the blocked
-    kernel's Gram of FP32 matrix products on the same rows and state."""
+def test_fp32_three_part_gram_accuracy(bp, orc, K, kmax, side):
+    """FP32 sums the Gram from six products of exact three-part BF16 splits
+    of the FP32 rows (each term within 2^-22 of y_i y_j, FP32's own product
+    rounding being 2^-24), in the column-per-lane kernel (K <= 32 with
+    kmax 32) and the blocked one (kmax 0, or K > 32).  Against the FP64
+    oracle on the same state the row errors stay at the level the FP32
+    products gave before (K = 10 and 32: worst 1.0e-6, median 2e-7 to
+    4.4e-7): worst within 2e-5 and median within 2e-6, well inside the 1e-4
+    single-step bound."""
     r = synth.random_small(40 + K, 700, 300, 20000, min(K, 16), empty_rows=5)
-    e3, g3, _ = single_step(bp, orc, r, K, "fp32", side, plan=(2048, 32, 0))
-    e1, g1, _ = single_step(bp, orc, r, K, "fp32", side, plan=(2048, 0, 0))
-    _say("  K=%d side=%d: three-part max %.2e median %.2e; FP32 products max %.2e median %.2e" % (
-        K, side, e3.max(), np.median(e3), e1.max(), np.median(e1)))
-    assert np.isfinite(g3).all() and np.isfinite(g1).all()
+    e3, g3, _ = single_step(bp, orc, r, K, "fp32", side, plan=(2048, kmax, 0))
+    _say("  K=%d kmax=%d side=%d: three-part max %.2e median %.2e" % (K, kmax, side, e3.max(), np.median(e3)))
+    assert np.isfinite(g3).all()
     assert e3.max() <= 2e-5
-    assert np.median(e3) <= 3 * np.median(e1) + 1e-7
+    assert np.median(e3) <= 2e-6
 
 
 @pytest.mark.parametrize("K", [10, 32, 64, 100])
