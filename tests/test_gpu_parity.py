@@ -204,7 +204,7 @@ def test_init_factor_matches_oracle(bp, orc, prec):
 @pytest.mark.parametrize("prec,K", [("fp64", 10), ("fp64", 1), ("fp64", 33), ("fp32", 10),
                                     ("fp32", 32), ("fp32", 48), ("fp32", 64), ("fp32", 100),
                                     ("fp32", 128), ("fp32", 7), ("fp32", 47), ("fp32", 1),
-                                    ("fp32", 16), ("fp32", 17), ("bf16", 1),
+                                    ("fp32", 16), ("fp32", 17), ("fp32", 33), ("fp32", 61), ("bf16", 1),
                                     ("bf16", 10), ("bf16", 32), ("bf16", 33), ("bf16", 46),
                                     ("bf16", 47), ("bf16", 61), ("bf16", 100), ("bf16", 128)])
 @pytest.mark.parametrize("side", [0, 1])
@@ -213,8 +213,11 @@ def test_row_update_single_step(bp, orc, prec, K, side):
     block count of the blocked kernel, with and without padding in the last
     block; in BF16-Gram mode K % 16 in 1..13 takes the rhs from the matrix
     cores (the rating parts in the padding), 0, 14 and 15 on the vector
-    units.  FP32 K = 1, 7, 10, 16, 17 and 32 run the three-part BF16 Gram
-    with one or two 16-component tiles, padded or full."""
+    units.  FP32 runs the three-part BF16 Gram in both kernels: K = 1, 7,
+    10, 16, 17 and 32 with one or two tiles, padded or full; above 32 the
+    same padding rule as BF16 decides whether the rating parts ride in the
+    last block (33, 61, 100) or the rhs is summed on the vector units (47,
+    48, 64, 128)."""
     r = synth.random_small(40 + K, 700, 300, 20000, min(K, 16), empty_rows=5)
     err, got, ref = single_step(bp, orc, r, K, prec, side)
     assert np.isfinite(got).all()
@@ -256,8 +259,8 @@ def test_bf16_gram_against_unrounded_oracle(bp, orc, K, side):
     assert err_u.max() <= TOL_BF16_UNROUNDED
 
 
-@pytest.mark.parametrize("prec,K", [("fp64", 10), ("fp32", 10), ("fp32", 32), ("fp32", 64), ("fp32", 100),
-                                    ("bf16", 64), ("bf16", 100), ("bf16", 47)])
+@pytest.mark.parametrize("prec,K", [("fp64", 10), ("fp32", 10), ("fp32", 32), ("fp32", 47), ("fp32", 64),
+                                    ("fp32", 100), ("bf16", 64), ("bf16", 100), ("bf16", 47)])
 def test_split_rows_single_step(bp, orc, prec, K):
     """Heavy rows split into segments (fixed-order partial reduction)."""
     r = synth.planted(seed=5, M=600, N=250, nnz=30000, K=min(K, 10), zipf=0.9)
