@@ -476,7 +476,7 @@ def foldin_bench(s, r, rate, seconds, seed, top_n=100, warm_seconds=0.0):
     }
 
 
-def timed_config(r, K, prec, steps, seed, autotune=True, with_peaks=True, warm=2):
+def timed_config(r, K, prec, steps, seed, autotune=True, with_peaks=True, warm=2, reorder=False):
     """One workload in one precision: measured peaks (optional), autotuned
     plan (outside the timed region), `warm` warm-up sweeps, then `steps`
     timed sweeps of the sweep graph (wall clock around them, device idle on
@@ -490,7 +490,7 @@ def timed_config(r, K, prec, steps, seed, autotune=True, with_peaks=True, warm=2
     ld = K if prec == "fp64" else (K + 3) // 4 * 4
     if with_peaks:
         peaks = measure_peaks(ld * esize, (r.M * ld * esize, r.N * ld * esize))
-    s = bp.Sampler(r, K, prec=prec, seed=seed)
+    s = bp.Sampler(r, K, prec=prec, seed=seed, reorder=reorder)
     plan = None
     if autotune:
         split, kmax, low, tried = s.autotune(3)
@@ -510,30 +510,43 @@ def timed_config(r, K, prec, steps, seed, autotune=True, with_peaks=True, warm=2
             "ratings_per_s": round(2 * r.nnz / ms * 1e3, 1),
             "rmse_avg": round(float(avg[-1]), 5), "rmse_last": round(float(last[-1]), 5),
             "row_kernel_ms": {"rows_V": round(kv, 3), "rows_U": round(ku, 3)},
-            "lowrank_rows": n_low, "autotune": plan,
+            "lowrank_rows": n_low, "autotune": plan, "reorder": bool(reorder),
             "roofline": kernel_roofline(K, prec, r, k_ms, peaks, n_low, steps),
             "sweep_roofline": sweep_roofline(K, prec, r, ms, peaks, n_low),
             "peaks_measured": peaks}
 
 
-def k100_compare(steps, seed, autotune=True, with_peaks=True):
+def k100_compare(steps, seed, autotune=True, with_peaks=True, reorder=False, reorder_ab=False):
     """The 100M-rating shape at K = 100: the same chain (same seed, same
     Philox draws) in FP32 and in the BF16-Gram form, `steps` timed sweeps
     each after two warm-up sweeps; reports throughput and the held-out RMSE
-    of both, and their ratio."""
+    of both, and their ratio.  reorder: both contexts hold users and movies
+    in degree order; reorder_ab: also time each precision in the other order
+    (the reordering's effect on the gather-bound sides, same GPU)."""
     t = time.perf_counter()
     r = synth.netflix_like()
     log("generated %s: M=%d N=%d nnz=%d in %.1fs" % (r.name, r.M, r.N, r.nnz, time.perf_counter() - t))
     out = {"workload": r.name, "M": r.M, "N": r.N, "nnz_train": r.nnz, "K": 100, "steps": steps}
     for prec in ("fp32", "bf16"):
-        out[prec] = timed_config(r, 100, prec, steps, seed, autotune, with_peaks)
+        out[prec] = timed_config(r, 100, prec, steps, seed, autotune, with_peaks, reorder=reorder)
         log("K=100 %s: %s" % (prec, {k: v for k, v in out[prec].items() if k != "peaks_measured"}))
+        if reorder_ab:
+            o = timed_config(r, 100, prec, steps, seed, autotune, False, reorder=not reorder)
+            a, b = (o, out[prec]) if reorder else (out[prec], o)
+            out[prec + "_order_ab"] = {
+                "reordered": o["reorder"], "ms_per_step": o["ms_per_step"],
+                "row_kernel_ms": o["row_kernel_ms"], "rmse_avg": o["rmse_avg"],
+                "reordered_over_caller_order": {
+                    "sweep": round(b["ms_per_step"] / a["ms_per_step"], 4),
+                    "rows_V": round(b["row_kernel_ms"]["rows_V"] / a["row_kernel_ms"]["rows_V"], 4),
+                    "rows_U": round(b["row_kernel_ms"]["rows_U"] / a["row_kernel_ms"]["rows_U"], 4)}}
+            log("K=100 %s order A/B: %s" % (prec, out[prec + "_order_ab"]))
     out["bf16_speedup"] = round(out["fp32"]["ms_per_step"] / out["bf16"]["ms_per_step"], 3)
     out["rmse_avg_rel_diff"] = round(out["bf16"]["rmse_avg"] / out["fp32"]["rmse_avg"] - 1.0, 6)
     return out
 
 
-def chembl_compare(steps, seed, autotune=True, with_peaks=True):
+def chembl_compare(steps, seed, autotune=True, with_peaks=True, reorder=False):
     """The compound x protein shape (483,500 x 5,775, 2,000,000 observations,
     20 columns holding 30%), K = 64, FP32: `steps` timed sweeps after the
     autotuner and two warm-up sweeps."""
@@ -542,7 +555,7 @@ def chembl_compare(steps, seed, autotune=True, with_peaks=True):
     log("generated %s: M=%d N=%d nnz=%d in %.1fs" % (r.name, r.M, r.N, r.nnz, time.perf_counter() - t))
     out = {"workload": r.name, "M": r.M, "N": r.N, "nnz_train": r.nnz, "K": 64, "precision": "fp32",
            "steps": steps}
-    out.update(timed_config(r, 64, "fp32", steps, seed, autotune, with_peaks))
+    out.update(timed_config(r, 64, "fp32", steps, seed, autotune, with_peaks, reorder=reorder))
     log("compound x protein: %s" % {k: v for k, v in out.items() if k != "peaks_measured"})
     return out
 
@@ -580,6 +593,11 @@ def main():
     ap.add_argument("--plan", default=None, metavar="SPLIT,KMAX,LOWD",
                     help="fix the plan (split threshold, fast-kernel K cut-off, rank-one degree "
                          "cut-off) instead of autotuning, e.g. to profile the plan a timed run chose")
+    ap.add_argument("--reorder", action="store_true",
+                    help="hold users and movies in descending degree order inside every context "
+                         "(the library's reorder parameter)")
+    ap.add_argument("--k100-reorder-ab", action="store_true",
+                    help="also time the K = 100 configurations in the other row order")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (torch), the "
                          "reference kernel for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE")
@@ -619,7 +637,7 @@ def main():
         peaks = measure_peaks(ld * esize, (r.M * ld * esize, r.N * ld * esize))
         log("measured peaks (%.1fs): %s" % (time.perf_counter() - t, peaks))
     t = time.perf_counter()
-    s = bp.Sampler(r, K, prec=prec, seed=args.seed)
+    s = bp.Sampler(r, K, prec=prec, seed=args.seed, reorder=args.reorder)
     log("created context in %.1fs" % (time.perf_counter() - t))
     steps, warm = args.steps, args.warmup
     tuned = None
@@ -680,7 +698,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": r.name, "M": r.M, "N": r.N, "nnz_train": r.nnz,
                    "n_test": int(len(r.test_row)), "K": K, "precision": prec,
-                   "gram": gram_arith(K, prec), "parallelism": "single-gpu"},
+                   "gram": gram_arith(K, prec), "reorder": bool(args.reorder),
+                   "parallelism": "single-gpu"},
         "ratings_per_s": round(2 * r.nnz / (ms_per_step / 1000.0), 1),
         "rmse_avg": round(float(avg[-1]), 5),
         "rmse_last": round(float(last[-1]), 5),
@@ -712,10 +731,11 @@ def main():
         log("fold-in load sweep: %s" % knee)
     s.close()
     if not args.no_k100 and args.workload == "movielens":
-        out["k100"] = k100_compare(args.k100_steps, args.seed, not args.no_autotune, not args.no_peaks)
+        out["k100"] = k100_compare(args.k100_steps, args.seed, not args.no_autotune, not args.no_peaks,
+                                   args.reorder, args.k100_reorder_ab)
     if not args.no_chembl and args.workload == "movielens":
         out["chembl"] = chembl_compare(args.chembl_steps, args.seed, not args.no_autotune,
-                                       not args.no_peaks)
+                                       not args.no_peaks, args.reorder)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(r, K, args.cpu_seconds, args.seed)
         log("cpu baseline: %s" % out["cpu_baseline"])

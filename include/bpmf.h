@@ -99,6 +99,15 @@ typedef struct bpmf_params {
                              creates its own); a caller's stream is borrowed, never destroyed,
                              and must outlive the context; it must not be the legacy null
                              stream (the sweep graph is captured on it) */
+    int32_t reorder;      /* 1: hold users and movies in descending order of their rating
+                             counts (ties by id), the reordering of R before partitioning
+                             (Sec. IV-B), so the most-gathered factor rows lie together;
+                             0 (default): keep the caller's order.  Every call still takes
+                             and returns the caller's ids; only the "row" of the noise
+                             counters, the initial factors' counters and the order of the
+                             hyper draw's sums and of fold-in ties are the internal
+                             position.  A relabelled context on R computes bit for bit
+                             what an ordinary one computes on R relabelled the same way. */
 } bpmf_params;
 
 /* Fill *p with the defaults above for latent dimension K. */
@@ -191,10 +200,11 @@ int bpmf_get_chain_state(bpmf_ctx *c, double *pred_sum, uint32_t *n_avg);
 int bpmf_set_chain_state(bpmf_ctx *c, const double *pred_sum, uint32_t n_avg);
 
 /* The CSC the library uses (N+1 offsets, nnz row ids, nnz centred values as
- * stored: float, or double in FP64 mode, r - mean).  For verification. */
+ * stored: float, or double in FP64 mode, r - mean), in the caller's ids also
+ * when params.reorder is set.  For verification. */
 int bpmf_get_csc(bpmf_ctx *c, int64_t *ptr, int32_t *row, void *rc);
 
-/* The degree plan of a side: perm[rows] = row ids in processing order
+/* The degree plan of a side: perm[rows] = (caller's) row ids in processing order
  * (degree descending, ties by row id), n_split = number of rows split
  * across wavefronts (they come first in perm), n_low = number of rows on the
  * rank-one-update path (the last ones in perm).  Any pointer may be NULL. */
@@ -277,7 +287,8 @@ int bpmf_row_kernel_ms(bpmf_ctx *c, double *ms);
  * with z_s the Philox normals of counter (lo32(id), s, 7<<24 | block, hi32(id))
  * (id = the request id), then scores p_sj = u_s . v_j^(s) + rbar for every
  * movie.  The result is the top_n unrated movies by mean_j = (1/S) sum_s p_sj
- * (descending, ties to the smaller id), with mean_j and the predictive
+ * (descending, ties to the smaller id -- the smaller internal position when
+ * params.reorder is set), with mean_j and the predictive
  * variance var_j = 1/alpha + (1/S) sum_s (p_sj - mean_j)^2. */
 
 /* Snapshot the current V and the user-side (mu_U, Lambda_U) into the next

@@ -67,6 +67,7 @@ class Params(ctypes.Structure):
         ("split_threshold", ctypes.c_int32),
         ("foldin_pool_bytes", ctypes.c_uint64),
         ("stream", ctypes.c_void_p),
+        ("reorder", ctypes.c_int32),
     ]
 
 
@@ -171,7 +172,7 @@ class Sampler:
 
     def __init__(self, ratings, K, prec="fp32", alpha=2.0, beta0=2.0, nu0=None, mu0=None,
                  W0=None, seed=0, center=True, burn_in=0, split_threshold=0, csc=None,
-                 foldin_S=16, foldin_pool_bytes=0, stream=None):
+                 foldin_S=16, foldin_pool_bytes=0, stream=None, reorder=False):
         L = lib()
         self.M, self.N, self.K = int(ratings.M), int(ratings.N), int(K)
         self.prec = PRECISIONS[prec] if isinstance(prec, str) else int(prec)
@@ -191,6 +192,7 @@ class Sampler:
         p.foldin_S = int(foldin_S)
         p.foldin_pool_bytes = int(foldin_pool_bytes)
         p.stream = None if stream is None else int(stream)  # a hipStream_t handle
+        p.reorder = 1 if reorder else 0
         ptr = _c(ratings.csr_ptr, np.int64)
         col = _c(ratings.csr_col, np.int32)
         val = _c(ratings.csr_val, np.float32)

@@ -454,6 +454,8 @@ int bpmf_foldin_submit(bpmf_ctx *c, int32_t n, const int32_t *movie, const float
         for (int32_t j = 0; j < i; ++j) seen[(size_t)movie[j] >> 6] &= ~(1ull << (movie[j] & 63));
         if (rc != BPMF_OK) return rc;
     }
+    if (c->relabel)
+        for (int32_t &m : r->movie) m = c->int_of[1][m];
     for (int32_t i = 0; i < n; ++i) {
         if (!(rating[i] == rating[i]) || rating[i] > 3.4e38f || rating[i] < -3.4e38f) return BPMF_E_FORMAT;
         r->rc[i] = (float)((double)rating[i] - c->rbar);
@@ -486,7 +488,10 @@ int bpmf_foldin_poll(bpmf_ctx *c, uint64_t req_id, int32_t *movie_out, float *me
     Request &r = *it->second;
     if (!f->dev_err.empty()) return BPMF_E_DEVICE;
     if (!r.done) return BPMF_PENDING;
-    if (movie_out) memcpy(movie_out, r.ids.data(), sizeof(int32_t) * r.ids.size());
+    if (movie_out) {
+        for (size_t k = 0; k < r.ids.size(); ++k)
+            movie_out[k] = (c->relabel && r.ids[k] >= 0) ? c->ext_of[1][r.ids[k]] : r.ids[k];
+    }
     if (mean_out) memcpy(mean_out, r.mean.data(), sizeof(float) * r.mean.size());
     if (var_out) memcpy(var_out, r.var.data(), sizeof(float) * r.var.size());
     if (latency_s) *latency_s = std::chrono::duration<double>(r.t_done - r.t_submit).count();

@@ -151,6 +151,13 @@ struct bpmf_ctx {
     int foldin_S = 16;
     uint64_t foldin_pool = 0;
     bpmf::FoldinState *foldin = nullptr;
+    // degree-order relabelling (params.reorder): users and movies are held in
+    // descending-degree order; ext_of[side][internal row] is the caller's id,
+    // int_of[side][caller id] the internal row (host), d_int_of the device
+    // copy of int_of used to map pair ids on the device
+    bool relabel = false;
+    std::vector<int32_t> ext_of[2], int_of[2];
+    int32_t *d_int_of[2] = {};
 };
 
 namespace bpmf {
@@ -165,6 +172,9 @@ hipError_t launch_hyper(bpmf_ctx *c, int side_id, hipStream_t s, uint32_t t_off 
 hipError_t launch_predict_test(bpmf_ctx *c, hipStream_t s);
 hipError_t launch_predict_pairs(bpmf_ctx *c, int64_t n, const int32_t *row, const int32_t *col,
                                 float *out, hipStream_t s);
+// Caller ids to internal rows in place (relabelled contexts): row[e] and col[e]
+// through d_int_of of the user and movie sides.
+hipError_t launch_map_pairs(bpmf_ctx *c, int64_t n, int32_t *row, int32_t *col, hipStream_t s);
 // Device address of the staging area of bpmf_predict_noalloc on c's device.
 hipError_t predict_scratch_init(bpmf_ctx *c);
 // Factor initialisation from Philox normals.

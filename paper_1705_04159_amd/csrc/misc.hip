@@ -300,6 +300,25 @@ hipError_t launch_predict_pairs(bpmf_ctx *c, int64_t n, const int32_t *row, cons
     return hipGetLastError();
 }
 
+// Caller ids to internal rows for a relabelled context, in place.  The ids
+// were range-checked on the host, so every table read is in bounds.
+__global__ void map_pairs(int64_t n, int32_t *__restrict__ row, int32_t *__restrict__ col,
+                          const int32_t *__restrict__ urow, const int32_t *__restrict__ vrow)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    row[e] = urow[row[e]];
+    col[e] = vrow[col[e]];
+}
+
+hipError_t launch_map_pairs(bpmf_ctx *c, int64_t n, int32_t *row, int32_t *col, hipStream_t s)
+{
+    if (!c->relabel || n == 0) return hipSuccess;
+    hipLaunchKernelGGL(map_pairs, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, row, col,
+                       (const int32_t *)c->d_int_of[0], (const int32_t *)c->d_int_of[1]);
+    return hipGetLastError();
+}
+
 // The device address of this GPU's staging area, looked up once per device
 // with that device current (called by bpmf_create).
 hipError_t predict_scratch_init(bpmf_ctx *c)
@@ -390,6 +409,7 @@ extern "C" int bpmf_predict_noalloc(bpmf_ctx *c, int64_t n, const int32_t *row, 
     float *d_out = (float *)(d_col + kScratchPairs);
     hipError_t e = hipMemcpyAsync(d_row, row, sizeof(int32_t) * n, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(d_col, col, sizeof(int32_t) * n, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = launch_map_pairs(c, n, d_row, d_col, c->stream);
     if (e == hipSuccess) e = launch_predict_pairs(c, n, d_row, d_col, d_out, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(out, d_out, sizeof(float) * n, hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);

@@ -324,9 +324,90 @@ void bpmf_default_params(bpmf_params *p, int32_t K)
     p->split_threshold = 0;
     p->foldin_pool_bytes = 0;
     p->stream = nullptr;
+    p->reorder = 0;
 }
 
 const char *bpmf_last_error(const bpmf_ctx *c) { return c ? c->err.c_str() : g_create_err.c_str(); }
+
+}  // extern "C"
+
+namespace {
+
+// The reordering of R before partitioning (Sec. IV-B), used here for
+// locality: users and movies are relabelled in descending order of their
+// rating counts (ties by the caller's id), so the most-gathered rows of each
+// factor sit together at the front of its array.  The relabelled matrix is
+// built from the transposition (columns visited in their new order, so each
+// new row's columns come out ascending) and handed to the ordinary create;
+// the maps between the two labellings stay with the context, and every call
+// that takes or returns user or movie ids translates them.  A relabelled
+// context on R computes exactly what an ordinary one computes on the
+// relabelled R.
+int create_relabelled(int64_t M, int64_t N, const int64_t *csr_ptr, const std::vector<int64_t> &tptr,
+                      const std::vector<int32_t> &trow, const std::vector<float> &tval, int64_t nnz,
+                      const int32_t *test_row, const int32_t *test_col, const float *test_val,
+                      int64_t n_test, const bpmf_params *p, bpmf_ctx **out)
+{
+    auto degree_order = [](int64_t rows, const int64_t *ptr, std::vector<int32_t> &ext,
+                           std::vector<int32_t> &inv) {
+        ext.resize(rows);
+        inv.resize(rows);
+        std::iota(ext.begin(), ext.end(), 0);
+        std::stable_sort(ext.begin(), ext.end(), [ptr](int32_t a, int32_t b) {
+            return ptr[a + 1] - ptr[a] > ptr[b + 1] - ptr[b];
+        });
+        for (int64_t r = 0; r < rows; ++r) inv[ext[r]] = (int32_t)r;
+    };
+    std::vector<int32_t> ext[2], inv[2];
+    degree_order(M, csr_ptr, ext[0], inv[0]);
+    degree_order(N, tptr.data(), ext[1], inv[1]);
+    std::vector<int64_t> nptr(M + 1, 0);
+    for (int64_t r = 0; r < M; ++r) nptr[r + 1] = nptr[r] + (csr_ptr[ext[0][r] + 1] - csr_ptr[ext[0][r]]);
+    std::vector<int32_t> ncol(nnz);
+    std::vector<float> nval(nnz);
+    {
+        std::vector<int64_t> fill(nptr.begin(), nptr.end() - 1);
+        for (int64_t jn = 0; jn < N; ++jn) {
+            const int32_t j = ext[1][jn];
+            for (int64_t e = tptr[j]; e < tptr[j + 1]; ++e) {
+                const int64_t q = fill[inv[0][trow[e]]]++;
+                ncol[q] = (int32_t)jn;
+                nval[q] = tval[e];
+            }
+        }
+    }
+    std::vector<int32_t> ntr(n_test), ntc(n_test);
+    for (int64_t e = 0; e < n_test; ++e) {
+        ntr[e] = inv[0][test_row[e]];
+        ntc[e] = inv[1][test_col[e]];
+    }
+    bpmf_params q = *p;
+    q.reorder = 0;
+    bpmf_ctx *c = nullptr;
+    int rc = bpmf_create(M, N, nptr.data(), ncol.data(), nval.data(), nullptr, nullptr, nullptr, nnz,
+                         ntr.data(), ntc.data(), test_val, n_test, &q, &c);
+    if (rc != BPMF_OK) return rc;
+    c->relabel = true;
+    for (int sid = 0; sid < 2; ++sid) {
+        const int64_t rows = sid == 0 ? M : N;
+        hipError_t e = dalloc(&c->d_int_of[sid], rows);
+        if (e == hipSuccess)
+            e = hipMemcpy(c->d_int_of[sid], inv[sid].data(), sizeof(int32_t) * rows, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            bpmf_destroy(c);
+            return fail(nullptr, e == hipErrorOutOfMemory ? BPMF_E_NOMEM : BPMF_E_DEVICE,
+                        "relabelling maps: %s", hipGetErrorString(e));
+        }
+        c->ext_of[sid] = std::move(ext[sid]);
+        c->int_of[sid] = std::move(inv[sid]);
+    }
+    *out = c;
+    return BPMF_OK;
+}
+
+}  // namespace
+
+extern "C" {
 
 int bpmf_create(int64_t M, int64_t N, const int64_t *csr_ptr, const int32_t *csr_col,
                 const float *csr_val, const int64_t *csc_ptr, const int32_t *csc_row,
@@ -404,6 +485,9 @@ int bpmf_create(int64_t M, int64_t N, const int64_t *csr_ptr, const int32_t *csr
     if (p->W0)
         for (size_t q = 0; q < (size_t)K * K; ++q) W0[q] = p->W0[q];
     if (!spd_inverse_host(K, W0, W0inv)) return fail(nullptr, BPMF_E_INVAL, "W0 is not SPD");
+    if (p->reorder < 0 || p->reorder > 1) return fail(nullptr, BPMF_E_INVAL, "reorder must be 0 or 1");
+    if (p->reorder) return create_relabelled(M, N, csr_ptr, tptr, trow, tval, nnz, test_row, test_col,
+                                             test_val, n_test, p, out);
 
     bpmf_ctx *c = new bpmf_ctx();
     c->M = M;
@@ -619,7 +703,8 @@ void bpmf_destroy(bpmf_ctx *c)
     void *ps[] = {c->d_mu0, c->d_W0inv, c->test_row, c->test_col, c->test_val, c->pred_sum,
                   c->rmse_part, c->rmse_hist, c->hyp_part[0], c->hyp_red[0], c->hyp_stats[0], c->hyp_scratch[0],
                   c->hyp_part[1], c->hyp_red[1], c->hyp_stats[1], c->hyp_scratch[1],
-                  c->hyp_status, c->part, c->ctr, c->q_row, c->q_col, c->q_out};
+                  c->hyp_status, c->part, c->ctr, c->q_row, c->q_col, c->q_out,
+                  c->d_int_of[0], c->d_int_of[1]};
     for (void *p : ps) (void)hipFree(p);
     for (auto &ev : c->fork_ev)
         if (ev) (void)hipEventDestroy(ev);
@@ -1109,6 +1194,7 @@ int bpmf_predict(bpmf_ctx *c, uint32_t t, int64_t n, const int32_t *row, const i
     }
     HIPCK(c, hipMemcpyAsync(c->q_row, row, sizeof(int32_t) * n, hipMemcpyHostToDevice, c->stream));
     HIPCK(c, hipMemcpyAsync(c->q_col, col, sizeof(int32_t) * n, hipMemcpyHostToDevice, c->stream));
+    HIPCK(c, launch_map_pairs(c, n, c->q_row, c->q_col, c->stream));
     HIPCK(c, launch_predict_pairs(c, n, c->q_row, c->q_col, c->q_out, c->stream));
     HIPCK(c, hipMemcpyAsync(out, c->q_out, sizeof(float) * n, hipMemcpyDeviceToHost, c->stream));
     HIPCK(c, hipStreamSynchronize(c->stream));
@@ -1121,6 +1207,21 @@ static int copy_factor(bpmf_ctx *c, int32_t side, void *host, bool to_host)
     size_t es = elem_bytes(c);
     HIPCK(c, hipStreamSynchronize(c->stream));
     if (sd.rows == 0) return BPMF_OK;
+    if (c->relabel) {
+        // internal row r is the caller's row ext_of[side][r]
+        const size_t rb = (size_t)c->K * es;
+        const std::vector<int32_t> &ext = c->ext_of[side];
+        std::vector<char> tmp((size_t)sd.rows * rb);
+        char *h = (char *)host;
+        if (to_host) {
+            HIPCK(c, hipMemcpy2D(tmp.data(), rb, sd.X, c->ld * es, rb, sd.rows, hipMemcpyDeviceToHost));
+            for (int64_t r = 0; r < sd.rows; ++r) memcpy(h + (size_t)ext[r] * rb, tmp.data() + (size_t)r * rb, rb);
+        } else {
+            for (int64_t r = 0; r < sd.rows; ++r) memcpy(tmp.data() + (size_t)r * rb, h + (size_t)ext[r] * rb, rb);
+            HIPCK(c, hipMemcpy2D(sd.X, c->ld * es, tmp.data(), rb, rb, sd.rows, hipMemcpyHostToDevice));
+        }
+        return BPMF_OK;
+    }
     if (to_host)
         HIPCK(c, hipMemcpy2D(host, c->K * es, sd.X, c->ld * es, c->K * es, sd.rows,
                              hipMemcpyDeviceToHost));
@@ -1236,6 +1337,36 @@ int bpmf_get_csc(bpmf_ctx *c, int64_t *ptr, int32_t *row, void *rc)
     STICKY(c);
     Side &sd = c->side[BPMF_SIDE_V];
     HIPCK(c, hipStreamSynchronize(c->stream));
+    if (c->relabel) {
+        // the stored CSC is that of the relabelled R: caller column j is internal
+        // column int_of[1][j], whose rows map back through ext_of[0] and are
+        // sorted again
+        const size_t es = elem_bytes(c);
+        std::vector<int64_t> iptr(c->N + 1);
+        std::vector<int32_t> irow(c->nnz);
+        std::vector<char> irc(c->nnz * es);
+        HIPCK(c, hipMemcpy(iptr.data(), sd.ptr, sizeof(int64_t) * (c->N + 1), hipMemcpyDeviceToHost));
+        if (c->nnz) {
+            HIPCK(c, hipMemcpy(irow.data(), sd.nbr, sizeof(int32_t) * c->nnz, hipMemcpyDeviceToHost));
+            HIPCK(c, hipMemcpy(irc.data(), sd.rc, es * c->nnz, hipMemcpyDeviceToHost));
+        }
+        std::vector<std::pair<int32_t, int64_t>> seg;
+        int64_t q = 0;
+        if (ptr) ptr[0] = 0;
+        for (int64_t j = 0; j < c->N; ++j) {
+            const int32_t jj = c->int_of[1][j];
+            seg.clear();
+            for (int64_t e = iptr[jj]; e < iptr[jj + 1]; ++e) seg.emplace_back(c->ext_of[0][irow[e]], e);
+            std::sort(seg.begin(), seg.end());
+            for (const auto &x : seg) {
+                if (row) row[q] = x.first;
+                if (rc) memcpy((char *)rc + q * es, irc.data() + x.second * es, es);
+                ++q;
+            }
+            if (ptr) ptr[j + 1] = q;
+        }
+        return BPMF_OK;
+    }
     if (ptr) HIPCK(c, hipMemcpy(ptr, sd.ptr, sizeof(int64_t) * (c->N + 1), hipMemcpyDeviceToHost));
     if (row && c->nnz)
         HIPCK(c, hipMemcpy(row, sd.nbr, sizeof(int32_t) * c->nnz, hipMemcpyDeviceToHost));
@@ -1249,7 +1380,10 @@ int bpmf_get_plan(bpmf_ctx *c, int32_t side, int32_t *perm, int64_t *n_split, in
     STICKY(c);
     if (int r = check_side(c, side)) return r;
     Side &sd = c->side[side];
-    if (perm) memcpy(perm, sd.perm.data(), sizeof(int32_t) * sd.rows);
+    if (perm && c->relabel)
+        for (int64_t k = 0; k < sd.rows; ++k) perm[k] = c->ext_of[side][sd.perm[k]];
+    else if (perm)
+        memcpy(perm, sd.perm.data(), sizeof(int32_t) * sd.rows);
     if (n_split) *n_split = sd.n_split;
     if (n_low) *n_low = sd.n_low;
     return BPMF_OK;

@@ -73,6 +73,48 @@ def test_default_params_and_error_paths(libpath):
     assert rc == bp.E_INVAL
 
 
+def test_params_layout_matches_header(tmp_path):
+    """The binding's Params mirrors bpmf_params field by field (offsets and
+    size from the C compiler on the header)."""
+    import subprocess
+
+    import paper_1705_04159_amd as bp
+
+    names = [n for n, _ in bp.Params._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text("#include <stddef.h>\n#include <stdio.h>\n#include \"bpmf.h\"\nint main(void){\n"
+                   + "".join('printf("%%zu\\n", offsetof(bpmf_params, %s));\n' % n for n in names)
+                   + 'printf("%zu\\n", sizeof(bpmf_params));\nreturn 0;}\n')
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True,
+                                          text=True).stdout.split()]
+    want = [getattr(bp.Params, n).offset for n in names] + [ctypes.sizeof(bp.Params)]
+    assert got == want
+
+
+def test_reorder_flag_validated(libpath):
+    """params.reorder defaults to 0 and values other than 0 and 1 are
+    rejected before any GPU work."""
+    import numpy as np
+
+    import paper_1705_04159_amd as bp
+
+    L = bp.lib()
+    p = bp.Params()
+    L.bpmf_default_params(ctypes.byref(p), 8)
+    assert p.reorder == 0
+    p.reorder = 2
+    ctx = ctypes.c_void_p()
+    ptr = np.array([0, 1, 1], np.int64)
+    col = np.array([1], np.int32)
+    val = np.array([1.0], np.float32)
+    rc = L.bpmf_create(2, 3, ptr.ctypes.data, col.ctypes.data, val.ctypes.data, None, None, None,
+                       1, None, None, None, 0, ctypes.byref(p), ctypes.byref(ctx))
+    assert rc == bp.E_INVAL
+    assert b"reorder" in L.bpmf_last_error(None)
+
+
 def test_peak_argument_checks(libpath):
     """The measurement calls reject bad sizes on the host, before any GPU work."""
     import paper_1705_04159_amd as bp
