@@ -593,9 +593,9 @@ def main():
     ap.add_argument("--plan", default=None, metavar="SPLIT,KMAX,LOWD",
                     help="fix the plan (split threshold, fast-kernel K cut-off, rank-one degree "
                          "cut-off) instead of autotuning, e.g. to profile the plan a timed run chose")
-    ap.add_argument("--reorder", action="store_true",
+    ap.add_argument("--reorder", action=argparse.BooleanOptionalAction, default=True,
                     help="hold users and movies in descending degree order inside every context "
-                         "(the library's reorder parameter)")
+                         "(the library's reorder parameter; --no-reorder keeps the generator's order)")
     ap.add_argument("--k100-reorder-ab", action="store_true",
                     help="also time the K = 100 configurations in the other row order")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",

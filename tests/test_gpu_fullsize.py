@@ -1,5 +1,6 @@
 """GPU parity at the benchmark's full problem sizes, in the launch
-configuration the benchmark times (default plan, same kernels and grids).
+configuration the benchmark times (default plan, same kernels and grids,
+users and movies held in degree order), and in the caller's order.
 
 The chain runs two graph sweeps on the GPU to reach a realistic state; then
 one eager step per side (hyper draw, row update) is compared with the FP64
@@ -7,8 +8,11 @@ oracle on sampled rows: the 100M-rating shape 10,000 random users and 2,000
 random movies plus the 100 highest-degree rows of each side, the other
 shapes 200 random rows and the 8 highest-degree rows of each side; the
 oracle takes the GPU's factors and hyperparameters as inputs (BF16-rounded
-neighbour rows in the BF16-Gram mode).  Tolerances as in the
-single-step tests: 1e-4 (FP32), 2e-2 (BF16-Gram) per row, relative.
+neighbour rows in the BF16-Gram mode).  In degree order the oracle runs on
+R relabelled by numpy the same way (its rows are the internal positions the
+noise counters use) and the library's factors are read in caller ids and
+permuted.  Tolerances as in the single-step tests: 1e-4 (FP32), 2e-2
+(BF16-Gram) per row, relative.
 """
 import functools
 import sys
@@ -17,6 +21,7 @@ import numpy as np
 import pytest
 
 import synth
+from relabel import relabel
 
 pytestmark = pytest.mark.gpu
 
@@ -30,6 +35,11 @@ DEFAULT_SAMPLE = {"U": (200, 8), "V": (200, 8)}
 @functools.lru_cache(maxsize=1)
 def _data(name):
     return GEN[name]()
+
+
+@functools.lru_cache(maxsize=1)
+def _relabelled(name):
+    return relabel(_data(name))
 
 
 @pytest.fixture(scope="module")
@@ -53,14 +63,26 @@ def _sample(ptr, rng, n_rand=200, n_top=8):
     return np.unique(np.concatenate([top, rnd]))
 
 
-@pytest.mark.parametrize("name,K,prec", [("movielens", 32, "fp32"), ("chembl", 64, "fp32"),
-                                         ("netflix", 100, "fp32"), ("netflix", 100, "bf16")])
-def test_full_size_sampled_rows(bp, orc, name, K, prec):
+@pytest.mark.parametrize("name,K,prec,reorder", [
+    ("movielens", 32, "fp32", True), ("movielens", 32, "fp32", False),
+    ("chembl", 64, "fp32", True), ("chembl", 64, "fp32", False),
+    ("netflix", 100, "fp32", True), ("netflix", 100, "fp32", False),
+    ("netflix", 100, "bf16", True), ("netflix", 100, "bf16", False)])
+def test_full_size_sampled_rows(bp, orc, name, K, prec, reorder):
     r = _data(name)
-    print("full-size %s K=%d %s: M=%d N=%d nnz=%d" % (name, K, prec, r.M, r.N, r.nnz), flush=True)
+    print("full-size %s K=%d %s reorder=%d: M=%d N=%d nnz=%d" % (name, K, prec, reorder, r.M, r.N,
+                                                                r.nnz), flush=True)
     seed, t = 11, 3
-    s = bp.Sampler(r, K, prec=prec, seed=seed)
+    s = bp.Sampler(r, K, prec=prec, seed=seed, reorder=reorder)
     s.run_sweeps(1, 2)
+    ext = {bp.SIDE_U: None, bp.SIDE_V: None}
+    if reorder:  # the oracle works in the library's internal labels
+        r, ext[bp.SIDE_U], ext[bp.SIDE_V], _, _ = _relabelled(name)
+
+    def factor(side):
+        X = s.get_factor(side).astype(np.float64)
+        return X if ext[side] is None else X[ext[side]]
+
     rbar = s.mean_rating
     csr_rc = r.csr_val.astype(np.float64) - rbar
     cptr, crow, cval = orc.transpose_csr(r.M, r.N, r.csr_ptr, r.csr_col, r.csr_val)
@@ -68,12 +90,12 @@ def test_full_size_sampled_rows(bp, orc, name, K, prec):
     rng = np.random.default_rng(K)
     rnd = (lambda Y: _bf16_round(Y)) if prec == "bf16" else (lambda Y: Y)
     for side in (bp.SIDE_V, bp.SIDE_U):
-        Y = s.get_factor(bp.SIDE_U if side == bp.SIDE_V else bp.SIDE_V).astype(np.float64)
-        X0 = s.get_factor(side).astype(np.float64)
+        Y = factor(bp.SIDE_U if side == bp.SIDE_V else bp.SIDE_V)
+        X0 = factor(side)
         s.sample_hyper(side, t)
         mu, Lam = s.get_hyper(side)
         s.update_side(side, t)
-        got = s.get_factor(side).astype(np.float64)
+        got = factor(side)
         n_rand, n_top = SAMPLE.get(name, DEFAULT_SAMPLE)["V" if side == bp.SIDE_V else "U"]
         if side == bp.SIDE_V:
             rows = _sample(cptr, rng, n_rand, n_top)

@@ -18,6 +18,7 @@ import pytest
 import scipy.sparse
 
 import synth
+from relabel import relabel
 
 pytestmark = pytest.mark.gpu
 
@@ -33,29 +34,6 @@ def bp():
 def _say(msg):
     print(msg, flush=True)
     sys.stdout.flush()
-
-
-def relabel(r):
-    """R with users and movies renumbered by descending degree (ties by id):
-    returns the relabelled Ratings and ext/int maps (ext[new] = old id,
-    inv[old] = new id) of both sides."""
-    M, N = r.M, r.N
-    du = np.diff(r.csr_ptr)
-    dv = np.bincount(r.csr_col, minlength=N)
-    ou = np.lexsort((np.arange(M), -du)).astype(np.int32)
-    ov = np.lexsort((np.arange(N), -dv)).astype(np.int32)
-    iu = np.empty(M, np.int32)
-    iu[ou] = np.arange(M, dtype=np.int32)
-    iv = np.empty(N, np.int32)
-    iv[ov] = np.arange(N, dtype=np.int32)
-    rows = iu[r.coo_rows()]
-    cols = iv[r.csr_col]
-    o = np.lexsort((cols, rows))
-    ptr = np.zeros(M + 1, np.int64)
-    ptr[1:] = np.cumsum(np.bincount(rows, minlength=M))
-    r2 = synth.Ratings(r.name + "-relabelled", M, N, ptr, cols[o].astype(np.int32),
-                       r.csr_val[o], iu[r.test_row], iv[r.test_col], r.test_val, r.K)
-    return r2, ou, ov, iu, iv
 
 
 CASES = [
