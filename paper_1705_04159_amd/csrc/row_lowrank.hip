@@ -312,10 +312,13 @@ __global__ __launch_bounds__(64 * kLowWPB) void row_lowrank(
 bool lowrank_available(const bpmf_ctx *c) { return c->prec == 1 && c->K <= 64 && fast_path_available(c); }
 
 // The rows stage of a side with low-rank rows: transform the gathered
-// factor, then the rows [n_items - n_low, n_items).  With a cut-off above 8
-// the rows with 9..16 ratings (first in the suffix: degrees descend) take a
-// 16-factor instance and the rest the 8-factor one, so that the larger
-// register footprint costs only the rows that need it.
+// factor, then the rows [n_items - n_low, n_items).  Degrees descend along
+// the suffix, so it splits into tiers by the instance whose register
+// footprint fits: rows with 9..16 ratings take the 16-factor instance, 5..8
+// the 8-factor one and at most 4 the 4-factor one (76 VGPRs at K = 64, six
+// waves per SIMD against four for the 8-factor one's 124).  A row's draw
+// does not depend on its tier: a wave runs as many factors as its largest
+// degree, and the extra ones of its other rows are exact identities.
 hipError_t launch_row_lowrank(bpmf_ctx *c, int side_id, hipStream_t s)
 {
     Side &sd = c->side[side_id];
@@ -324,6 +327,18 @@ hipError_t launch_row_lowrank(bpmf_ctx *c, int side_id, hipStream_t s)
     const int nb = (c->K + 15) / 16;
     const int64_t item0 = sd.n_items - sd.n_low;
     const int64_t item_small = sd.n_items - sd.n_low_small;
+    // the rows with at most 4 ratings: the last ones of the plan, whose whole
+    // rows are the last items in the same order
+    int64_t lo = sd.rows - sd.n_low, hi = sd.rows;
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        const int32_t r = sd.perm[mid];
+        if (sd.hptr[r + 1] - sd.hptr[r] <= 4)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    const int64_t item_tiny = sd.n_items - (sd.rows - lo);
     auto go = [&](auto cc) {
         constexpr int C = decltype(cc)::value;
         constexpr int KP = 16 * C;
@@ -346,9 +361,11 @@ hipError_t launch_row_lowrank(bpmf_ctx *c, int side_id, hipStream_t s)
         using D16 = std::integral_constant<int, 16>;
         if (c->low_dmax > 8) {
             rows(D16{}, item0, item_small);
-            rows(D8{}, item_small, sd.n_items);
+            rows(D8{}, item_small, item_tiny);
+            rows(D4{}, item_tiny, sd.n_items);
         } else if (c->low_dmax > 4) {
-            rows(D8{}, item0, sd.n_items);
+            rows(D8{}, item0, item_tiny);
+            rows(D4{}, item_tiny, sd.n_items);
         } else {
             rows(D4{}, item0, sd.n_items);
         }
