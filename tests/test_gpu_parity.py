@@ -471,14 +471,16 @@ def test_row_kernel_timing_inside_graph(bp):
     b.close()
 
 
-@pytest.mark.parametrize("K", [16, 48])
-def test_autotune_keeps_the_chain(bp, K):
+@pytest.mark.parametrize("K,reorder", [(16, False), (48, False), (16, True), (48, True)])
+def test_autotune_keeps_the_chain(bp, K, reorder):
     """The autotuner tries split thresholds (and, for FP32 K = 48, both kernel
     families), restores the chain state bit-for-bit and leaves a plan with
-    which the chain continues to the same RMSE as an untuned run."""
+    which the chain continues to the same RMSE as an untuned run; also on a
+    context that holds users and movies in degree order (as the benchmark
+    runs it), its factors read back in caller ids."""
     r = synth.planted(seed=5, M=600, N=250, nnz=30000, K=10, zipf=0.9)
-    a = bp.Sampler(r, K, prec="fp32", seed=3)
-    b = bp.Sampler(r, K, prec="fp32", seed=3)
+    a = bp.Sampler(r, K, prec="fp32", seed=3, reorder=reorder)
+    b = bp.Sampler(r, K, prec="fp32", seed=3, reorder=reorder)
     a.run_sweeps(1, 2)
     b.run_sweeps(1, 2)
     split, kmax, low, tried = a.autotune(2)

@@ -127,9 +127,24 @@ def test_reorder_equals_relabelled_input(bp, prec, K, wl, split):
 
 
 def test_reorder_rejects_bad_ids(bp):
-    """Range checks happen on the caller's ids, before any mapping."""
+    """Range checks happen on the caller's ids, before any mapping: at create
+    (a column out of range, a CSC that is not the transpose) and on every
+    call that takes ids."""
     r = synth.planted(seed=3, M=300, N=200, nnz=4000, K=8)
-    A = bp.Sampler(r, 8, prec="fp32", seed=1, reorder=True)
+    bad = synth.Ratings(**{**r.__dict__})
+    bad.csr_col = r.csr_col.copy()
+    bad.csr_col[0] = r.N
+    with pytest.raises(bp.BPMFError) as e:
+        bp.Sampler(bad, 8, reorder=True)
+    assert e.value.code == bp.E_RANGE
+    C = scipy.sparse.csr_matrix((r.csr_val, r.csr_col, r.csr_ptr), shape=(r.M, r.N)).tocsc()
+    C.sort_indices()
+    wrong = C.data.copy()
+    wrong[0] += 1
+    with pytest.raises(bp.BPMFError) as e:
+        bp.Sampler(r, 8, csc=(C.indptr, C.indices, wrong), reorder=True)
+    assert e.value.code == bp.E_FORMAT
+    A = bp.Sampler(r, 8, prec="fp32", seed=1, reorder=True, csc=(C.indptr, C.indices, C.data))
     with pytest.raises(bp.BPMFError) as e:
         A.predict(np.array([0, r.M], np.int32), np.array([0, 0], np.int32))
     assert e.value.code == bp.E_RANGE
