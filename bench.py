@@ -574,7 +574,7 @@ def main():
     ap.add_argument("--foldin-rate", type=float, default=5000.0)
     ap.add_argument("--foldin-seconds", type=float, default=10.0)
     ap.add_argument("--foldin-warmup-seconds", type=float, default=2.0)
-    ap.add_argument("--foldin-sweep", default="1000,2500,10000,20000,40000,80000,160000",
+    ap.add_argument("--foldin-sweep", default="1000,2500,10000,20000,40000,80000,160000,240000",
                     help="offered loads (req/s) of the 1-s load sweep, comma separated; empty: none")
     ap.add_argument("--no-foldin", action="store_true")
     ap.add_argument("--k100-steps", type=int, default=50,

@@ -43,7 +43,6 @@
 namespace bpmf {
 
 size_t foldin_topk_lds(int N, int top_max);
-size_t foldin_score_lds(int S, int ld);
 
 namespace {
 
@@ -358,8 +357,8 @@ int bpmf_store_sample(bpmf_ctx *c)
     if (!c) return BPMF_E_INVAL;
     if (c->sticky) return ffail(c, BPMF_E_DEVICE, "context unusable after a device error");
     if (!fast_path_available(c)) return ffail(c, BPMF_E_INVAL, "fold-in needs FP32 factors and K <= 64");
-    if (foldin_score_lds(c->foldin_S, c->ld) > 65536 || foldin_topk_lds((int)c->N, kTopMax) > 65536)
-        return ffail(c, BPMF_E_INVAL, "fold-in: foldin_S * K or N too large for one workgroup's LDS");
+    if (foldin_topk_lds((int)c->N, kTopMax) > 65536)
+        return ffail(c, BPMF_E_INVAL, "fold-in: N too large for one workgroup's LDS");
     hipError_t e;
     if (!c->foldin) {
         auto *f = new FoldinState();

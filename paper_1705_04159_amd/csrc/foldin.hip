@@ -11,68 +11,115 @@
 namespace bpmf {
 namespace {
 
-constexpr int kScoreThreads = 128;
-constexpr int kReqPerBlock = 16;
+typedef float score4 __attribute__((ext_vector_type(4)));  // one MFMA result per lane
+
+constexpr int kScoreWaves = 4;  // waves per score workgroup, one 16-movie tile each
 constexpr int kTopThreads = 1024;
 constexpr int kTopWaves = kTopThreads / 64;
 
-// Block (request group rg, movie tile m) of the score grid.  Workgroups are
+// Block (request group rg, movie block m) of the score grid.  Workgroups are
 // dealt to the eight XCDs round-robin by their linear id, so the request
-// groups of one movie tile are given ids 8 apart: they land on the same XCD
-// and read that tile of the stored V samples from its L2 once.
-__device__ __forceinline__ bool score_block(int n_tiles, int n_rg, int &rg, int &m)
+// groups of one movie block are given ids 8 apart: they land on the same XCD
+// and read that block of the stored V samples from its L2 once.
+__device__ __forceinline__ bool score_block(int n_blocks, int n_rg, int &rg, int &m)
 {
     const int L = blockIdx.x;
     const int r = L >> 3;
     rg = r % n_rg;
     m = (r / n_rg) * 8 + (L & 7);
-    return m < n_tiles;
+    return m < n_blocks;
 }
 
-// thread = one movie of the tile, kReqPerBlock requests.  Mean and second
-// central moment over samples by Welford's update.
-__global__ __launch_bounds__(kScoreThreads) void foldin_score(
-    int K, int ld, int N, int S, int n_req, const float *__restrict__ Vring, int64_t v_stride,
+// The scores of one sample are a matrix product, P_s = U_s V_s^T (requests x
+// movies, over the K components), on the FP32 matrix cores: one wave takes 16
+// requests x 16 movies, ld / 4 steps of v_mfma_f32_16x16x4_f32 per sample.
+// Lane (g, c) holds components KQ g .. KQ g + KQ - 1 (KQ = ld / 4) of request
+// c (A operand) and of movie c (B operand) and feeds component KQ g + t in
+// step t, so both operands are contiguous loads; the operands of the next
+// 2-8 samples (as registers allow) are in flight during each sample's
+// products, which hides the load latency when a batch is a single request.
+// The result D[4 g + v][c] (request 4 g + v, movie c) is folded into its
+// running mean and second central moment by Welford's update.  Each output
+// depends on its own request's row only (rows past the batch are zero), so
+// it is the same in any batch.
+template <int KQ>
+__global__ __launch_bounds__(64 * kScoreWaves) void foldin_score(
+    int N, int S, int n_req, const float *__restrict__ Vring, int64_t v_stride,
     const float *__restrict__ U, float rbar, float inv_alpha, float *__restrict__ mean,
     float *__restrict__ var)
 {
-    extern __shared__ float us[];  // [kReqPerBlock][S][ld]
-    const int n_tiles = (N + kScoreThreads - 1) / kScoreThreads;
-    const int n_rg = (n_req + kReqPerBlock - 1) / kReqPerBlock;
-    int rg, mt;
-    if (!score_block(n_tiles, n_rg, rg, mt)) return;
-    const int b0 = rg * kReqPerBlock;
-    const int nb = min(kReqPerBlock, n_req - b0);
-    const int per_req = S * ld;
-    for (int q = threadIdx.x; q < nb * per_req; q += kScoreThreads)
-        us[q] = U[(size_t)b0 * per_req + q];
-    __syncthreads();
-    const int j = mt * kScoreThreads + threadIdx.x;
-    if (j >= N) return;
-    float m[kReqPerBlock], m2[kReqPerBlock];
+    constexpr int LD = 4 * KQ;
+    const int n_tiles = (N + 15) / 16;
+    const int n_blocks = (n_tiles + kScoreWaves - 1) / kScoreWaves;
+    const int n_rg = (n_req + 15) / 16;
+    int rg, mb;
+    if (!score_block(n_blocks, n_rg, rg, mb)) return;
+    const int lane = threadIdx.x & 63;
+    const int g = lane >> 4, c = lane & 15;
+    const int tile = mb * kScoreWaves + (threadIdx.x >> 6);
+    if (tile >= n_tiles) return;  // wave-uniform
+    const int req = rg * 16 + c;     // request of this lane's A row
+    const int mov = tile * 16 + c;   // movie of this lane's B column
+    const bool ra = req < n_req, mv = mov < N;
+    const float *up = U + (size_t)(ra ? req : 0) * S * LD + KQ * g;
+    const float *vp = Vring + (size_t)(mv ? mov : 0) * LD + KQ * g;
+    // a ring of PF samples' operands in flight (slot q holds sample s0 + q)
+    constexpr int PF = KQ <= 4 ? 8 : (KQ <= 8 ? 4 : 2);
+    float a[PF][KQ], b[PF][KQ];
+    auto load = [&](int q, int s) {
+        const float *ua = up + (size_t)s * LD, *vb = vp + (size_t)s * v_stride;
+        if constexpr (KQ % 4 == 0) {  // 16-byte runs: float4 loads
 #pragma unroll
-    for (int b = 0; b < kReqPerBlock; ++b) m[b] = m2[b] = 0.f;
-    for (int s = 0; s < S; ++s) {
-        const float *v = Vring + (size_t)s * v_stride + (size_t)j * ld;
-        const float inv_n = 1.0f / (float)(s + 1);
-#pragma unroll
-        for (int b = 0; b < kReqPerBlock; ++b) {
-            if (b >= nb) break;
-            const float *u = us + b * per_req + s * ld;
-            float p = 0.f;
-            for (int k = 0; k < K; k += 4) {
-                const float4 a = *reinterpret_cast<const float4 *>(u + k);
-                const float4 w = *reinterpret_cast<const float4 *>(v + k);
-                p += a.x * w.x + a.y * w.y + a.z * w.z + a.w * w.w;  // padding is 0
+            for (int t = 0; t < KQ; t += 4) {
+                const float4 x = ra ? *reinterpret_cast<const float4 *>(ua + t) : float4{0.f, 0.f, 0.f, 0.f};
+                const float4 y = mv ? *reinterpret_cast<const float4 *>(vb + t) : float4{0.f, 0.f, 0.f, 0.f};
+                a[q][t] = x.x, a[q][t + 1] = x.y, a[q][t + 2] = x.z, a[q][t + 3] = x.w;
+                b[q][t] = y.x, b[q][t + 1] = y.y, b[q][t + 2] = y.z, b[q][t + 3] = y.w;
             }
-            const float d = p - m[b];
-            m[b] += d * inv_n;
-            m2[b] += d * (p - m[b]);
+        } else {
+#pragma unroll
+            for (int t = 0; t < KQ; ++t) {
+                a[q][t] = ra ? ua[t] : 0.f;
+                b[q][t] = mv ? vb[t] : 0.f;
+            }
+        }
+    };
+    float m[4] = {0.f, 0.f, 0.f, 0.f}, m2[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int q = 0; q < PF; ++q)
+        if (q < S) load(q, q);
+    for (int s0 = 0; s0 < S; s0 += PF) {
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            const int s = s0 + q;
+            if (s >= S) break;  // uniform
+            float ca[KQ], cb[KQ];
+#pragma unroll
+            for (int t = 0; t < KQ; ++t) {
+                ca[t] = a[q][t];
+                cb[t] = b[q][t];
+            }
+            if (s + PF < S) load(q, s + PF);
+            score4 p = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int t = 0; t < KQ; ++t) p = __builtin_amdgcn_mfma_f32_16x16x4f32(ca[t], cb[t], p, 0, 0, 0);
+            const float inv_n = 1.0f / (float)(s + 1);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const float d = p[v] - m[v];
+                m[v] += d * inv_n;
+                m2[v] += d * (p[v] - m[v]);
+            }
         }
     }
-    for (int b = 0; b < nb; ++b) {
-        mean[(size_t)(b0 + b) * N + j] = m[b] + rbar;
-        var[(size_t)(b0 + b) * N + j] = inv_alpha + m2[b] / (float)S;
+    if (!mv) return;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int r = rg * 16 + 4 * g + v;
+        if (r < n_req) {
+            mean[(size_t)r * N + mov] = m[v] + rbar;
+            var[(size_t)r * N + mov] = inv_alpha + m2[v] / (float)S;
+        }
     }
 }
 
@@ -298,12 +345,34 @@ hipError_t launch_foldin_score(const bpmf_ctx *c, int n_req, int S, const float 
 {
     if (n_req == 0) return hipSuccess;
     const int64_t v_stride = c->N * (int64_t)c->ld;
-    const int n_tiles = (int)((c->N + kScoreThreads - 1) / kScoreThreads);
-    const int n_rg = (n_req + kReqPerBlock - 1) / kReqPerBlock;
-    const unsigned grid = (unsigned)((n_tiles + 7) / 8 * 8 * n_rg);
-    const size_t lds = sizeof(float) * kReqPerBlock * S * c->ld;
-    hipLaunchKernelGGL(foldin_score, dim3(grid), dim3(kScoreThreads), lds, s, c->K, c->ld, (int)c->N, S,
-                       n_req, Vring, v_stride, U, (float)c->rbar, (float)(1.0 / c->alpha), mean, var);
+    const int n_tiles = (int)((c->N + 15) / 16);
+    const int n_blocks = (n_tiles + kScoreWaves - 1) / kScoreWaves;
+    const int n_rg = (n_req + 15) / 16;
+    const unsigned grid = (unsigned)((n_blocks + 7) / 8 * 8 * n_rg);
+    auto go = [&](auto kq) {
+        constexpr int KQ = decltype(kq)::value;
+        hipLaunchKernelGGL((foldin_score<KQ>), dim3(grid), dim3(64 * kScoreWaves), 0, s, (int)c->N, S,
+                           n_req, Vring, v_stride, U, (float)c->rbar, (float)(1.0 / c->alpha), mean, var);
+    };
+    switch (c->ld / 4) {  // fold-in runs with K <= 64
+    case 1: go(std::integral_constant<int, 1>{}); break;
+    case 2: go(std::integral_constant<int, 2>{}); break;
+    case 3: go(std::integral_constant<int, 3>{}); break;
+    case 4: go(std::integral_constant<int, 4>{}); break;
+    case 5: go(std::integral_constant<int, 5>{}); break;
+    case 6: go(std::integral_constant<int, 6>{}); break;
+    case 7: go(std::integral_constant<int, 7>{}); break;
+    case 8: go(std::integral_constant<int, 8>{}); break;
+    case 9: go(std::integral_constant<int, 9>{}); break;
+    case 10: go(std::integral_constant<int, 10>{}); break;
+    case 11: go(std::integral_constant<int, 11>{}); break;
+    case 12: go(std::integral_constant<int, 12>{}); break;
+    case 13: go(std::integral_constant<int, 13>{}); break;
+    case 14: go(std::integral_constant<int, 14>{}); break;
+    case 15: go(std::integral_constant<int, 15>{}); break;
+    case 16: go(std::integral_constant<int, 16>{}); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -313,7 +382,6 @@ size_t foldin_topk_lds(int N, int top_max)
     return sizeof(uint32_t) * (words + 256 + kTopWaves + 1) + sizeof(unsigned long long) * top_max + 16;
 }
 
-size_t foldin_score_lds(int S, int ld) { return sizeof(float) * kReqPerBlock * S * ld; }
 
 hipError_t launch_foldin_topk(const bpmf_ctx *c, int n_req, const float *mean, const float *var,
                               const int32_t *req_beg, const int32_t *nbr, const int32_t *top_n,
